@@ -1,0 +1,150 @@
+/*
+ * fvr.h - C ABI of the MI355X (gfx950) volumetric Fourier-transform surface
+ * reconstruction library.
+ *
+ * Method: Alexiadis et al., "An Integrated Platform for Live 3D Human
+ * Reconstruction and Motion Capturing", IEEE TCSVT 2017, Sec. III-B:
+ *   1. weighted Gaussian splat of the oriented points into a vector field
+ *      V(q) with density normalisation (eqs. (1)-(2));
+ *   2. forward 3D FFT of V_X, V_Y, V_Z;
+ *   3. integration filter j w / |w|^2 applied in the frequency domain;
+ *   4. inverse 3D FFT and sum of the components -> indicator A(q);
+ *   5. iso-level L = mean of A at the input sample locations;
+ *   6. marching cubes on A(q) = L -> welded triangle mesh.
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - Grid dims are (Nx, Ny, Nz).  Scalar fields are stored (Nz, Ny, Nx),
+ *     x fastest: element (qx, qy, qz) at qx + Nx (qy + Ny qz).
+ *   - The bbox (xmin, ymin, zmin, xmax, ymax, zmax) is the FFT's periodic
+ *     domain; voxel q has centre bmin + (q + 1/2) h with h = (bmax - bmin)/N.
+ *     The caller pads the bbox around the object (zero padding, Sec. III-B).
+ *   - sigma1 = half the voxel diagonal, sigma2^2 = 3/2 sigma1^2, g(x; s) =
+ *     exp(-x^2/s^2)/s, footprint = the 4 voxel centres per axis nearest the
+ *     point (4^3 voxels, text after eq. (2)).
+ *   - FFT: forward exp(-i...), unnormalised; inverse exp(+i...) / n;
+ *     w_a = 2 pi kappa_a / extent_a; the derivative factor is zero on each
+ *     axis's Nyquist plane; the filtered DC bin is zero.
+ *   - L is the unweighted mean of the trilinearly sampled A over the
+ *     accepted points, summed in double precision.
+ *   - Marching cubes: inside <=> A > L (strict); one vertex per grid edge
+ *     that crosses the level, numbered in (linear index of the edge's lower
+ *     grid point, axis) order; triangles in (cell linear index, table) order;
+ *     outward (inside -> outside) counter-clockwise winding; the table is
+ *     generated from a face-consistent rule, so the mesh is closed and
+ *     manifold whenever the surface does not reach the grid border.
+ *
+ * Memory: every array pointer is a DEVICE pointer on the context's device
+ * unless stated otherwise, row-major, float32 unless stated otherwise.
+ * Inputs are borrowed for the duration of the call; outputs are
+ * caller-allocated.  The context owns its FFT plans, twiddle tables and
+ * scratch memory; they stay resident and grow to the largest grid and point
+ * count seen.  A context is used by one host thread at a time; work is
+ * enqueued on the context's stream.
+ *
+ * Errors: every call returns an fvr_status; fvr_last_error() gives a
+ * message.  On error no output array is written, except the counts that
+ * FVR_E_CAPACITY reports.
+ */
+#ifndef FVR_H
+#define FVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FVR_OK = 0,
+    FVR_E_INVALID = -1,     /* bad argument or non-finite / negative input value */
+    FVR_E_UNSUPPORTED = -2, /* a grid dim not of the form 2^a 3^b 5^c, or > 512 */
+    FVR_E_NOMEM = -3,       /* device allocation failed */
+    FVR_E_CAPACITY = -4,    /* output arrays too small; required counts written */
+    FVR_E_DEVICE = -5       /* a HIP runtime error */
+} fvr_status;
+
+/* fvr_mesh.flags bits */
+#define FVR_FLAG_OPEN_SURFACE 1u /* a voxel on the grid's outer layer is inside:
+                                    the bbox was not padded enough */
+
+typedef struct fvr_ctx fvr_ctx;
+
+/* One capture frame: the oriented, confidence-weighted point set of
+ * Sec. III-A (points X, normals N, weights W) and the grid. */
+typedef struct {
+    const float *points;  /* M x 3, world units */
+    const float *normals; /* M x 3 (used as given; not renormalised) */
+    const float *weights; /* M, >= 0; NULL means every weight is 1 */
+    int64_t n_points;     /* M >= 0 */
+    int32_t dims[3];      /* Nx, Ny, Nz: each even, 8..512, 2^a 3^b 5^c */
+    float bbox[6];        /* xmin, ymin, zmin, xmax, ymax, zmax (max > min) */
+} fvr_frame;
+
+typedef struct {
+    float *vertices;            /* out: capacity x 3 */
+    int32_t *triangles;         /* out: capacity x 3 vertex indices */
+    int64_t vertex_capacity;    /* in */
+    int64_t triangle_capacity;  /* in */
+    int64_t n_vertices;         /* out: written count, or the required count on FVR_E_CAPACITY */
+    int64_t n_triangles;        /* out: same */
+    double level;               /* out: iso-level L */
+    int64_t n_rejected;         /* out: points outside the bbox (not an error) */
+    uint32_t flags;             /* out: FVR_FLAG_* */
+} fvr_mesh;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+fvr_status fvr_create(int device, void *hip_stream, fvr_ctx **out);
+void fvr_destroy(fvr_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+fvr_status fvr_set_stream(fvr_ctx *ctx, void *hip_stream);
+
+/* The whole path, Sec. III-B steps 1-6.  Enqueues on the context's stream
+ * and waits for completion.  Points outside the bbox are rejected and
+ * counted.  M = 0, or all points rejected, gives FVR_OK, level 0 and an
+ * empty mesh.  If the mesh does not fit, returns FVR_E_CAPACITY with the
+ * required n_vertices / n_triangles and writes nothing else. */
+fvr_status fvr_reconstruct(fvr_ctx *ctx, const fvr_frame *frame, fvr_mesh *mesh);
+
+/* Steps 1-5 only: the indicator A (Nz x Ny x Nx floats, device) and L.
+ * Same kernels as fvr_reconstruct. */
+fvr_status fvr_indicator(fvr_ctx *ctx, const fvr_frame *frame, float *field_out,
+                         double *level_out);
+
+/* Step 6 only: marching cubes of a caller field (Nz x Ny x Nx floats,
+ * device) at `level`.  cases_out (optional, device, (Nz-1)(Ny-1)(Nx-1)
+ * bytes, x fastest) receives each cell's case byte sum_k [A(corner k) > L]
+ * 2^k with corner k at offset (k&1, (k>>1)&1, (k>>2)&1).  mesh->level is set
+ * to `level`; mesh->n_rejected to 0.  Same kernels as fvr_reconstruct. */
+fvr_status fvr_extract(fvr_ctx *ctx, const float *field, const int32_t dims[3],
+                       const float bbox[6], float level, fvr_mesh *mesh,
+                       uint8_t *cases_out);
+
+/* Step 1 output for parity checks: V (3 x Nz x Ny x Nx floats, device,
+ * component-major) written by the same splat kernel the path uses. */
+fvr_status fvr_debug_splat(fvr_ctx *ctx, const fvr_frame *frame, float *v_out);
+
+/* Host-only helpers (no device work; callable without a GPU). */
+/* Check dims and bbox as fvr_reconstruct would. */
+fvr_status fvr_check_grid(const int32_t dims[3], const float bbox[6]);
+/* Copy the library's generated marching-cubes table: counts[256] triangles
+ * per case and edges[256 * 15] cube-edge ids (-1 padded), cube edge
+ * id = 4 axis + b_lo + 2 b_hi. */
+fvr_status fvr_mc_table(uint8_t counts[256], int8_t edges[256 * 15]);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch (off by default).  Index i in [0, fvr_timing_count()). */
+fvr_status fvr_timing_enable(fvr_ctx *ctx, int enable);
+fvr_status fvr_timing_reset(fvr_ctx *ctx);
+int fvr_timing_count(void);
+const char *fvr_timing_name(int i);
+fvr_status fvr_timing_get(const fvr_ctx *ctx, int i, double *total_ms, int64_t *launches);
+
+const char *fvr_status_string(fvr_status s);
+const char *fvr_last_error(const fvr_ctx *ctx); /* ctx may be NULL */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVR_H */

@@ -1,0 +1,347 @@
+"""MI355X (gfx950) volumetric Fourier-transform surface reconstruction.
+
+Python binding over the C ABI in ``include/fvr.h`` (``libfvr.so``).  The
+binding only marshals arguments: every step of the reconstruction runs in the
+library's HIP kernels.  PyTorch supplies device memory and the stream: inputs
+are CUDA (HIP) float32 tensors on the context's device and work is enqueued
+on ``torch.cuda.current_stream()``.
+
+The method is Sec. III-B of Alexiadis et al. (IEEE TCSVT 2017): weighted
+Gaussian splat of oriented points (eqs. (1)-(2)), forward 3D FFT of the three
+components, integration filter j w / |w|^2, inverse FFT and component sum,
+iso-level at the input points, marching cubes.
+
+There is no CPU fallback: if the library is missing, importing works but every
+call raises ``FvrUnavailable``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from collections import namedtuple
+
+__all__ = [
+    "FvrError", "FvrUnavailable", "Context", "Mesh", "reconstruct", "indicator",
+    "extract", "debug_splat", "mc_table", "check_grid", "library_path", "load_library",
+    "STATUS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfvr.so")
+
+STATUS = {0: "FVR_OK", -1: "FVR_E_INVALID", -2: "FVR_E_UNSUPPORTED", -3: "FVR_E_NOMEM",
+          -4: "FVR_E_CAPACITY", -5: "FVR_E_DEVICE"}
+FVR_FLAG_OPEN_SURFACE = 1
+
+
+class FvrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class FvrUnavailable(RuntimeError):
+    pass
+
+
+class _Frame(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("normals", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("n_points", ctypes.c_int64),
+                ("dims", ctypes.c_int32 * 3), ("bbox", ctypes.c_float * 6)]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("vertices", ctypes.c_void_p), ("triangles", ctypes.c_void_p),
+                ("vertex_capacity", ctypes.c_int64), ("triangle_capacity", ctypes.c_int64),
+                ("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
+                ("level", ctypes.c_double), ("n_rejected", ctypes.c_int64),
+                ("flags", ctypes.c_uint32)]
+
+
+Mesh = namedtuple("Mesh", "vertices triangles level n_rejected open_surface")
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libfvr.so (raises FvrUnavailable if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise FvrUnavailable(f"{_LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    lib.fvr_create.argtypes = [I, P, ctypes.POINTER(P)]
+    lib.fvr_destroy.argtypes = [P]
+    lib.fvr_destroy.restype = None
+    lib.fvr_set_stream.argtypes = [P, P]
+    lib.fvr_reconstruct.argtypes = [P, ctypes.POINTER(_Frame), ctypes.POINTER(_Mesh)]
+    lib.fvr_indicator.argtypes = [P, ctypes.POINTER(_Frame), P, ctypes.POINTER(ctypes.c_double)]
+    lib.fvr_extract.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                                ctypes.c_float, ctypes.POINTER(_Mesh), P]
+    lib.fvr_debug_splat.argtypes = [P, ctypes.POINTER(_Frame), P]
+    lib.fvr_check_grid.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+    lib.fvr_mc_table.argtypes = [P, P]
+    lib.fvr_timing_enable.argtypes = [P, I]
+    lib.fvr_timing_reset.argtypes = [P]
+    lib.fvr_timing_count.argtypes = []
+    lib.fvr_timing_name.argtypes = [I]
+    lib.fvr_timing_name.restype = ctypes.c_char_p
+    lib.fvr_timing_get.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.fvr_status_string.argtypes = [I]
+    lib.fvr_status_string.restype = ctypes.c_char_p
+    lib.fvr_last_error.argtypes = [P]
+    lib.fvr_last_error.restype = ctypes.c_char_p
+    for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_indicator", "fvr_extract",
+               "fvr_debug_splat", "fvr_check_grid", "fvr_mc_table", "fvr_timing_enable",
+               "fvr_timing_reset", "fvr_timing_get"):
+        getattr(lib, fn).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(lib, status, ctx=None):
+    if status != 0:
+        msg = lib.fvr_last_error(ctx)
+        raise FvrError(status, msg.decode() if msg else "")
+
+
+def check_grid(dims, bbox) -> int:
+    """Host-only validation of dims/bbox; returns the fvr_status code."""
+    lib = load_library()
+    d = (ctypes.c_int32 * 3)(*[int(x) for x in dims])
+    b = (ctypes.c_float * 6)(*[float(x) for x in bbox])
+    return int(lib.fvr_check_grid(d, b))
+
+
+def mc_table():
+    """The library's generated marching-cubes table as numpy arrays
+    (counts uint8[256], edges int8[256, 15])."""
+    import numpy as np
+    lib = load_library()
+    counts = np.zeros(256, np.uint8)
+    edges = np.zeros((256, 15), np.int8)
+    _check(lib, lib.fvr_mc_table(counts.ctypes.data, edges.ctypes.data))
+    return counts, edges
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f32(t, name, device, shape_tail):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must live on cuda:{device}")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+    return t.contiguous()
+
+
+class Context:
+    """An fvr_ctx on one device: resident FFT plans, twiddles and scratch."""
+
+    def __init__(self, device: int | None = None):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.fvr_create(self.device, None, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fvr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def _stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib, self.lib.fvr_set_stream(self.handle, ctypes.c_void_p(s)), self.handle)
+
+    def _frame(self, points, normals, weights, grid_dim, bbox):
+        points = _dev_f32(points, "points", self.device, (3,))
+        normals = _dev_f32(normals, "normals", self.device, (3,))
+        if normals.shape[0] != points.shape[0]:
+            raise ValueError("points and normals differ in length")
+        if weights is not None:
+            weights = _dev_f32(weights.reshape(-1, 1), "weights", self.device, (1,))
+            if weights.shape[0] != points.shape[0]:
+                raise ValueError("weights length differs from points")
+        f = _Frame()
+        m = points.shape[0]
+        f.points = points.data_ptr() if m else None
+        f.normals = normals.data_ptr() if m else None
+        f.weights = weights.data_ptr() if (weights is not None and m) else None
+        f.n_points = m
+        gd = (grid_dim,) * 3 if isinstance(grid_dim, int) else tuple(grid_dim)
+        f.dims[:] = [int(x) for x in gd]
+        f.bbox[:] = [float(x) for x in _flat_bbox(bbox)]
+        return f, (points, normals, weights)
+
+    def _run_mesh(self, call, dims, out, vcap, tcap):
+        torch = _torch()
+        if out is not None:
+            verts, tris = out
+        else:
+            if vcap is None:
+                nx, ny, nz = dims
+                vcap = max(4096, 6 * (nx * ny + ny * nz + nx * nz))
+            if tcap is None:
+                tcap = 2 * vcap
+            verts = torch.empty((vcap, 3), dtype=torch.float32, device=f"cuda:{self.device}")
+            tris = torch.empty((tcap, 3), dtype=torch.int32, device=f"cuda:{self.device}")
+        for attempt in range(2):
+            m = _Mesh()
+            m.vertices = verts.data_ptr()
+            m.triangles = tris.data_ptr()
+            m.vertex_capacity = verts.shape[0]
+            m.triangle_capacity = tris.shape[0]
+            st = call(m)
+            if st == -4 and attempt == 0 and out is None:
+                verts = torch.empty((max(m.n_vertices, 1), 3), dtype=torch.float32,
+                                    device=f"cuda:{self.device}")
+                tris = torch.empty((max(m.n_triangles, 1), 3), dtype=torch.int32,
+                                   device=f"cuda:{self.device}")
+                continue
+            _check(self.lib, st, self.handle)
+            break
+        return Mesh(verts[:m.n_vertices], tris[:m.n_triangles], m.level, int(m.n_rejected),
+                    bool(m.flags & FVR_FLAG_OPEN_SURFACE))
+
+    # -- API ----------------------------------------------------------------
+    def reconstruct(self, points, normals, weights=None, grid_dim=(128, 128, 128),
+                    bbox=((-1, -1, -1), (1, 1, 1)), out=None, vertex_capacity=None,
+                    triangle_capacity=None) -> Mesh:
+        """Sec. III-B end to end: returns Mesh(vertices [V,3] f32, triangles
+        [T,3] i32, level, n_rejected, open_surface).  ``out`` = (verts, tris)
+        preallocated buffers, used without retry."""
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        self._stream()
+        dims = tuple(f.dims)
+        return self._run_mesh(lambda m: self.lib.fvr_reconstruct(self.handle, ctypes.byref(f),
+                                                                 ctypes.byref(m)),
+                              dims, out, vertex_capacity, triangle_capacity)
+
+    def indicator(self, points, normals, weights=None, grid_dim=(128, 128, 128),
+                  bbox=((-1, -1, -1), (1, 1, 1))):
+        """Steps up to the iso-level: returns (A [Nz, Ny, Nx] f32 tensor, L)."""
+        torch = _torch()
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        self._stream()
+        nx, ny, nz = tuple(f.dims)
+        A = torch.empty((nz, ny, nx), dtype=torch.float32, device=f"cuda:{self.device}")
+        lvl = ctypes.c_double()
+        _check(self.lib, self.lib.fvr_indicator(self.handle, ctypes.byref(f), A.data_ptr(),
+                                                ctypes.byref(lvl)), self.handle)
+        return A, lvl.value
+
+    def extract(self, field, bbox, level, with_cases=False, out=None, vertex_capacity=None,
+                triangle_capacity=None):
+        """Marching cubes of a device field (Nz, Ny, Nx) at ``level``.
+        Returns Mesh, plus the case bytes (Nz-1, Ny-1, Nx-1) if requested."""
+        torch = _torch()
+        if field.device.type != "cuda" or field.device.index != self.device:
+            raise ValueError(f"field must live on cuda:{self.device}")
+        if field.dtype != torch.float32 or field.dim() != 3:
+            raise TypeError("field must be a 3D float32 tensor")
+        field = field.contiguous()
+        nz, ny, nx = field.shape
+        d = (ctypes.c_int32 * 3)(nx, ny, nz)
+        b = (ctypes.c_float * 6)(*[float(x) for x in _flat_bbox(bbox)])
+        cases = None
+        if with_cases:
+            cases = torch.empty((nz - 1, ny - 1, nx - 1), dtype=torch.uint8,
+                                device=f"cuda:{self.device}")
+        self._stream()
+        mesh = self._run_mesh(
+            lambda m: self.lib.fvr_extract(self.handle, field.data_ptr(), d, b, float(level),
+                                           ctypes.byref(m), cases.data_ptr() if cases is not None else None),
+            (nx, ny, nz), out, vertex_capacity, triangle_capacity)
+        return (mesh, cases) if with_cases else mesh
+
+    def debug_splat(self, points, normals, weights=None, grid_dim=(128, 128, 128),
+                    bbox=((-1, -1, -1), (1, 1, 1))):
+        """The splat kernel's V field (3, Nz, Ny, Nx) f32."""
+        torch = _torch()
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        self._stream()
+        nx, ny, nz = tuple(f.dims)
+        V = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=f"cuda:{self.device}")
+        _check(self.lib, self.lib.fvr_debug_splat(self.handle, ctypes.byref(f), V.data_ptr()),
+               self.handle)
+        return V
+
+    # -- timing -------------------------------------------------------------
+    def timing(self, enable: bool = True):
+        _check(self.lib, self.lib.fvr_timing_enable(self.handle, 1 if enable else 0), self.handle)
+
+    def timing_reset(self):
+        _check(self.lib, self.lib.fvr_timing_reset(self.handle), self.handle)
+
+    def timings(self) -> dict:
+        """{kernel name: (total ms, launches)} from HIP events."""
+        out = {}
+        for i in range(self.lib.fvr_timing_count()):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            _check(self.lib, self.lib.fvr_timing_get(self.handle, i, ctypes.byref(ms), ctypes.byref(n)))
+            out[self.lib.fvr_timing_name(i).decode()] = (ms.value, n.value)
+        return out
+
+
+def _flat_bbox(bbox):
+    b = list(bbox)
+    if len(b) == 2:
+        return [float(x) for x in b[0]] + [float(x) for x in b[1]]
+    if len(b) != 6:
+        raise ValueError("bbox must be (lo, hi) or 6 floats")
+    return [float(x) for x in b]
+
+
+_default = {}
+
+
+def _ctx(device=None) -> Context:
+    torch = _torch()
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _default:
+        _default[d] = Context(d)
+    return _default[d]
+
+
+def reconstruct(points, normals, weights=None, grid_dim=(128, 128, 128),
+                bbox=((-1, -1, -1), (1, 1, 1)), **kw) -> Mesh:
+    """Module-level convenience over a per-device default Context."""
+    return _ctx(points.device.index).reconstruct(points, normals, weights, grid_dim, bbox, **kw)
+
+
+def indicator(points, normals, weights=None, grid_dim=(128, 128, 128),
+              bbox=((-1, -1, -1), (1, 1, 1))):
+    return _ctx(points.device.index).indicator(points, normals, weights, grid_dim, bbox)
+
+
+def extract(field, bbox, level, with_cases=False, **kw):
+    return _ctx(field.device.index).extract(field, bbox, level, with_cases, **kw)
+
+
+def debug_splat(points, normals, weights=None, grid_dim=(128, 128, 128),
+                bbox=((-1, -1, -1), (1, 1, 1))):
+    return _ctx(points.device.index).debug_splat(points, normals, weights, grid_dim, bbox)

@@ -1,0 +1,543 @@
+// Host runtime and C ABI of the gfx950 FT-reconstruction library.
+//
+// A context owns, per device: a plan cache keyed by grid dims (radix
+// schedule and float32 twiddle tables rounded from double), grow-only device
+// scratch, a pinned status block, and optional per-kernel HIP-event timing.
+// fvr_reconstruct enqueues the stages of Sec. III-B on the context's stream:
+//   reset -> bin_count -> scan -> bin_scatter -> splat+fft_x -> fft_y ->
+//   fft_z+solve -> fft_y_inv -> fft_x_c2r -> level -> mc_count -> scan
+//   -> [one device->host read of the counts] -> mc_generate -> mc_triangles.
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fvr.h"
+#include "fvr_common.h"
+
+using namespace fvr;
+
+namespace {
+
+enum KernelId {
+    K_RESET, K_BIN_FILL, K_BIN_COUNT, K_BIN_SCAN, K_BIN_SCATTER, K_SPLAT_FFT_X,
+    K_FFT_Y_FWD, K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_LEVEL, K_LEVEL_F32,
+    K_MC_COUNT, K_MC_SCAN, K_MC_GENERATE, K_MC_TRIANGLES, K_COUNT
+};
+const char *kKernelNames[K_COUNT] = {
+    "reset_status", "bin_fill", "bin_count", "bin_scan", "bin_scatter", "splat_fft_x",
+    "fft_y_fwd", "fft_z_solve", "fft_y_inv", "fft_x_c2r", "level", "level_to_f32",
+    "mc_count", "mc_scan", "mc_generate", "mc_triangles"};
+
+thread_local std::string g_error;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct Plan {
+    int dims[3];
+    FftAxis ax[3];
+    float2 *tw = nullptr;
+    SplatConsts sc;
+};
+
+// Radix schedule: as many 8s as possible, then a 4 or 2, then 3s and 5s.
+bool factor(int n, std::vector<int> &rad) {
+    rad.clear();
+    int a = 0;
+    while (n % 2 == 0) { n /= 2; ++a; }
+    while (a >= 3) { rad.push_back(8); a -= 3; }
+    if (a == 2) rad.push_back(4);
+    if (a == 1) rad.push_back(2);
+    while (n % 3 == 0) { n /= 3; rad.push_back(3); }
+    while (n % 5 == 0) { n /= 5; rad.push_back(5); }
+    return n == 1 && (int)rad.size() <= kMaxStages;
+}
+
+}  // namespace
+
+struct fvr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::map<std::array<int, 3>, Plan> plans;
+    DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off,
+        lvl_sum, lvl_cnt, status, level_f32, scan_tot;
+    DevStatus *host_status = nullptr;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<int> ev_kid;
+    size_t ev_used = 0;
+    double t_ms[K_COUNT] = {0};
+    int64_t t_n[K_COUNT] = {0};
+};
+
+namespace {
+
+fvr_status fail(fvr_ctx *c, fvr_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    g_error = msg;
+    return s;
+}
+
+fvr_status hip_fail(fvr_ctx *c, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? FVR_E_NOMEM : FVR_E_DEVICE, m);
+}
+
+#define HIP_TRY(c, expr, what)                              \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail((c), e_, (what)); \
+    } while (0)
+
+hipError_t ensure(DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (bytes <= b.cap) return hipSuccess;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.cap = bytes;
+    return e;
+}
+
+template <class T> T *P(DevBuf &b) { return static_cast<T *>(b.p); }
+
+// RAII launch timer: records a HIP event before and after the launch when
+// timing is on; the pairs are read after the next synchronisation.
+struct Timed {
+    fvr_ctx *c;
+    int kid;
+    size_t idx = (size_t)-1;
+    Timed(fvr_ctx *ctx, int k) : c(ctx), kid(k) {
+        if (!c->timing) return;
+        if (c->ev_used == c->ev.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+            c->ev.push_back({a, b});
+            c->ev_kid.push_back(k);
+        }
+        idx = c->ev_used++;
+        c->ev_kid[idx] = k;
+        (void)hipEventRecord(c->ev[idx].first, c->stream);
+    }
+    ~Timed() {
+        if (idx != (size_t)-1) (void)hipEventRecord(c->ev[idx].second, c->stream);
+    }
+};
+
+void collect_timing(fvr_ctx *c) {
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[i].first, c->ev[i].second) == hipSuccess) {
+            c->t_ms[c->ev_kid[i]] += ms;
+            c->t_n[c->ev_kid[i]] += 1;
+        }
+    }
+    c->ev_used = 0;
+}
+
+fvr_status sync(fvr_ctx *c) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (c->timing) collect_timing(c);
+    return FVR_OK;
+}
+
+fvr_status check_grid(fvr_ctx *c, const int32_t dims[3], const float bbox[6]) {
+    if (!dims || !bbox) return fail(c, FVR_E_INVALID, "dims or bbox is NULL");
+    for (int a = 0; a < 3; ++a) {
+        const int n = dims[a];
+        if (n < 8 || (n & 1)) return fail(c, FVR_E_INVALID, "grid dims must be even and >= 8");
+        if (n > kMaxDim) return fail(c, FVR_E_UNSUPPORTED, "grid dim above 512");
+        std::vector<int> r;
+        if (!factor(n, r)) return fail(c, FVR_E_UNSUPPORTED, "grid dim must be 2^a 3^b 5^c");
+        if (!std::isfinite(bbox[a]) || !std::isfinite(bbox[a + 3]) || !(bbox[a + 3] > bbox[a]))
+            return fail(c, FVR_E_INVALID, "bbox must be finite with max > min");
+        const float h = (bbox[a + 3] - bbox[a]) / (float)n;
+        if (!(h > 0.f) || !std::isfinite(h)) return fail(c, FVR_E_INVALID, "bbox extent too small");
+    }
+    return FVR_OK;
+}
+
+Grid make_grid(const int32_t dims[3], const float bbox[6]) {
+    Grid g;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = dims[a];
+        g.bmin[a] = bbox[a];
+        g.bmax[a] = bbox[a + 3];
+        volatile float ext = bbox[a + 3] - bbox[a];
+        volatile float h = ext / (float)dims[a];
+        g.h[a] = h;
+        g.wstep[a] = (float)(2.0 * M_PI / ((double)bbox[a + 3] - (double)bbox[a]));
+    }
+    g.H = dims[0] / 2 + 1;
+    return g;
+}
+
+fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan **out) {
+    const std::array<int, 3> key = {dims[0], dims[1], dims[2]};
+    auto it = c->plans.find(key);
+    Plan *p;
+    if (it == c->plans.end()) {
+        Plan np;
+        std::memcpy(np.dims, dims, sizeof(np.dims));
+        std::vector<float2> tab;
+        std::vector<size_t> offs;
+        for (int a = 0; a < 3; ++a) {
+            std::vector<int> r;
+            factor(dims[a], r);
+            np.ax[a].n = dims[a];
+            np.ax[a].nstages = (int)r.size();
+            for (int s = 0; s < kMaxStages; ++s) np.ax[a].radix[s] = s < (int)r.size() ? r[s] : 1;
+            offs.push_back(tab.size());
+            for (int t = 0; t < dims[a]; ++t) {
+                const double ang = 2.0 * M_PI * (double)t / (double)dims[a];
+                tab.push_back(make_float2((float)std::cos(ang), (float)-std::sin(ang)));
+            }
+        }
+        HIP_TRY(c, hipMalloc(&np.tw, tab.size() * sizeof(float2)), "hipMalloc(twiddles)");
+        HIP_TRY(c, hipMemcpy(np.tw, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice),
+                "hipMemcpy(twiddles)");
+        for (int a = 0; a < 3; ++a) np.ax[a].tw = np.tw + offs[a];
+        // splat tile: ty x tz full x-rows with 4 float planes <= 64 KiB of LDS
+        const int nx = dims[0];
+        int R = 64;
+        while (R > 4 && R * nx > 4096) R /= 2;
+        np.sc.tz = R >= 64 ? 8 : R >= 32 ? 8 : R >= 16 ? 4 : R >= 8 ? 4 : 2;
+        np.sc.ty = R / np.sc.tz;
+        np.sc.tiles_y = (dims[1] + np.sc.ty - 1) / np.sc.ty;
+        p = &(c->plans[key] = np);
+    } else {
+        p = &it->second;
+    }
+    // geometry-dependent splat constants (bbox may change between calls)
+    double h[3], s1sq = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        h[a] = ((double)bbox[a + 3] - (double)bbox[a]) / (double)dims[a];
+        s1sq += 0.25 * h[a] * h[a];
+    }
+    const double s2sq = 1.5 * s1sq;
+    const double log2e = 1.4426950408889634;
+    for (int a = 0; a < 3; ++a) {
+        p->sc.e1[a] = (float)(-h[a] * h[a] / s1sq * log2e);
+        p->sc.e2[a] = (float)(-h[a] * h[a] / s2sq * log2e);
+    }
+    p->sc.vscale = (float)std::sqrt(1.5);
+    *out = p;
+    return FVR_OK;
+}
+
+fvr_status check_frame(fvr_ctx *c, const fvr_frame *f) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    if (!f) return fail(c, FVR_E_INVALID, "frame is NULL");
+    if (f->n_points < 0) return fail(c, FVR_E_INVALID, "n_points < 0");
+    if (f->n_points > 0x7fffffff) return fail(c, FVR_E_INVALID, "n_points above 2^31 - 1");
+    if (f->n_points > 0 && (!f->points || !f->normals))
+        return fail(c, FVR_E_INVALID, "points or normals is NULL");
+    return check_grid(c, f->dims, f->bbox);
+}
+
+// Stages 1-4 (and optionally 5): status reset, binning, splat + x FFT and,
+// unless splat_only, the remaining transform passes into `field`.
+fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g, float *field,
+                     float *v_out, bool splat_only) {
+    const int m = (int)f->n_points;
+    const int nbins = (g.n[2] + 1) * (g.n[1] + 1);
+    const size_t nspec = (size_t)g.n[2] * g.n[1] * g.H;
+    HIP_TRY(c, ensure(c->bin_count, sizeof(int32_t) * nbins), "alloc bins");
+    HIP_TRY(c, ensure(c->bin_off, sizeof(int32_t) * (nbins + 1)), "alloc bin offsets");
+    HIP_TRY(c, ensure(c->key, sizeof(int32_t) * (size_t)m), "alloc keys");
+    HIP_TRY(c, ensure(c->rank, sizeof(int32_t) * (size_t)m), "alloc ranks");
+    HIP_TRY(c, ensure(c->rec, sizeof(float4) * 2 * (size_t)m), "alloc records");
+    HIP_TRY(c, ensure(c->spec, sizeof(float2) * 3 * nspec), "alloc spectra");
+    HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
+    HIP_TRY(c, ensure(c->scan_tot, sizeof(int32_t) * 4), "alloc scan totals");
+    DevStatus *st = P<DevStatus>(c->status);
+    hipStream_t s = c->stream;
+    { Timed t(c, K_RESET); HIP_TRY(c, launch_reset_status(st, s), "reset_status"); }
+    { Timed t(c, K_BIN_FILL); HIP_TRY(c, launch_fill_i32(P<int32_t>(c->bin_count), nbins, 0, s), "bin_fill"); }
+    { Timed t(c, K_BIN_COUNT);
+      HIP_TRY(c, launch_bin_count(f->points, f->normals, f->weights, m, g, P<int32_t>(c->bin_count),
+                                  P<int32_t>(c->key), P<int32_t>(c->rank), st, s), "bin_count"); }
+    { Timed t(c, K_BIN_SCAN);
+      HIP_TRY(c, launch_scan(P<int32_t>(c->bin_count), P<int32_t>(c->bin_off), nbins, 1,
+                             P<int32_t>(c->scan_tot), s), "bin_scan"); }
+    { Timed t(c, K_BIN_SCATTER);
+      HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, P<int32_t>(c->key),
+                                    P<int32_t>(c->rank), P<int32_t>(c->bin_off), P<float4>(c->rec), s),
+              "bin_scatter"); }
+    { Timed t(c, K_SPLAT_FFT_X);
+      HIP_TRY(c, launch_splat_fft_x(P<float4>(c->rec), P<int32_t>(c->bin_off), g, p->sc, p->ax[0],
+                                    P<float2>(c->spec), v_out, s), "splat_fft_x"); }
+    if (splat_only) return FVR_OK;
+    float2 *sp = P<float2>(c->spec);
+    { Timed t(c, K_FFT_Y_FWD); HIP_TRY(c, launch_fft_y_fwd(sp, g, p->ax[1], s), "fft_y_fwd"); }
+    { Timed t(c, K_FFT_Z_SOLVE); HIP_TRY(c, launch_fft_z_solve(sp, g, p->ax[2], s), "fft_z_solve"); }
+    { Timed t(c, K_FFT_Y_INV); HIP_TRY(c, launch_fft_y_inv(sp, g, p->ax[1], s), "fft_y_inv"); }
+    { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, g, p->ax[0], s), "fft_x_c2r"); }
+    return FVR_OK;
+}
+
+fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float *field) {
+    const int m = (int)f->n_points;
+    const int nb = level_blocks(m);
+    HIP_TRY(c, ensure(c->lvl_sum, sizeof(double) * (size_t)nb), "alloc level partials");
+    HIP_TRY(c, ensure(c->lvl_cnt, sizeof(int32_t) * (size_t)nb), "alloc level counts");
+    HIP_TRY(c, ensure(c->level_f32, sizeof(float)), "alloc level");
+    { Timed t(c, K_LEVEL);
+      HIP_TRY(c, launch_level(f->points, m, field, g, P<double>(c->lvl_sum), P<int32_t>(c->lvl_cnt),
+                              P<DevStatus>(c->status), c->stream), "level"); }
+    { Timed t(c, K_LEVEL_F32);
+      HIP_TRY(c, launch_level_to_f32(P<DevStatus>(c->status), P<float>(c->level_f32), c->stream),
+              "level_to_f32"); }
+    return FVR_OK;
+}
+
+// Marching cubes on `field` at the level in c->level_f32; status block must
+// already be reset.  Fills mesh counts; writes arrays only if they fit.
+fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
+                  uint8_t *cases_out, bool check_invalid) {
+    const int nb = mc_blocks(g);
+    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
+    HIP_TRY(c, ensure(c->mc_cnt, sizeof(int32_t) * 3 * (size_t)nb), "alloc mc counts");
+    HIP_TRY(c, ensure(c->mc_off, sizeof(int32_t) * 3 * ((size_t)nb + 1)), "alloc mc offsets");
+    HIP_TRY(c, ensure(c->vidx, sizeof(int32_t) * 3 * n), "alloc vertex ids");
+    DevStatus *st = P<DevStatus>(c->status);
+    hipStream_t s = c->stream;
+    { Timed t(c, K_MC_COUNT);
+      HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_cnt), cases_out,
+                                 st, s), "mc_count"); }
+    { Timed t(c, K_MC_SCAN);
+      HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3, st->mc_total, s),
+              "mc_scan"); }
+    HIP_TRY(c, hipMemcpyAsync(c->host_status, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s),
+            "status readback");
+    fvr_status r = sync(c);
+    if (r != FVR_OK) return r;
+    const DevStatus hs = *c->host_status;
+    if (check_invalid && (hs.flags & kFlagInvalid))
+        return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
+    mesh->n_vertices = hs.mc_total[0];
+    mesh->n_triangles = hs.mc_total[1];
+    mesh->n_rejected = hs.rejected;
+    mesh->flags = (hs.flags & kFlagOpen) ? FVR_FLAG_OPEN_SURFACE : 0u;
+    if (hs.mc_total[0] > mesh->vertex_capacity || hs.mc_total[1] > mesh->triangle_capacity)
+        return fail(c, FVR_E_CAPACITY, "mesh output capacity too small");
+    if (hs.mc_total[0] > 0 && !mesh->vertices) return fail(c, FVR_E_INVALID, "vertices is NULL");
+    if (hs.mc_total[1] > 0 && !mesh->triangles) return fail(c, FVR_E_INVALID, "triangles is NULL");
+    const int ncells = hs.mc_total[2];
+    HIP_TRY(c, ensure(c->cells, sizeof(int4) * (size_t)ncells), "alloc active cells");
+    if (hs.mc_total[0] > 0) {
+        { Timed t(c, K_MC_GENERATE);
+          HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_off),
+                                        mesh->vertices, P<int32_t>(c->vidx), P<int4>(c->cells), s),
+                  "mc_generate"); }
+        { Timed t(c, K_MC_TRIANGLES);
+          HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), ncells, P<int32_t>(c->vidx), g,
+                                         mesh->triangles, s), "mc_triangles"); }
+    }
+    return sync(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+fvr_status fvr_create(int device, void *hip_stream, fvr_ctx **out) {
+    if (!out) return fail(nullptr, FVR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(nullptr, FVR_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(nullptr, FVR_E_INVALID, "device index out of range");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    fvr_ctx *c = new fvr_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    uint8_t counts[256];
+    int8_t edges[256 * kMcRow];
+    try {
+        mc_generate_table(counts, edges);
+    } catch (const std::exception &ex) {
+        delete c;
+        return fail(nullptr, FVR_E_DEVICE, std::string("mc table: ") + ex.what());
+    }
+    e = mc_upload_table(counts, edges);
+    if (e == hipSuccess) e = splat_configure();
+    if (e == hipSuccess) e = fft_configure();
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_status, sizeof(DevStatus));
+    if (e != hipSuccess) {
+        fvr_status s = hip_fail(nullptr, e, "context setup");
+        delete c;
+        return s;
+    }
+    *out = c;
+    return FVR_OK;
+}
+
+void fvr_destroy(fvr_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
+    DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
+                      &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->lvl_sum, &c->lvl_cnt,
+                      &c->status, &c->level_f32, &c->scan_tot};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (auto &pr : c->ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    if (c->host_status) (void)hipHostFree(c->host_status);
+    delete c;
+}
+
+fvr_status fvr_set_stream(fvr_ctx *c, void *hip_stream) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    c->stream = (hipStream_t)hip_stream;
+    return FVR_OK;
+}
+
+fvr_status fvr_reconstruct(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mesh) {
+    fvr_status r = check_frame(c, f);
+    if (r != FVR_OK) return r;
+    if (!mesh) return fail(c, FVR_E_INVALID, "mesh is NULL");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    Plan *p;
+    if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
+    const Grid g = make_grid(f->dims, f->bbox);
+    HIP_TRY(c, ensure(c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2]), "alloc field");
+    if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
+    if ((r = run_level(c, f, g, P<float>(c->field))) != FVR_OK) return r;
+    r = run_mc(c, g, P<float>(c->field), mesh, nullptr, true);
+    mesh->level = c->host_status->level;
+    return r;
+}
+
+fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, double *level_out) {
+    fvr_status r = check_frame(c, f);
+    if (r != FVR_OK) return r;
+    if (!field_out) return fail(c, FVR_E_INVALID, "field_out is NULL");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    Plan *p;
+    if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
+    const Grid g = make_grid(f->dims, f->bbox);
+    // the transform writes into the context's field first: on invalid input
+    // the caller's buffer stays untouched
+    HIP_TRY(c, ensure(c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2]), "alloc field");
+    if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
+    if ((r = run_level(c, f, g, P<float>(c->field))) != FVR_OK) return r;
+    HIP_TRY(c, hipMemcpyAsync(c->host_status, c->status.p, sizeof(DevStatus), hipMemcpyDeviceToHost,
+                              c->stream), "status readback");
+    if ((r = sync(c)) != FVR_OK) return r;
+    if (c->host_status->flags & kFlagInvalid)
+        return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
+    HIP_TRY(c, hipMemcpyAsync(field_out, c->field.p, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2],
+                              hipMemcpyDeviceToDevice, c->stream), "field copy");
+    if ((r = sync(c)) != FVR_OK) return r;
+    if (level_out) *level_out = c->host_status->level;
+    return FVR_OK;
+}
+
+fvr_status fvr_extract(fvr_ctx *c, const float *field, const int32_t dims[3], const float bbox[6],
+                       float level, fvr_mesh *mesh, uint8_t *cases_out) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    fvr_status r = check_grid(c, dims, bbox);
+    if (r != FVR_OK) return r;
+    if (!field || !mesh) return fail(c, FVR_E_INVALID, "field or mesh is NULL");
+    if (!std::isfinite(level)) return fail(c, FVR_E_INVALID, "level is not finite");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    const Grid g = make_grid(dims, bbox);
+    HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
+    HIP_TRY(c, ensure(c->level_f32, sizeof(float)), "alloc level");
+    { Timed t(c, K_RESET); HIP_TRY(c, launch_reset_status(P<DevStatus>(c->status), c->stream), "reset_status"); }
+    HIP_TRY(c, hipMemcpyAsync(c->level_f32.p, &level, sizeof(float), hipMemcpyHostToDevice, c->stream),
+            "level upload");
+    r = run_mc(c, g, field, mesh, cases_out, false);
+    mesh->level = level;
+    mesh->n_rejected = 0;
+    return r;
+}
+
+fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
+    fvr_status r = check_frame(c, f);
+    if (r != FVR_OK) return r;
+    if (!v_out) return fail(c, FVR_E_INVALID, "v_out is NULL");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    Plan *p;
+    if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
+    const Grid g = make_grid(f->dims, f->bbox);
+    if ((r = run_field(c, f, p, g, nullptr, v_out, true)) != FVR_OK) return r;
+    HIP_TRY(c, hipMemcpyAsync(c->host_status, c->status.p, sizeof(DevStatus), hipMemcpyDeviceToHost,
+                              c->stream), "status readback");
+    if ((r = sync(c)) != FVR_OK) return r;
+    if (c->host_status->flags & kFlagInvalid)
+        return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
+    return FVR_OK;
+}
+
+fvr_status fvr_check_grid(const int32_t dims[3], const float bbox[6]) {
+    return check_grid(nullptr, dims, bbox);
+}
+
+fvr_status fvr_mc_table(uint8_t counts[256], int8_t edges[256 * 15]) {
+    if (!counts || !edges) return fail(nullptr, FVR_E_INVALID, "NULL output");
+    try {
+        mc_generate_table(counts, edges);
+    } catch (const std::exception &ex) {
+        return fail(nullptr, FVR_E_DEVICE, std::string("mc table: ") + ex.what());
+    }
+    return FVR_OK;
+}
+
+fvr_status fvr_timing_enable(fvr_ctx *c, int enable) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    c->timing = enable != 0;
+    return FVR_OK;
+}
+
+fvr_status fvr_timing_reset(fvr_ctx *c) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    for (int i = 0; i < K_COUNT; ++i) {
+        c->t_ms[i] = 0.0;
+        c->t_n[i] = 0;
+    }
+    return FVR_OK;
+}
+
+int fvr_timing_count(void) { return K_COUNT; }
+
+const char *fvr_timing_name(int i) { return (i >= 0 && i < K_COUNT) ? kKernelNames[i] : nullptr; }
+
+fvr_status fvr_timing_get(const fvr_ctx *c, int i, double *total_ms, int64_t *launches) {
+    if (!c || i < 0 || i >= K_COUNT) return fail(nullptr, FVR_E_INVALID, "bad context or index");
+    if (total_ms) *total_ms = c->t_ms[i];
+    if (launches) *launches = c->t_n[i];
+    return FVR_OK;
+}
+
+const char *fvr_status_string(fvr_status s) {
+    switch (s) {
+        case FVR_OK: return "ok";
+        case FVR_E_INVALID: return "invalid argument";
+        case FVR_E_UNSUPPORTED: return "unsupported grid";
+        case FVR_E_NOMEM: return "out of device memory";
+        case FVR_E_CAPACITY: return "output capacity too small";
+        case FVR_E_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char *fvr_last_error(const fvr_ctx *c) { return c ? c->err.c_str() : g_error.c_str(); }
+
+}  // extern "C"

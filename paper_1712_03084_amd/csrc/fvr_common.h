@@ -1,0 +1,130 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// gfx950 FT-reconstruction library.  Not part of the public ABI (include/fvr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fvr {
+
+constexpr int kMaxDim = 512;
+constexpr int kMaxStages = 8;
+constexpr int kMcMaxTris = 5;         // triangles per marching-cubes case, at most
+constexpr int kMcRow = 3 * kMcMaxTris;
+constexpr int kMaxDynLds = 160 * 1024 - 4096;  // gfx950: 160 KiB of LDS per workgroup
+
+// One axis of the 3D FFT: length n = prod(radix[0..nstages)), radices from
+// {2, 3, 4, 5, 8}; tw[t] = exp(-2 pi i t / n) for t < n, float32 values
+// rounded from a double-precision table.
+struct FftAxis {
+    int n;
+    int nstages;
+    int radix[kMaxStages];
+    const float2 *tw;
+};
+
+// Grid geometry in float32, shared by every stage.
+struct Grid {
+    int n[3];          // Nx, Ny, Nz
+    int H;             // Nx/2 + 1: length of a half-spectrum row
+    float bmin[3];
+    float bmax[3];
+    float h[3];        // (bmax - bmin) / N, float32
+    float wstep[3];    // 2 pi / extent: angular frequency of wavenumber 1
+};
+
+// Splat-specific constants.  Gaussian weights are evaluated per axis as
+// exp2(e1[a] * d^2) with d the point-to-centre offset in voxels of axis a:
+// e1[a] = -h_a^2 / sigma1^2 * log2(e), e2[a] the same with sigma2.
+struct SplatConsts {
+    float e1[3];
+    float e2[3];
+    float vscale;      // sigma2 / sigma1: the ratio of the two 1/sigma prefactors
+    int ty, tz;        // tile rows along y and z (full x rows per tile)
+    int tiles_y;       // ceil(Ny / ty)
+};
+
+// Device-side status block, read back once per frame.
+struct DevStatus {
+    uint32_t flags;       // bit 0: invalid input value; bit 1: open surface
+    uint32_t rejected;    // points outside the bbox
+    int32_t mc_total[3];  // vertices, triangles, active cells
+    int32_t n_used;       // points that entered the level average
+    double level;
+};
+constexpr uint32_t kFlagInvalid = 1u;
+constexpr uint32_t kFlagOpen = 2u;
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (each enqueues on `s` and returns the launch error)
+// ---------------------------------------------------------------------------
+
+// Fill `n` int32 with `v`.
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// Reset the status block (flags, counts, level).
+hipError_t launch_reset_status(DevStatus *st, hipStream_t s);
+
+// Exclusive scan of `n` items of `C` interleaved int32 components (C = 1 or 3):
+// out[i*C + c] = sum_{j<i} in[j*C + c]; out[n*C + c] = total; totals[c] = total.
+hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *totals,
+                       hipStream_t s);
+
+// Splat, stage 1: validate and bin points by the (y, z) row of their
+// footprint origin.  key[i] = -1 for rejected points.
+hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
+                            const Grid &g, int32_t *bin_count, int32_t *key, int32_t *rank,
+                            DevStatus *st, hipStream_t s);
+// Splat, stage 2: scatter packed records (x, y, z, W, W*N) into bin order.
+hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
+                              const int32_t *key, const int32_t *rank, const int32_t *bin_off,
+                              float4 *rec, hipStream_t s);
+// Splat, stage 3 fused with the forward real FFT along x: each block owns
+// ty x tz full x-rows, accumulates S_x, S_y, S_z and D in LDS, forms
+// V = S/D, transforms along x and writes three half-spectrum planes
+// (the x-component already multiplied by j w_x).  v_out (optional) receives V.
+hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
+                              const SplatConsts &sc, const FftAxis &ax, float2 *spec,
+                              float *v_out, hipStream_t s);
+size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc);
+
+// Forward y transform of the three planes, combining the x and y
+// derivative terms: plane0 <- F_y(plane0) + j w_y F_y(plane1); plane2 <- F_y(plane2).
+hipError_t launch_fft_y_fwd(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
+// Forward z transform of planes 0 and 2, the spectral solve, inverse z:
+// plane0 <- F_z^-1[(F_z plane0 + j w_z F_z plane2) / |w|^2], DC -> 0.
+hipError_t launch_fft_z_solve(float2 *spec, const Grid &g, const FftAxis &az, hipStream_t s);
+// Inverse y transform of plane 0.
+hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
+// Inverse real FFT along x of plane 0, scaled by 1/n -> A (Nz, Ny, Nx).
+hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const FftAxis &ax,
+                            hipStream_t s);
+
+// Iso-level: per-block double partial sums of trilinear A at accepted points,
+// then one block reduces them in a fixed order into st->level and st->n_used.
+hipError_t launch_level(const float *pts, int m, const float *A, const Grid &g,
+                        double *partial_sum, int32_t *partial_cnt, DevStatus *st,
+                        hipStream_t s);
+int level_blocks(int m);
+
+// Marching cubes.
+hipError_t mc_upload_table(const uint8_t *counts, const int8_t *edges);
+int mc_blocks(const Grid &g);
+hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
+                           int32_t *blk_counts, uint8_t *cases_out, DevStatus *st,
+                           hipStream_t s);
+hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
+                              const int32_t *blk_offsets, float *verts, int32_t *vidx,
+                              int4 *cells, hipStream_t s);
+hipError_t launch_mc_triangles(const int4 *cells, int n_cells, const int32_t *vidx,
+                               const Grid &g, int32_t *tris, hipStream_t s);
+// level_f32 <- (float)st->level
+hipError_t launch_level_to_f32(const DevStatus *st, float *level_f32, hipStream_t s);
+
+// Raise the dynamic-LDS limit of the kernels that stage tiles above 64 KiB.
+hipError_t splat_configure();
+hipError_t fft_configure();
+
+// Host-side marching-cubes table generation (library's own generator).
+void mc_generate_table(uint8_t counts[256], int8_t edges[256 * kMcRow]);
+
+}  // namespace fvr

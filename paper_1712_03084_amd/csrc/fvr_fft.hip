@@ -1,0 +1,224 @@
+// Strided FFT passes of the spectral integration (Sec. III-B) on gfx950.
+//
+// Spectra are three half-spectrum planes of shape (Nz, Ny, H), H = Nx/2 + 1,
+// complex64, kx fastest.  The forward x transform (with the x derivative
+// factor) is fused into the splat kernel; these passes finish the transform
+// along y and z, apply the integration filter, and invert:
+//
+//   fft_y_fwd   P0 <- F_y P0 + j w_y F_y P1          (x and y derivative terms)
+//               P2 <- F_y P2
+//   fft_z_solve P0 <- F_z^-1 [ (F_z P0 + j w_z F_z P2) / |w|^2 ],  DC -> 0
+//   fft_y_inv   P0 <- F_y^-1 P0
+//   fft_x_c2r   A  <- F_x^-1 P0 / (Nx Ny Nz)          (real output)
+//
+// By linearity this equals the paper's per-component transform, filter and
+// inverse followed by the sum of the X, Y and Z components.
+//
+// y and z passes: a block owns kChunk consecutive kx columns of one plane
+// line (fixed z for y, fixed ky for z) and the whole transformed axis, staged
+// in LDS as [axis][kChunk] so each global row access is kChunk contiguous
+// complex values.
+#include "fvr_common.h"
+#include "fvr_fft_engine.h"
+
+namespace fvr {
+
+constexpr int kChunk = 16;
+constexpr int kPassThreads = 256;
+constexpr int kC2rRows = 16;  // real rows per C2R block (pairs -> 8 complex rows)
+
+__device__ __forceinline__ int nchunks(int H) { return (H + kChunk - 1) / kChunk; }
+
+__global__ void __launch_bounds__(kPassThreads)
+fft_y_fwd_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
+    extern __shared__ float2 lds[];
+    const int Ny = g.n[1], H = g.H;
+    const size_t plane = (size_t)g.n[2] * Ny * H;
+    const int nch = nchunks(H);
+    const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
+    const int k0 = chunk * kChunk;
+    float2 *A = lds, *B = lds + Ny * kChunk;
+    const int tot = Ny * kChunk;
+    const size_t zoff = (size_t)z * Ny * H;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
+        const size_t o = zoff + (size_t)y * H + kx;
+        const bool ok = kx < H;
+        A[i] = ok ? spec[o] : make_float2(0.f, 0.f);
+        B[i] = ok ? spec[plane + o] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, ay, -1);
+    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, -1);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int ky = i / kChunk, c = i % kChunk, kx = k0 + c;
+        const float w = deriv_w(ky, Ny, g.wstep[1]);
+        const float2 b = B[i];
+        const float2 r = make_float2(A[i].x - w * b.y, A[i].y + w * b.x);
+        if (kx < H) spec[zoff + (size_t)ky * H + kx] = r;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
+        B[i] = kx < H ? spec[2 * plane + zoff + (size_t)y * H + kx] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, -1);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int ky = i / kChunk, c = i % kChunk, kx = k0 + c;
+        if (kx < H) spec[2 * plane + zoff + (size_t)ky * H + kx] = B[i];
+    }
+}
+
+__global__ void __launch_bounds__(kPassThreads)
+fft_z_solve_kernel(float2 *__restrict__ spec, Grid g, FftAxis az) {
+    extern __shared__ float2 lds[];
+    const int Ny = g.n[1], Nz = g.n[2], H = g.H;
+    const size_t plane = (size_t)Nz * Ny * H;
+    const size_t zstride = (size_t)Ny * H;
+    const int nch = nchunks(H);
+    const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
+    const int k0 = chunk * kChunk;
+    float2 *A = lds, *B = lds + Nz * kChunk;
+    const int tot = Nz * kChunk;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int z = i / kChunk, c = i % kChunk, kx = k0 + c;
+        const size_t o = z * zstride + (size_t)ky * H + kx;
+        const bool ok = kx < H;
+        A[i] = ok ? spec[o] : make_float2(0.f, 0.f);
+        B[i] = ok ? spec[2 * plane + o] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, -1);
+    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, az, -1);
+    const float wxs = g.wstep[0], wys = g.wstep[1];
+    const float wy = (float)kappa(ky, Ny) * wys;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int kz = i / kChunk, c = i % kChunk, kx = k0 + c;
+        const float wx = (float)kappa(kx, g.n[0]) * wxs;
+        const float wzf = (float)kappa(kz, Nz) * g.wstep[2];
+        const float w2 = wx * wx + wy * wy + wzf * wzf;
+        const float inv = w2 > 0.f ? 1.0f / w2 : 0.0f;
+        const float wz = deriv_w(kz, Nz, g.wstep[2]);
+        const float2 b = B[i];
+        const float2 a = A[i];
+        A[i] = make_float2((a.x - wz * b.y) * inv, (a.y + wz * b.x) * inv);
+    }
+    __syncthreads();
+    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, +1);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int z = i / kChunk, c = i % kChunk, kx = k0 + c;
+        if (kx < H) spec[z * zstride + (size_t)ky * H + kx] = A[i];
+    }
+}
+
+__global__ void __launch_bounds__(kPassThreads)
+fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
+    extern __shared__ float2 lds[];
+    const int Ny = g.n[1], H = g.H;
+    const int nch = nchunks(H);
+    const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
+    const int k0 = chunk * kChunk;
+    const int tot = Ny * kChunk;
+    const size_t zoff = (size_t)z * Ny * H;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
+        lds[i] = kx < H ? spec[zoff + (size_t)y * H + kx] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_rows<true>(RowsC{lds, 1, kChunk}, kChunk, ay, +1);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
+        if (kx < H) spec[zoff + (size_t)y * H + kx] = lds[i];
+    }
+}
+
+// Inverse real transform along x.  Two real rows a, b (consecutive linear
+// rows) are recovered together from one complex transform of
+// Z[k] = X_a[k] + i X_b[k], with X[k] for k > Nx/2 taken as conj(X[Nx-k])
+// (Hermitian symmetry of a real row's spectrum); the imaginary parts of the
+// k = 0 and k = Nx/2 bins are dropped, as a real row's spectrum has none.
+__global__ void __launch_bounds__(kPassThreads)
+fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g, FftAxis ax,
+                 float scale) {
+    extern __shared__ float2 lds[];
+    const int Nx = g.n[0], H = g.H;
+    const int nrows = g.n[1] * g.n[2];
+    const int row0 = blockIdx.x * kC2rRows;
+    const int ncx = kC2rRows / 2;
+    const int tot = ncx * Nx;
+    const unsigned mN = div_magic(Nx);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int jr = udiv(i, Nx, mN), k = i - jr * Nx;
+        const int ra = row0 + 2 * jr;
+        float2 xa = make_float2(0.f, 0.f), xb = xa;
+        if (ra < nrows) {
+            const bool mirror = k > Nx / 2;
+            const int kk = mirror ? Nx - k : k;
+            xa = spec[(size_t)ra * H + kk];
+            xb = spec[(size_t)(ra + 1) * H + kk];
+            if (mirror) {
+                xa.y = -xa.y;
+                xb.y = -xb.y;
+            }
+            if (k == 0 || 2 * k == Nx) {
+                xa.y = 0.f;
+                xb.y = 0.f;
+            }
+        }
+        lds[i] = make_float2(xa.x - xb.y, xa.y + xb.x);
+    }
+    __syncthreads();
+    fft_rows<false>(RowsC{lds, Nx, 1}, ncx, ax, +1);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int jr = udiv(i, Nx, mN), k = i - jr * Nx;
+        const int ra = row0 + 2 * jr;
+        if (ra < nrows) {
+            const float2 z = lds[i];
+            A[(size_t)ra * Nx + k] = z.x * scale;
+            A[(size_t)(ra + 1) * Nx + k] = z.y * scale;
+        }
+    }
+}
+
+hipError_t fft_configure() {
+    const void *k[] = {(const void *)fft_y_fwd_kernel, (const void *)fft_z_solve_kernel,
+                       (const void *)fft_y_inv_kernel, (const void *)fft_x_c2r_kernel};
+    for (const void *f : k) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static size_t pass_lds(int n, int bufs) { return (size_t)bufs * n * kChunk * sizeof(float2); }
+
+hipError_t launch_fft_y_fwd(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s) {
+    const int nch = (g.H + kChunk - 1) / kChunk;
+    fft_y_fwd_kernel<<<dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 2), s>>>(spec, g, ay);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_z_solve(float2 *spec, const Grid &g, const FftAxis &az, hipStream_t s) {
+    const int nch = (g.H + kChunk - 1) / kChunk;
+    fft_z_solve_kernel<<<dim3(nch * g.n[1]), dim3(kPassThreads), pass_lds(g.n[2], 2), s>>>(spec, g, az);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s) {
+    const int nch = (g.H + kChunk - 1) / kChunk;
+    fft_y_inv_kernel<<<dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 1), s>>>(spec, g, ay);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const FftAxis &ax,
+                            hipStream_t s) {
+    const int nrows = g.n[1] * g.n[2];
+    const int blocks = (nrows + kC2rRows - 1) / kC2rRows;
+    const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
+    const size_t lds = (size_t)(kC2rRows / 2) * g.n[0] * sizeof(float2);
+    fft_x_c2r_kernel<<<dim3(blocks), dim3(kPassThreads), lds, s>>>(spec, A, g, ax, scale);
+    return hipGetLastError();
+}
+
+}  // namespace fvr

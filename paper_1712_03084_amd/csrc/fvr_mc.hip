@@ -1,0 +1,507 @@
+// Iso-level, marching cubes with prefix-sum compaction, and the small
+// utility kernels (fill, status reset, scan) for gfx950.
+//
+// Iso-level (Sec. III-B): L = mean of A at the input sample locations,
+// sampled trilinearly between voxel centres; per-thread compensated double
+// sums, a fixed reduction tree per block and one block that reduces the block
+// partials in a fixed order, so L is deterministic.  This is the only double
+// precision arithmetic on the GPU.
+//
+// Marching cubes (end of Sec. III-B) without a dense per-cell output:
+//   mc_count    each thread owns 4 consecutive grid points q (linear order):
+//               the 3 grid edges leaving q that cross the level (vertices),
+//               the case of the cell with lower corner q, its triangle count
+//               and whether it is active; block totals -> blk_counts
+//   scan        exclusive scan of the block totals
+//   mc_generate recompute, block-scan, write each vertex at its global rank
+//               (vertex order = (linear index, axis)), record the vertex id of
+//               every crossing edge, and compact the active cells
+//               (linear index, case, first triangle)
+//   mc_triangles one thread per active cell emits its table triangles
+#include "fvr_common.h"
+
+namespace fvr {
+
+__constant__ uint8_t c_mc_count[256];
+__constant__ int8_t c_mc_edges[256 * kMcRow];
+
+constexpr int kMcThreads = 256;
+constexpr int kMcPpt = 4;                       // grid points per thread
+constexpr int kMcPerBlock = kMcThreads * kMcPpt;
+constexpr int kLevelThreads = 256;
+constexpr int kLevelPpt = 4;
+constexpr int kScanThreads = 1024;
+
+// ---------------------------------------------------------------------------
+// Utilities
+// ---------------------------------------------------------------------------
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void reset_status_kernel(DevStatus *st) {
+    if (threadIdx.x == 0) {
+        st->flags = 0;
+        st->rejected = 0;
+        st->mc_total[0] = st->mc_total[1] = st->mc_total[2] = 0;
+        st->n_used = 0;
+        st->level = 0.0;
+    }
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    fill_i32_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_status(DevStatus *st, hipStream_t s) {
+    reset_status_kernel<<<1, 64, 0, s>>>(st);
+    return hipGetLastError();
+}
+
+// Inclusive scan of one int across a 64-lane wave.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Single-block exclusive scan of n items of C interleaved components.
+template <int C>
+__global__ void __launch_bounds__(kScanThreads)
+scan_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int n, int32_t *totals) {
+    __shared__ int wsum[C][kScanThreads / 64];
+    __shared__ int carry[C];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (threadIdx.x < C) carry[threadIdx.x] = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        int v[C], incl[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            v[c] = i < n ? in[(size_t)i * C + c] : 0;
+            incl[c] = wave_incl_scan(v[c]);
+            if (lane == 63) wsum[c][wid] = incl[c];
+        }
+        __syncthreads();
+        if (wid == 0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int t = lane < nw ? wsum[c][lane] : 0;
+                const int ti = wave_incl_scan(t);
+                if (lane < nw) wsum[c][lane] = ti - t;  // exclusive wave offsets
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (i < n) out[(size_t)i * C + c] = carry[c] + wsum[c][wid] + incl[c] - v[c];
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) carry[c] += wsum[c][wid] + incl[c];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < C) {
+        out[(size_t)n * C + threadIdx.x] = carry[threadIdx.x];
+        if (totals) totals[threadIdx.x] = carry[threadIdx.x];
+    }
+}
+
+hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *totals,
+                       hipStream_t s) {
+    if (C == 1)
+        scan_kernel<1><<<1, kScanThreads, 0, s>>>(in, out, n, totals);
+    else
+        scan_kernel<3><<<1, kScanThreads, 0, s>>>(in, out, n, totals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Iso-level
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sample_trilinear(const float *__restrict__ A, const Grid &g,
+                                                  float x, float y, float z) {
+    const float X[3] = {x, y, z};
+    int b[3];
+    float t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = __fsub_rn(__fdiv_rn(__fsub_rn(X[a], g.bmin[a]), g.h[a]), 0.5f);
+        int bb = (int)floorf(u);
+        bb = min(max(bb, 0), g.n[a] - 2);
+        b[a] = bb;
+        t[a] = fminf(fmaxf(u - (float)bb, 0.0f), 1.0f);
+    }
+    const size_t sx = 1, sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
+    const size_t o = b[0] + sy * b[1] + sz * b[2];
+    const float c00 = A[o] + t[0] * (A[o + sx] - A[o]);
+    const float c10 = A[o + sy] + t[0] * (A[o + sy + sx] - A[o + sy]);
+    const float c01 = A[o + sz] + t[0] * (A[o + sz + sx] - A[o + sz]);
+    const float c11 = A[o + sz + sy] + t[0] * (A[o + sz + sy + sx] - A[o + sz + sy]);
+    const float c0 = c00 + t[1] * (c10 - c00);
+    const float c1 = c01 + t[1] * (c11 - c01);
+    return c0 + t[2] * (c1 - c0);
+}
+
+__global__ void __launch_bounds__(kLevelThreads)
+level_partial_kernel(const float *__restrict__ pts, int m, const float *__restrict__ A, Grid g,
+                     double *__restrict__ psum, int32_t *__restrict__ pcnt) {
+    __shared__ double ssum[kLevelThreads];
+    __shared__ int scnt[kLevelThreads];
+    double sum = 0.0, comp = 0.0;
+    int cnt = 0;
+    const int base = blockIdx.x * kLevelThreads * kLevelPpt;
+    for (int j = 0; j < kLevelPpt; ++j) {
+        const int i = base + j * kLevelThreads + threadIdx.x;
+        if (i >= m) break;
+        const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+        const bool acc = x >= g.bmin[0] && x <= g.bmax[0] && y >= g.bmin[1] && y <= g.bmax[1] &&
+                         z >= g.bmin[2] && z <= g.bmax[2];
+        if (!acc) continue;  // NaN coordinates fail the comparisons too
+        const double v = (double)sample_trilinear(A, g, x, y, z);
+        const double s = sum + v;
+        comp += fabs(sum) >= fabs(v) ? (sum - s) + v : (v - s) + sum;
+        sum = s;
+        ++cnt;
+    }
+    ssum[threadIdx.x] = sum + comp;
+    scnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = kLevelThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+            scnt[threadIdx.x] += scnt[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        psum[blockIdx.x] = ssum[0];
+        pcnt[blockIdx.x] = scnt[0];
+    }
+}
+
+__global__ void __launch_bounds__(kLevelThreads)
+level_final_kernel(const double *__restrict__ psum, const int32_t *__restrict__ pcnt, int nb,
+                   DevStatus *st) {
+    __shared__ double ssum[kLevelThreads];
+    __shared__ int scnt[kLevelThreads];
+    double sum = 0.0, comp = 0.0;
+    int cnt = 0;
+    for (int i = threadIdx.x; i < nb; i += kLevelThreads) {
+        const double v = psum[i];
+        const double s = sum + v;
+        comp += fabs(sum) >= fabs(v) ? (sum - s) + v : (v - s) + sum;
+        sum = s;
+        cnt += pcnt[i];
+    }
+    ssum[threadIdx.x] = sum + comp;
+    scnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = kLevelThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+            scnt[threadIdx.x] += scnt[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->n_used = scnt[0];
+        st->level = scnt[0] > 0 ? ssum[0] / (double)scnt[0] : 0.0;
+    }
+}
+
+int level_blocks(int m) { return (m + kLevelThreads * kLevelPpt - 1) / (kLevelThreads * kLevelPpt); }
+
+hipError_t launch_level(const float *pts, int m, const float *A, const Grid &g, double *psum,
+                        int32_t *pcnt, DevStatus *st, hipStream_t s) {
+    const int nb = level_blocks(m);
+    if (nb > 0) {
+        level_partial_kernel<<<dim3(nb), dim3(kLevelThreads), 0, s>>>(pts, m, A, g, psum, pcnt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    level_final_kernel<<<1, kLevelThreads, 0, s>>>(psum, pcnt, nb, st);
+    return hipGetLastError();
+}
+
+__global__ void level_to_f32_kernel(const DevStatus *st, float *lf) {
+    if (threadIdx.x == 0) *lf = (float)st->level;
+}
+
+hipError_t launch_level_to_f32(const DevStatus *st, float *level_f32, hipStream_t s) {
+    level_to_f32_kernel<<<1, 64, 0, s>>>(st, level_f32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Marching cubes
+// ---------------------------------------------------------------------------
+hipError_t mc_upload_table(const uint8_t *counts, const int8_t *edges) {
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_mc_count), counts, 256);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_mc_edges), edges, 256 * kMcRow);
+}
+
+int mc_blocks(const Grid &g) {
+    const int64_t n = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    return (int)((n + kMcPerBlock - 1) / kMcPerBlock);
+}
+
+// Edge bits (bit a: grid edge (q, q + e_a) crosses the level) and the case of
+// the cell with lower corner q (-1 when q is on the upper border).
+__device__ __forceinline__ void mc_point(const float *__restrict__ A, const Grid &g, int qx, int qy,
+                                         int qz, size_t l, float L, int &ebits, int &cs) {
+    const size_t sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
+    const bool in0 = A[l] > L;
+    const bool hx = qx + 1 < g.n[0], hy = qy + 1 < g.n[1], hz = qz + 1 < g.n[2];
+    ebits = 0;
+    cs = -1;
+    if (hx && hy && hz) {
+        cs = in0 ? 1 : 0;
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+            const size_t o = l + (k & 1) + ((k >> 1) & 1) * sy + ((k >> 2) & 1) * sz;
+            cs |= (A[o] > L ? 1 : 0) << k;
+        }
+        ebits = (((cs >> 1) & 1) != (cs & 1) ? 1 : 0) | (((cs >> 2) & 1) != (cs & 1) ? 2 : 0) |
+                (((cs >> 4) & 1) != (cs & 1) ? 4 : 0);
+    } else {
+        if (hx && ((A[l + 1] > L) != in0)) ebits |= 1;
+        if (hy && ((A[l + sy] > L) != in0)) ebits |= 2;
+        if (hz && ((A[l + sz] > L) != in0)) ebits |= 4;
+    }
+}
+
+__device__ __forceinline__ int block_sum(int v, int *red) {
+    // 256 threads = 4 waves
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wid] = v;
+    __syncthreads();
+    const int t = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ void __launch_bounds__(kMcThreads)
+mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
+                int32_t *__restrict__ blk_counts, uint8_t *__restrict__ cases_out, DevStatus *st) {
+    __shared__ int red[4];
+    const float L = *level_f32;
+    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
+    const size_t l0 = (size_t)blockIdx.x * kMcPerBlock + (size_t)threadIdx.x * kMcPpt;
+    int nv = 0, nt = 0, na = 0;
+    bool open = false;
+    if (l0 < n) {
+        int qx = (int)(l0 % g.n[0]);
+        size_t r = l0 / g.n[0];
+        int qy = (int)(r % g.n[1]);
+        int qz = (int)(r / g.n[1]);
+        for (int i = 0; i < kMcPpt; ++i) {
+            const size_t l = l0 + i;
+            if (l >= n) break;
+            int eb, cs;
+            mc_point(A, g, qx, qy, qz, l, L, eb, cs);
+            nv += __popc(eb);
+            if (cs >= 0) {
+                const int c = c_mc_count[cs];
+                nt += c;
+                na += c > 0;
+                if (cases_out)
+                    cases_out[qx + (size_t)(g.n[0] - 1) * (qy + (size_t)(g.n[1] - 1) * qz)] = (uint8_t)cs;
+            }
+            const bool border = qx == 0 || qy == 0 || qz == 0 || qx == g.n[0] - 1 ||
+                                qy == g.n[1] - 1 || qz == g.n[2] - 1;
+            if (border && A[l] > L) open = true;
+            if (++qx == g.n[0]) {
+                qx = 0;
+                if (++qy == g.n[1]) {
+                    qy = 0;
+                    ++qz;
+                }
+            }
+        }
+    }
+    if (__ballot(open) && (threadIdx.x & 63) == 0) atomicOr(&st->flags, kFlagOpen);
+    nv = block_sum(nv, red);
+    nt = block_sum(nt, red);
+    na = block_sum(na, red);
+    if (threadIdx.x == 0) {
+        blk_counts[3 * blockIdx.x + 0] = nv;
+        blk_counts[3 * blockIdx.x + 1] = nt;
+        blk_counts[3 * blockIdx.x + 2] = na;
+    }
+}
+
+// Exclusive block scan of three counters (256 threads).
+__device__ __forceinline__ void block_excl_scan3(int v[3], int *red /* [3][4] */) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        incl[c] = v[c];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl[c], d, 64);
+            if (lane >= d) incl[c] += u;
+        }
+        if (lane == 63) red[c * 4 + wid] = incl[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int off = 0;
+        for (int w = 0; w < wid; ++w) off += red[c * 4 + w];
+        v[c] = off + incl[c] - v[c];
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kMcThreads)
+mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
+                   const int32_t *__restrict__ blk_off, float *__restrict__ verts,
+                   int32_t *__restrict__ vidx, int4 *__restrict__ cells) {
+    __shared__ int red[12];
+    const float L = *level_f32;
+    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
+    const size_t l0 = (size_t)blockIdx.x * kMcPerBlock + (size_t)threadIdx.x * kMcPpt;
+    int eb[kMcPpt], cs[kMcPpt];
+    int cnt[3] = {0, 0, 0};
+    int qx = 0, qy = 0, qz = 0;
+    if (l0 < n) {
+        qx = (int)(l0 % g.n[0]);
+        const size_t r = l0 / g.n[0];
+        qy = (int)(r % g.n[1]);
+        qz = (int)(r / g.n[1]);
+    }
+    {
+        int x = qx, y = qy, z = qz;
+#pragma unroll
+        for (int i = 0; i < kMcPpt; ++i) {
+            eb[i] = 0;
+            cs[i] = -1;
+            const size_t l = l0 + i;
+            if (l < n) {
+                mc_point(A, g, x, y, z, l, L, eb[i], cs[i]);
+                cnt[0] += __popc(eb[i]);
+                if (cs[i] >= 0) {
+                    const int c = c_mc_count[cs[i]];
+                    cnt[1] += c;
+                    cnt[2] += c > 0;
+                }
+            }
+            if (++x == g.n[0]) {
+                x = 0;
+                if (++y == g.n[1]) {
+                    y = 0;
+                    ++z;
+                }
+            }
+        }
+    }
+    block_excl_scan3(cnt, red);
+    int vbase = blk_off[3 * blockIdx.x + 0] + cnt[0];
+    int tbase = blk_off[3 * blockIdx.x + 1] + cnt[1];
+    int abase = blk_off[3 * blockIdx.x + 2] + cnt[2];
+    const size_t sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
+    int x = qx, y = qy, z = qz;
+    for (int i = 0; i < kMcPpt; ++i) {
+        const size_t l = l0 + i;
+        if (l >= n) break;
+        if (eb[i]) {
+            const float a0 = A[l];
+            const float px = fmaf((float)x + 0.5f, g.h[0], g.bmin[0]);
+            const float py = fmaf((float)y + 0.5f, g.h[1], g.bmin[1]);
+            const float pz = fmaf((float)z + 0.5f, g.h[2], g.bmin[2]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (!((eb[i] >> a) & 1)) continue;
+                const float a1 = A[l + (a == 0 ? 1 : a == 1 ? sy : sz)];
+                const float t = (L - a0) / (a1 - a0);
+                float p[3] = {px, py, pz};
+                p[a] += t * g.h[a];
+                verts[3 * (size_t)vbase + 0] = p[0];
+                verts[3 * (size_t)vbase + 1] = p[1];
+                verts[3 * (size_t)vbase + 2] = p[2];
+                vidx[3 * l + a] = vbase;
+                ++vbase;
+            }
+        }
+        if (cs[i] >= 0) {
+            const int c = c_mc_count[cs[i]];
+            if (c > 0) {
+                cells[abase] = make_int4((int)l, cs[i], tbase, 0);
+                ++abase;
+                tbase += c;
+            }
+        }
+        if (++x == g.n[0]) {
+            x = 0;
+            if (++y == g.n[1]) {
+                y = 0;
+                ++z;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+mc_triangles_kernel(const int4 *__restrict__ cells, int n_cells, const int32_t *__restrict__ vidx,
+                    Grid g, int32_t *__restrict__ tris) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cells) return;
+    const int4 c = cells[i];
+    const size_t l = (size_t)(unsigned)c.x;
+    const int cs = c.y;
+    const size_t sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
+    const int nt = c_mc_count[cs];
+    for (int t = 0; t < nt; ++t) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int e = c_mc_edges[cs * kMcRow + 3 * t + j];
+            const int axis = e >> 2, r = e & 3;
+            // offsets of the edge's low corner on the two other axes (x<y<z order)
+            const int o0 = axis == 0 ? 1 : 0, o1 = axis == 2 ? 1 : 2;
+            int off[3] = {0, 0, 0};
+            off[o0] = r & 1;
+            off[o1] = r >> 1;
+            const size_t lq = l + off[0] + off[1] * sy + off[2] * sz;
+            tris[3 * ((size_t)c.z + t) + j] = vidx[3 * lq + axis];
+        }
+    }
+}
+
+hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
+                           int32_t *blk_counts, uint8_t *cases_out, DevStatus *st, hipStream_t s) {
+    mc_count_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, g, blk_counts,
+                                                                    cases_out, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
+                              const int32_t *blk_offsets, float *verts, int32_t *vidx, int4 *cells,
+                              hipStream_t s) {
+    mc_generate_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, g, blk_offsets,
+                                                                       verts, vidx, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_triangles(const int4 *cells, int n_cells, const int32_t *vidx, const Grid &g,
+                               int32_t *tris, hipStream_t s) {
+    if (n_cells <= 0) return hipSuccess;
+    mc_triangles_kernel<<<dim3((n_cells + 255) / 256), dim3(256), 0, s>>>(cells, n_cells, vidx, g,
+                                                                          tris);
+    return hipGetLastError();
+}
+
+}  // namespace fvr

@@ -1,0 +1,67 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/fvr.h declares, validates grids on the host, and its own
+marching-cubes table generator agrees byte for byte with the oracle's
+independently written one."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1712_03084_amd as fvr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fvr.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(fvr_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(fvr.library_path())
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_check_grid_statuses():
+    ok = (-1, -1, -1, 1, 1, 1)
+    assert fvr.check_grid((64, 64, 64), ok) == 0
+    assert fvr.check_grid((96, 160, 192), ok) == 0
+    assert fvr.check_grid((32, 64, 32), ok) == 0
+    assert fvr.check_grid((512, 8, 10), ok) == 0
+    assert fvr.check_grid((7, 64, 64), ok) == -1        # odd
+    assert fvr.check_grid((6, 64, 64), ok) == -1        # below 8
+    assert fvr.check_grid((14, 64, 64), ok) == -2       # 7 is not a factor allowed
+    assert fvr.check_grid((1024, 64, 64), ok) == -2     # above 512
+    assert fvr.check_grid((64, 64, 64), (0, 0, 0, 1, 0, 1)) == -1   # empty extent
+    assert fvr.check_grid((64, 64, 64), (0, 0, 0, 1, float("nan"), 1)) == -1
+
+
+def test_mc_table_identical_to_oracle_generator():
+    c_gpu, e_gpu = fvr.mc_table()
+    c_orc, e_orc = oracle.mc_table()
+    assert np.array_equal(c_gpu, c_orc)
+    assert np.array_equal(e_gpu, e_orc)
+
+
+def test_status_strings_and_null_context():
+    lib = fvr.load_library()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.fvr_status_string(s)
+    assert lib.fvr_reconstruct(None, None, None) == -1
+    assert lib.fvr_last_error(None)
+
+
+def test_entry_points_fail_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(fvr, "_LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(fvr, "_lib", None)
+    with pytest.raises(fvr.FvrUnavailable):
+        fvr.load_library()

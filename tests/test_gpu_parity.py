@@ -1,0 +1,273 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (float32 path vs double oracle):
+  splat V        max |V_gpu - V_orc| <= 1e-4 * max |V_orc|
+  indicator A    max |A_gpu - A_orc| <= 1e-4 * (max A_orc - min A_orc)   (stated target)
+  level L        |L_gpu - L_orc|     <= 1e-4 * range(A_orc)
+  marching cubes on the oracle's field rounded to float32 with L rounded to
+                 float32: case bytes, vertex/triangle counts and triangle index
+                 arrays bit-exact; vertex positions within 1e-4 h
+  end to end     symmetric vertex Hausdorff distance to the oracle mesh <= 0.05 h
+"""
+import collections
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1712_03084_amd as fvr  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return fvr.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _frame_dev(f):
+    w = None if f.weights is None else _dev(f.weights)
+    return _dev(f.points), _dev(f.normals), w
+
+
+def _random_frame(seed, m, dims, bbox, outside_frac=0.05):
+    rng = np.random.default_rng(seed)
+    b = np.asarray(bbox, np.float64)
+    lo, hi = b[:3], b[3:]
+    ext = hi - lo
+    p = rng.uniform(lo - outside_frac * ext, hi + outside_frac * ext, (m, 3))
+    n = rng.standard_normal((m, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    w = rng.uniform(0.05, 2.0, m)
+    return synth.Frame(p.astype(np.float32), n.astype(np.float32), w.astype(np.float32),
+                       tuple(dims), tuple(float(x) for x in bbox))
+
+
+def _hausdorff(a, b):
+    from scipy.spatial import cKDTree
+    if len(a) == 0 and len(b) == 0:
+        return 0.0
+    d1 = cKDTree(b).query(a)[0].max()
+    d2 = cKDTree(a).query(b)[0].max()
+    return float(max(d1, d2))
+
+
+def _closed(tris):
+    und = collections.Counter()
+    for t in tris:
+        for i in range(3):
+            a, b = int(t[i]), int(t[(i + 1) % 3])
+            und[(min(a, b), max(a, b))] += 1
+    return all(v == 2 for v in und.values()), len(und)
+
+
+SPLAT_CASES = [
+    ("sphere64", None),
+    ("ragged_aniso", ((20, 12, 18), (-0.5, -0.3, -0.45, 0.5, 0.3, 0.45))),
+    ("paper_shape", ((32, 64, 32), (-0.5, -1.0, -0.5, 0.5, 1.0, 0.5))),
+    ("mixed_radix", ((30, 24, 40), (0.0, 0.0, 0.0, 1.2, 0.9, 1.5))),
+]
+
+
+def _case_frame(name, spec, seed=11, m=20000):
+    if name == "sphere64":
+        return synth.sphere_frame(seed=0, m=50_000, grid=64)
+    dims, bbox = spec
+    return _random_frame(seed, m, dims, bbox)
+
+
+@pytest.mark.parametrize("name,spec", SPLAT_CASES)
+def test_splat_parity(ctx, name, spec):
+    print(f"[splat] {name}", flush=True)
+    f = _case_frame(name, spec)
+    V = ctx.debug_splat(*_frame_dev(f), grid_dim=f.dims, bbox=f.bbox).cpu().numpy()
+    Vo, _, _, _ = oracle.splat(f.points, f.normals, f.weights, f.dims, f.bbox)
+    scale = np.abs(Vo).max()
+    err = np.abs(V - Vo).max()
+    print(f"  max|V|={scale:.4g} max err={err:.3g} rel={err / scale:.3g}")
+    assert err <= 1e-4 * scale
+    # identical support: the footprint decision is the same float32 formula
+    assert np.array_equal(np.abs(V).sum(0) > 0, np.abs(Vo).sum(0) > 0)
+
+
+INDICATOR_CASES = SPLAT_CASES + [
+    ("paper_r6_shape", ((64, 128, 64), (-0.6, -1.2, -0.6, 0.6, 1.2, 0.6))),
+    ("radix_96_160_192", ((96, 160, 192), (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0))),
+]
+
+
+@pytest.mark.parametrize("name,spec", INDICATOR_CASES)
+def test_indicator_and_level_parity(ctx, name, spec):
+    print(f"[indicator] {name}", flush=True)
+    f = _case_frame(name, spec, m=60000)
+    A, L = ctx.indicator(*_frame_dev(f), grid_dim=f.dims, bbox=f.bbox)
+    A = A.cpu().numpy()
+    Vo, _, _, _ = oracle.splat(f.points, f.normals, f.weights, f.dims, f.bbox)
+    Ao = oracle.indicator(Vo, f.dims, f.bbox)
+    Lo, _ = oracle.level(Ao, f.points, f.dims, f.bbox)
+    rng_ = Ao.max() - Ao.min()
+    err = np.abs(A - Ao).max()
+    print(f"  range={rng_:.4g} max err={err:.3g} rel={err / rng_:.3g}  L={L:.8g} Lo={Lo:.8g}")
+    assert err <= 1e-4 * rng_
+    assert abs(L - Lo) <= 1e-4 * rng_
+
+
+def _mc_compare(ctx, Ao, Lo, dims, bbox):
+    A32 = Ao.astype(np.float32)
+    L32 = np.float32(Lo)
+    mesh, cases = ctx.extract(_dev(A32), bbox, float(L32), with_cases=True)
+    vo, to, co = oracle.extract(A32.astype(np.float64), float(L32), dims, bbox)
+    assert np.array_equal(cases.cpu().numpy(), co)
+    assert mesh.vertices.shape[0] == len(vo)
+    assert mesh.triangles.shape[0] == len(to)
+    assert np.array_equal(mesh.triangles.cpu().numpy(), to)
+    h = (np.asarray(bbox[3:], np.float64) - np.asarray(bbox[:3], np.float64)) / np.asarray(dims)
+    dv = np.abs(mesh.vertices.cpu().numpy().astype(np.float64) - vo).max(0) if len(vo) else np.zeros(3)
+    print(f"  V={len(vo)} T={len(to)} max vertex err / h = {dv / h}")
+    assert np.all(dv <= 1e-4 * h)
+    return mesh
+
+
+def test_marching_cubes_bit_exact_on_oracle_field_sphere(ctx):
+    f = synth.sphere_frame(seed=0, m=50_000, grid=64)
+    r = oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+    _mc_compare(ctx, r["A"], r["level"], f.dims, f.bbox)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_marching_cubes_bit_exact_random_fields(ctx, seed):
+    """Random fields exercise every case family, ragged block tails and
+    surfaces that reach the grid border."""
+    rng = np.random.default_rng(seed)
+    dims = (36, 22, 30)
+    A = rng.standard_normal(dims[::-1])
+    _mc_compare(ctx, A, 0.1, dims, (0.0, 0.0, 0.0, 3.6, 2.2, 3.0))
+
+
+def test_marching_cubes_ties_are_outside(ctx):
+    rng = np.random.default_rng(5)
+    dims = (16, 10, 12)
+    A = rng.integers(0, 3, dims[::-1]).astype(np.float64)
+    _mc_compare(ctx, A, 1.0, dims, (0.0, 0.0, 0.0, 1.6, 1.0, 1.2))
+
+
+def test_reconstruct_sphere_end_to_end(ctx):
+    f = synth.sphere_frame(seed=0, m=50_000, grid=64)
+    mesh = ctx.reconstruct(*_frame_dev(f), grid_dim=f.dims, bbox=f.bbox)
+    r = oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+    v = mesh.vertices.cpu().numpy().astype(np.float64)
+    t = mesh.triangles.cpu().numpy()
+    h = 2.0 / 64
+    hd = _hausdorff(v, r["verts"])
+    print(f"  V={len(v)} (oracle {len(r['verts'])}) T={len(t)} Hausdorff/h={hd / h:.3g} "
+          f"L={mesh.level:.8g} Lo={r['level']:.8g}")
+    assert hd <= 0.05 * h
+    assert np.max(np.abs(np.linalg.norm(v, axis=1) - 0.8)) <= h
+    ok, ne = _closed(t)
+    assert ok and len(v) - ne + len(t) == 2
+    assert mesh.n_rejected == 0 and not mesh.open_surface
+
+
+@pytest.mark.slow
+def test_full_size_human_proxy_256(ctx):
+    """The headline workload: 6-view human proxy, 700k points, 256^3."""
+    print("[full] generating human proxy 6 views 256^3", flush=True)
+    f = synth.config_frame("proxy256")
+    dev = _frame_dev(f)
+    A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
+    mesh = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox)
+    print("[full] oracle", flush=True)
+    r = oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+    Ao = r["A"]
+    rng_ = Ao.max() - Ao.min()
+    err = np.abs(A.cpu().numpy() - Ao).max()
+    h = 2.0 / 256
+    hd = _hausdorff(mesh.vertices.cpu().numpy().astype(np.float64), r["verts"])
+    print(f"  A rel err={err / rng_:.3g} L={L:.8g} Lo={r['level']:.8g} V={mesh.vertices.shape[0]} "
+          f"(oracle {len(r['verts'])}) Hausdorff/h={hd / h:.3g}")
+    assert err <= 1e-4 * rng_
+    assert abs(L - r["level"]) <= 1e-4 * rng_
+    assert abs(mesh.level - r["level"]) <= 1e-4 * rng_
+    assert hd <= 0.05 * h
+    assert abs(mesh.vertices.shape[0] - len(r["verts"])) <= 0.001 * len(r["verts"])
+    ok, _ = _closed(mesh.triangles.cpu().numpy())
+    assert ok
+
+
+def test_empty_and_all_rejected(ctx):
+    z = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    mesh = ctx.reconstruct(z, z, None, grid_dim=(16, 16, 16), bbox=(-1, -1, -1, 1, 1, 1))
+    assert mesh.vertices.shape[0] == 0 and mesh.triangles.shape[0] == 0 and mesh.level == 0.0
+    p = torch.full((100, 3), 5.0, device="cuda")
+    mesh = ctx.reconstruct(p, p, None, grid_dim=(16, 16, 16), bbox=(-1, -1, -1, 1, 1, 1))
+    assert mesh.n_rejected == 100 and mesh.vertices.shape[0] == 0 and mesh.level == 0.0
+
+
+def test_invalid_values_rejected(ctx):
+    f = synth.sphere_frame(seed=3, m=1000, grid=16)
+    p, n, w = _frame_dev(f)
+    p2 = p.clone()
+    p2[17, 1] = float("nan")
+    with pytest.raises(fvr.FvrError) as e:
+        ctx.reconstruct(p2, n, w, grid_dim=f.dims, bbox=f.bbox)
+    assert e.value.status == -1
+    w2 = w.clone()
+    w2[3] = -1.0
+    with pytest.raises(fvr.FvrError) as e:
+        ctx.reconstruct(p, n, w2, grid_dim=f.dims, bbox=f.bbox)
+    assert e.value.status == -1
+    with pytest.raises(fvr.FvrError) as e:
+        ctx.reconstruct(p, n, w, grid_dim=(14, 16, 16), bbox=f.bbox)
+    assert e.value.status == -2
+    # the context still works afterwards
+    mesh = ctx.reconstruct(p, n, w, grid_dim=f.dims, bbox=f.bbox)
+    assert mesh.vertices.shape[0] > 0
+
+
+def test_capacity_shortfall_reports_counts_then_retry(ctx):
+    f = synth.sphere_frame(seed=0, m=20_000, grid=32)
+    p, n, w = _frame_dev(f)
+    full = ctx.reconstruct(p, n, w, grid_dim=f.dims, bbox=f.bbox)
+    small = (torch.empty((8, 3), dtype=torch.float32, device="cuda"),
+             torch.empty((8, 3), dtype=torch.int32, device="cuda"))
+    with pytest.raises(fvr.FvrError) as e:
+        ctx.reconstruct(p, n, w, grid_dim=f.dims, bbox=f.bbox, out=small)
+    assert e.value.status == -4
+    retried = ctx.reconstruct(p, n, w, grid_dim=f.dims, bbox=f.bbox, vertex_capacity=8,
+                              triangle_capacity=8)
+    assert retried.vertices.shape == full.vertices.shape
+    assert retried.triangles.shape == full.triangles.shape
+
+
+@pytest.mark.parametrize("dims", [(512, 16, 16), (16, 512, 16), (16, 16, 512)])
+def test_maximum_axis_length(ctx, dims):
+    print(f"[max axis] {dims}", flush=True)
+    bbox = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
+    f = _random_frame(21, 20000, dims, bbox)
+    A, L = ctx.indicator(*_frame_dev(f), grid_dim=dims, bbox=bbox)
+    Vo, _, _, _ = oracle.splat(f.points, f.normals, f.weights, dims, bbox)
+    Ao = oracle.indicator(Vo, dims, bbox)
+    rng_ = Ao.max() - Ao.min()
+    err = np.abs(A.cpu().numpy() - Ao).max()
+    print(f"  rel err={err / rng_:.3g}")
+    assert err <= 1e-4 * rng_
+
+
+def test_open_surface_flag(ctx):
+    f = synth.sphere_frame(seed=4, m=30_000, grid=32, half_extent=0.7)
+    mesh = ctx.reconstruct(*_frame_dev(f), grid_dim=f.dims, bbox=f.bbox)
+    r = oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+    assert mesh.n_rejected == r["n_rejected"] > 0
+    assert mesh.open_surface == r["open_surface"]
+    g = synth.sphere_frame(seed=4, m=30_000, grid=32)
+    assert not ctx.reconstruct(*_frame_dev(g), grid_dim=g.dims, bbox=g.bbox).open_surface

@@ -113,7 +113,8 @@ fvr_status fvr_indicator(fvr_ctx *ctx, const fvr_frame *frame, float *field_out,
                          double *level_out);
 
 /* Step 6 only: marching cubes of a caller field (Nz x Ny x Nx floats,
- * device) at `level`.  cases_out (optional, device, (Nz-1)(Ny-1)(Nx-1)
+ * device) at `level`.  Any dims >= 2 are accepted (no transform-size
+ * constraint) as long as 3 Nx Ny Nz < 2^31.  cases_out (optional, device, (Nz-1)(Ny-1)(Nx-1)
  * bytes, x fastest) receives each cell's case byte sum_k [A(corner k) > L]
  * 2^k with corner k at offset (k&1, (k>>1)&1, (k>>2)&1).  mesh->level is set
  * to `level`; mesh->n_rejected to 0.  Same kernels as fvr_reconstruct. */

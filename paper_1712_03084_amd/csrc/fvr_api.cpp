@@ -167,6 +167,21 @@ fvr_status check_grid(fvr_ctx *c, const int32_t dims[3], const float bbox[6]) {
     return FVR_OK;
 }
 
+// Marching cubes alone has no transform-size constraint: any dims >= 2 whose
+// 3 n edge slots fit int32 indexing.
+fvr_status check_extract_grid(fvr_ctx *c, const int32_t dims[3], const float bbox[6]) {
+    if (!dims || !bbox) return fail(c, FVR_E_INVALID, "dims or bbox is NULL");
+    int64_t n = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] < 2) return fail(c, FVR_E_INVALID, "grid dims must be >= 2");
+        n *= dims[a];
+        if (!std::isfinite(bbox[a]) || !std::isfinite(bbox[a + 3]) || !(bbox[a + 3] > bbox[a]))
+            return fail(c, FVR_E_INVALID, "bbox must be finite with max > min");
+    }
+    if (3 * n > 0x7fffffff) return fail(c, FVR_E_UNSUPPORTED, "grid too large for int32 indexing");
+    return FVR_OK;
+}
+
 Grid make_grid(const int32_t dims[3], const float bbox[6]) {
     Grid g;
     for (int a = 0; a < 3; ++a) {
@@ -452,7 +467,7 @@ fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, doubl
 fvr_status fvr_extract(fvr_ctx *c, const float *field, const int32_t dims[3], const float bbox[6],
                        float level, fvr_mesh *mesh, uint8_t *cases_out) {
     if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
-    fvr_status r = check_grid(c, dims, bbox);
+    fvr_status r = check_extract_grid(c, dims, bbox);
     if (r != FVR_OK) return r;
     if (!field || !mesh) return fail(c, FVR_E_INVALID, "field or mesh is NULL");
     if (!std::isfinite(level)) return fail(c, FVR_E_INVALID, "level is not finite");

@@ -7,6 +7,7 @@
 //   reset -> bin_count -> scan -> bin_scatter -> splat+fft_x -> fft_y ->
 //   fft_z+solve -> fft_y_inv -> fft_x_c2r -> level -> mc_count -> scan
 //   -> [one device->host read of the counts] -> mc_generate -> mc_triangles.
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -24,14 +25,14 @@ using namespace fvr;
 namespace {
 
 enum KernelId {
-    K_RESET, K_BIN_FILL, K_BIN_COUNT, K_BIN_SCAN, K_BIN_SCATTER, K_SPLAT_FFT_X,
-    K_FFT_Y_FWD, K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_LEVEL, K_LEVEL_F32,
-    K_MC_COUNT, K_MC_SCAN, K_MC_GENERATE, K_MC_TRIANGLES, K_COUNT
+    K_PREP, K_BIN_COUNT, K_BIN_SCAN, K_BIN_SCATTER, K_SPLAT_FFT_X, K_FFT_Y_FWD,
+    K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_LEVEL, K_MC_COUNT, K_MC_SCAN,
+    K_MC_GENERATE, K_MC_TRIANGLES, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {
-    "reset_status", "bin_fill", "bin_count", "bin_scan", "bin_scatter", "splat_fft_x",
-    "fft_y_fwd", "fft_z_solve", "fft_y_inv", "fft_x_c2r", "level", "level_to_f32",
-    "mc_count", "mc_scan", "mc_generate", "mc_triangles"};
+    "prep", "bin_count", "bin_scan", "bin_scatter", "splat_fft_x", "fft_y_fwd",
+    "fft_z_solve", "fft_y_inv", "fft_x_c2r", "level", "mc_count", "mc_scan",
+    "mc_generate", "mc_triangles"};
 
 thread_local std::string g_error;
 
@@ -68,7 +69,7 @@ struct fvr_ctx {
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off,
-        lvl_sum, lvl_cnt, status, level_f32, scan_tot;
+        lvl_sum, lvl_cnt, status, level_f32, scan_part;
     DevStatus *host_status = nullptr;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -222,7 +223,7 @@ fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan
         HIP_TRY(c, hipMemcpy(np.tw, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice),
                 "hipMemcpy(twiddles)");
         for (int a = 0; a < 3; ++a) np.ax[a].tw = np.tw + offs[a];
-        // splat tile: ty x tz full x-rows with 4 float planes <= 64 KiB of LDS
+        // splat tile: ty x tz full x-rows, 4 int64 planes <= 128 KiB of LDS
         const int nx = dims[0];
         int R = 64;
         while (R > 4 && R * nx > 4096) R /= 2;
@@ -274,24 +275,25 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g, flo
     HIP_TRY(c, ensure(c->rec, sizeof(float4) * 2 * (size_t)m), "alloc records");
     HIP_TRY(c, ensure(c->spec, sizeof(float2) * 3 * nspec), "alloc spectra");
     HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
-    HIP_TRY(c, ensure(c->scan_tot, sizeof(int32_t) * 4), "alloc scan totals");
+    // sized for both scans of the frame before anything is enqueued
+    const int scan_items = std::max(scan_partials(nbins), scan_partials(mc_blocks(g)));
+    HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_items), "alloc scan scratch");
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
-    { Timed t(c, K_RESET); HIP_TRY(c, launch_reset_status(st, s), "reset_status"); }
-    { Timed t(c, K_BIN_FILL); HIP_TRY(c, launch_fill_i32(P<int32_t>(c->bin_count), nbins, 0, s), "bin_fill"); }
+    { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(st, P<int32_t>(c->bin_count), nbins, s), "prep"); }
     { Timed t(c, K_BIN_COUNT);
       HIP_TRY(c, launch_bin_count(f->points, f->normals, f->weights, m, g, P<int32_t>(c->bin_count),
                                   P<int32_t>(c->key), P<int32_t>(c->rank), st, s), "bin_count"); }
     { Timed t(c, K_BIN_SCAN);
       HIP_TRY(c, launch_scan(P<int32_t>(c->bin_count), P<int32_t>(c->bin_off), nbins, 1,
-                             P<int32_t>(c->scan_tot), s), "bin_scan"); }
+                             P<int32_t>(c->scan_part), nullptr, s), "bin_scan"); }
     { Timed t(c, K_BIN_SCATTER);
       HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, P<int32_t>(c->key),
                                     P<int32_t>(c->rank), P<int32_t>(c->bin_off), P<float4>(c->rec), s),
               "bin_scatter"); }
     { Timed t(c, K_SPLAT_FFT_X);
       HIP_TRY(c, launch_splat_fft_x(P<float4>(c->rec), P<int32_t>(c->bin_off), g, p->sc, p->ax[0],
-                                    P<float2>(c->spec), v_out, s), "splat_fft_x"); }
+                                    st, P<float2>(c->spec), v_out, s), "splat_fft_x"); }
     if (splat_only) return FVR_OK;
     float2 *sp = P<float2>(c->spec);
     { Timed t(c, K_FFT_Y_FWD); HIP_TRY(c, launch_fft_y_fwd(sp, g, p->ax[1], s), "fft_y_fwd"); }
@@ -309,10 +311,7 @@ fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float 
     HIP_TRY(c, ensure(c->level_f32, sizeof(float)), "alloc level");
     { Timed t(c, K_LEVEL);
       HIP_TRY(c, launch_level(f->points, m, field, g, P<double>(c->lvl_sum), P<int32_t>(c->lvl_cnt),
-                              P<DevStatus>(c->status), c->stream), "level"); }
-    { Timed t(c, K_LEVEL_F32);
-      HIP_TRY(c, launch_level_to_f32(P<DevStatus>(c->status), P<float>(c->level_f32), c->stream),
-              "level_to_f32"); }
+                              P<DevStatus>(c->status), P<float>(c->level_f32), c->stream), "level"); }
     return FVR_OK;
 }
 
@@ -325,14 +324,15 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
     HIP_TRY(c, ensure(c->mc_cnt, sizeof(int32_t) * 3 * (size_t)nb), "alloc mc counts");
     HIP_TRY(c, ensure(c->mc_off, sizeof(int32_t) * 3 * ((size_t)nb + 1)), "alloc mc offsets");
     HIP_TRY(c, ensure(c->vidx, sizeof(int32_t) * 3 * n), "alloc vertex ids");
+    HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_partials(nb)), "alloc scan scratch");
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     { Timed t(c, K_MC_COUNT);
       HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_cnt), cases_out,
                                  st, s), "mc_count"); }
     { Timed t(c, K_MC_SCAN);
-      HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3, st->mc_total, s),
-              "mc_scan"); }
+      HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3,
+                             P<int32_t>(c->scan_part), st->mc_total, s), "mc_scan"); }
     HIP_TRY(c, hipMemcpyAsync(c->host_status, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s),
             "status readback");
     fvr_status r = sync(c);
@@ -406,7 +406,7 @@ void fvr_destroy(fvr_ctx *c) {
     for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_tot};
+                      &c->status, &c->level_f32, &c->scan_part};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {
@@ -475,7 +475,7 @@ fvr_status fvr_extract(fvr_ctx *c, const float *field, const int32_t dims[3], co
     const Grid g = make_grid(dims, bbox);
     HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
     HIP_TRY(c, ensure(c->level_f32, sizeof(float)), "alloc level");
-    { Timed t(c, K_RESET); HIP_TRY(c, launch_reset_status(P<DevStatus>(c->status), c->stream), "reset_status"); }
+    { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(P<DevStatus>(c->status), nullptr, 0, c->stream), "prep"); }
     HIP_TRY(c, hipMemcpyAsync(c->level_f32.p, &level, sizeof(float), hipMemcpyHostToDevice, c->stream),
             "level upload");
     r = run_mc(c, g, field, mesh, cases_out, false);

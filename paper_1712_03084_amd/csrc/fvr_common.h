@@ -51,6 +51,8 @@ struct DevStatus {
     int32_t mc_total[3];  // vertices, triangles, active cells
     int32_t n_used;       // points that entered the level average
     double level;
+    uint32_t wmax_bits;   // float bits of max W over accepted points (W >= 0)
+    uint32_t wnmax_bits;  // float bits of max W |N_c| over accepted points
 };
 constexpr uint32_t kFlagInvalid = 1u;
 constexpr uint32_t kFlagOpen = 2u;
@@ -61,13 +63,16 @@ constexpr uint32_t kFlagOpen = 2u;
 
 // Fill `n` int32 with `v`.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
-// Reset the status block (flags, counts, level).
-hipError_t launch_reset_status(DevStatus *st, hipStream_t s);
+
+// Reset the status block and zero `nbins` bin counters in one launch.
+hipError_t launch_prep(DevStatus *st, int32_t *bins, int nbins, hipStream_t s);
 
 // Exclusive scan of `n` items of `C` interleaved int32 components (C = 1 or 3):
 // out[i*C + c] = sum_{j<i} in[j*C + c]; out[n*C + c] = total; totals[c] = total.
-hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *totals,
-                       hipStream_t s);
+// `partial` is scratch of scan_partials(n) * C ints.
+int scan_partials(int n);
+hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *partial,
+                       int32_t *totals, hipStream_t s);
 
 // Splat, stage 1: validate and bin points by the (y, z) row of their
 // footprint origin.  key[i] = -1 for rejected points.
@@ -79,12 +84,13 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
                               const int32_t *key, const int32_t *rank, const int32_t *bin_off,
                               float4 *rec, hipStream_t s);
 // Splat, stage 3 fused with the forward real FFT along x: each block owns
-// ty x tz full x-rows, accumulates S_x, S_y, S_z and D in LDS, forms
+// ty x tz full x-rows, accumulates S_x, S_y, S_z and D in LDS (64-bit fixed
+// point, scaled per frame from st->wmax_bits / wnmax_bits), forms
 // V = S/D, transforms along x and writes three half-spectrum planes
 // (the x-component already multiplied by j w_x).  v_out (optional) receives V.
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
-                              const SplatConsts &sc, const FftAxis &ax, float2 *spec,
-                              float *v_out, hipStream_t s);
+                              const SplatConsts &sc, const FftAxis &ax, const DevStatus *st,
+                              float2 *spec, float *v_out, hipStream_t s);
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc);
 
 // Forward y transform of the three planes, combining the x and y
@@ -100,10 +106,11 @@ hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const F
                             hipStream_t s);
 
 // Iso-level: per-block double partial sums of trilinear A at accepted points,
-// then one block reduces them in a fixed order into st->level and st->n_used.
+// then one block reduces them in a fixed order into st->level, st->n_used and
+// *level_f32 (the level rounded to float for the marching-cubes comparisons).
 hipError_t launch_level(const float *pts, int m, const float *A, const Grid &g,
                         double *partial_sum, int32_t *partial_cnt, DevStatus *st,
-                        hipStream_t s);
+                        float *level_f32, hipStream_t s);
 int level_blocks(int m);
 
 // Marching cubes.
@@ -117,8 +124,6 @@ hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid
                               int4 *cells, hipStream_t s);
 hipError_t launch_mc_triangles(const int4 *cells, int n_cells, const int32_t *vidx,
                                const Grid &g, int32_t *tris, hipStream_t s);
-// level_f32 <- (float)st->level
-hipError_t launch_level_to_f32(const DevStatus *st, float *level_f32, hipStream_t s);
 
 // Raise the dynamic-LDS limit of the kernels that stage tiles above 64 KiB.
 hipError_t splat_configure();

@@ -25,9 +25,42 @@ namespace fvr {
 
 constexpr int kChunk = 16;
 constexpr int kPassThreads = 256;
-constexpr int kC2rRows = 16;  // real rows per C2R block (pairs -> 8 complex rows)
+constexpr int kC2rRows = 16;   // real rows per C2R block (pairs -> 8 complex rows)
+constexpr int kBatch = 8;      // global loads kept in flight per thread
 
 __device__ __forceinline__ int nchunks(int H) { return (H + kChunk - 1) / kChunk; }
+
+// Stage a [len][kChunk] pencil tile of one spectrum plane into LDS: element
+// (t, c) from src[t * stride + kx0 + c], zero for kx0 + c >= H.  Loads are
+// issued kBatch at a time into registers before any LDS store, so each
+// thread keeps several global loads in flight instead of one.
+__device__ __forceinline__ void load_pencils(float2 *dst, const float2 *__restrict__ src,
+                                             size_t stride, int len, int kx0, int H) {
+    const int tot = len * kChunk;
+    for (int base = 0; base < tot; base += kBatch * kPassThreads) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = base + u * kPassThreads + threadIdx.x;
+            const int t = i / kChunk, c = i % kChunk;
+            v[u] = (i < tot && kx0 + c < H) ? src[t * stride + kx0 + c] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = base + u * kPassThreads + threadIdx.x;
+            if (i < tot) dst[i] = v[u];
+        }
+    }
+}
+
+__device__ __forceinline__ void store_pencils(float2 *__restrict__ dstg, const float2 *src,
+                                              size_t stride, int len, int kx0, int H) {
+    const int tot = len * kChunk;
+    for (int i = threadIdx.x; i < tot; i += kPassThreads) {
+        const int t = i / kChunk, c = i % kChunk;
+        if (kx0 + c < H) dstg[t * stride + kx0 + c] = src[i];
+    }
+}
 
 __global__ void __launch_bounds__(kPassThreads)
 fft_y_fwd_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
@@ -37,37 +70,27 @@ fft_y_fwd_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
-    float2 *A = lds, *B = lds + Ny * kChunk;
+    float2 *A = lds, *B = lds + Ny * kChunk, *tw = lds + 2 * Ny * kChunk;
     const int tot = Ny * kChunk;
     const size_t zoff = (size_t)z * Ny * H;
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
-        const size_t o = zoff + (size_t)y * H + kx;
-        const bool ok = kx < H;
-        A[i] = ok ? spec[o] : make_float2(0.f, 0.f);
-        B[i] = ok ? spec[plane + o] : make_float2(0.f, 0.f);
-    }
+    load_twiddles(tw, ay);
+    load_pencils(A, spec + zoff, H, Ny, k0, H);
+    load_pencils(B, spec + plane + zoff, H, Ny, k0, H);
     __syncthreads();
-    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, ay, -1);
-    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, -1);
+    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, ay, tw, -1);
+    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, tw, -1);
     for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int ky = i / kChunk, c = i % kChunk, kx = k0 + c;
+        const int ky = i / kChunk;
         const float w = deriv_w(ky, Ny, g.wstep[1]);
         const float2 b = B[i];
-        const float2 r = make_float2(A[i].x - w * b.y, A[i].y + w * b.x);
-        if (kx < H) spec[zoff + (size_t)ky * H + kx] = r;
+        A[i] = make_float2(A[i].x - w * b.y, A[i].y + w * b.x);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
-        B[i] = kx < H ? spec[2 * plane + zoff + (size_t)y * H + kx] : make_float2(0.f, 0.f);
-    }
+    store_pencils(spec + zoff, A, H, Ny, k0, H);
+    load_pencils(B, spec + 2 * plane + zoff, H, Ny, k0, H);
     __syncthreads();
-    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, -1);
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int ky = i / kChunk, c = i % kChunk, kx = k0 + c;
-        if (kx < H) spec[2 * plane + zoff + (size_t)ky * H + kx] = B[i];
-    }
+    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, tw, -1);
+    store_pencils(spec + 2 * plane + zoff, B, H, Ny, k0, H);
 }
 
 __global__ void __launch_bounds__(kPassThreads)
@@ -79,23 +102,19 @@ fft_z_solve_kernel(float2 *__restrict__ spec, Grid g, FftAxis az) {
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
-    float2 *A = lds, *B = lds + Nz * kChunk;
+    float2 *A = lds, *B = lds + Nz * kChunk, *tw = lds + 2 * Nz * kChunk;
     const int tot = Nz * kChunk;
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int z = i / kChunk, c = i % kChunk, kx = k0 + c;
-        const size_t o = z * zstride + (size_t)ky * H + kx;
-        const bool ok = kx < H;
-        A[i] = ok ? spec[o] : make_float2(0.f, 0.f);
-        B[i] = ok ? spec[2 * plane + o] : make_float2(0.f, 0.f);
-    }
+    const size_t yoff = (size_t)ky * H;
+    load_twiddles(tw, az);
+    load_pencils(A, spec + yoff, zstride, Nz, k0, H);
+    load_pencils(B, spec + 2 * plane + yoff, zstride, Nz, k0, H);
     __syncthreads();
-    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, -1);
-    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, az, -1);
-    const float wxs = g.wstep[0], wys = g.wstep[1];
-    const float wy = (float)kappa(ky, Ny) * wys;
+    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, tw, -1);
+    fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, az, tw, -1);
+    const float wy = (float)kappa(ky, Ny) * g.wstep[1];
     for (int i = threadIdx.x; i < tot; i += blockDim.x) {
         const int kz = i / kChunk, c = i % kChunk, kx = k0 + c;
-        const float wx = (float)kappa(kx, g.n[0]) * wxs;
+        const float wx = (float)kappa(kx, g.n[0]) * g.wstep[0];
         const float wzf = (float)kappa(kz, Nz) * g.wstep[2];
         const float w2 = wx * wx + wy * wy + wzf * wzf;
         const float inv = w2 > 0.f ? 1.0f / w2 : 0.0f;
@@ -105,11 +124,8 @@ fft_z_solve_kernel(float2 *__restrict__ spec, Grid g, FftAxis az) {
         A[i] = make_float2((a.x - wz * b.y) * inv, (a.y + wz * b.x) * inv);
     }
     __syncthreads();
-    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, +1);
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int z = i / kChunk, c = i % kChunk, kx = k0 + c;
-        if (kx < H) spec[z * zstride + (size_t)ky * H + kx] = A[i];
-    }
+    fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, tw, +1);
+    store_pencils(spec + yoff, A, zstride, Nz, k0, H);
 }
 
 __global__ void __launch_bounds__(kPassThreads)
@@ -119,18 +135,13 @@ fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
-    const int tot = Ny * kChunk;
     const size_t zoff = (size_t)z * Ny * H;
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
-        lds[i] = kx < H ? spec[zoff + (size_t)y * H + kx] : make_float2(0.f, 0.f);
-    }
+    float2 *tw = lds + Ny * kChunk;
+    load_twiddles(tw, ay);
+    load_pencils(lds, spec + zoff, H, Ny, k0, H);
     __syncthreads();
-    fft_rows<true>(RowsC{lds, 1, kChunk}, kChunk, ay, +1);
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int y = i / kChunk, c = i % kChunk, kx = k0 + c;
-        if (kx < H) spec[zoff + (size_t)y * H + kx] = lds[i];
-    }
+    fft_rows<true>(RowsC{lds, 1, kChunk}, kChunk, ay, tw, +1);
+    store_pencils(spec + zoff, lds, H, Ny, k0, H);
 }
 
 // Inverse real transform along x.  Two real rows a, b (consecutive linear
@@ -147,29 +158,42 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
     const int row0 = blockIdx.x * kC2rRows;
     const int ncx = kC2rRows / 2;
     const int tot = ncx * Nx;
+    float2 *tw = lds + tot;
+    load_twiddles(tw, ax);
     const unsigned mN = div_magic(Nx);
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-        const int jr = udiv(i, Nx, mN), k = i - jr * Nx;
-        const int ra = row0 + 2 * jr;
-        float2 xa = make_float2(0.f, 0.f), xb = xa;
-        if (ra < nrows) {
-            const bool mirror = k > Nx / 2;
-            const int kk = mirror ? Nx - k : k;
-            xa = spec[(size_t)ra * H + kk];
-            xb = spec[(size_t)(ra + 1) * H + kk];
-            if (mirror) {
-                xa.y = -xa.y;
-                xb.y = -xb.y;
-            }
-            if (k == 0 || 2 * k == Nx) {
-                xa.y = 0.f;
-                xb.y = 0.f;
+    for (int base = 0; base < tot; base += kBatch * kPassThreads) {
+        float2 xa[kBatch], xb[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = base + u * kPassThreads + threadIdx.x;
+            const int jr = udiv(i, Nx, mN), k = i - jr * Nx;
+            const int ra = row0 + 2 * jr;
+            xa[u] = xb[u] = make_float2(0.f, 0.f);
+            if (i < tot && ra < nrows) {
+                const int kk = k > Nx / 2 ? Nx - k : k;
+                xa[u] = spec[(size_t)ra * H + kk];
+                xb[u] = spec[(size_t)(ra + 1) * H + kk];
             }
         }
-        lds[i] = make_float2(xa.x - xb.y, xa.y + xb.x);
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = base + u * kPassThreads + threadIdx.x;
+            if (i >= tot) continue;
+            const int jr = udiv(i, Nx, mN), k = i - jr * Nx;
+            float2 a = xa[u], b = xb[u];
+            if (k > Nx / 2) {
+                a.y = -a.y;
+                b.y = -b.y;
+            }
+            if (k == 0 || 2 * k == Nx) {
+                a.y = 0.f;
+                b.y = 0.f;
+            }
+            lds[i] = make_float2(a.x - b.y, a.y + b.x);
+        }
     }
     __syncthreads();
-    fft_rows<false>(RowsC{lds, Nx, 1}, ncx, ax, +1);
+    fft_rows<false>(RowsC{lds, Nx, 1}, ncx, ax, tw, +1);
     for (int i = threadIdx.x; i < tot; i += blockDim.x) {
         const int jr = udiv(i, Nx, mN), k = i - jr * Nx;
         const int ra = row0 + 2 * jr;
@@ -191,7 +215,8 @@ hipError_t fft_configure() {
     return hipSuccess;
 }
 
-static size_t pass_lds(int n, int bufs) { return (size_t)bufs * n * kChunk * sizeof(float2); }
+// pencil buffers plus the twiddle table
+static size_t pass_lds(int n, int bufs) { return ((size_t)bufs * n * kChunk + n) * sizeof(float2); }
 
 hipError_t launch_fft_y_fwd(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
@@ -216,7 +241,7 @@ hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const F
     const int nrows = g.n[1] * g.n[2];
     const int blocks = (nrows + kC2rRows - 1) / kC2rRows;
     const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
-    const size_t lds = (size_t)(kC2rRows / 2) * g.n[0] * sizeof(float2);
+    const size_t lds = ((size_t)(kC2rRows / 2) * g.n[0] + g.n[0]) * sizeof(float2);
     fft_x_c2r_kernel<<<dim3(blocks), dim3(kPassThreads), lds, s>>>(spec, A, g, ax, scale);
     return hipGetLastError();
 }

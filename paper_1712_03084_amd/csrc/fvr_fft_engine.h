@@ -187,22 +187,29 @@ __device__ __forceinline__ void fft_stage(const Acc &acc, int nrows, int n, int 
     __syncthreads();
 }
 
-// Transform all rows.  The caller has synchronised after filling the rows;
-// the rows are synchronised again on return.
+// Transform all rows.  The caller has synchronised after filling the rows
+// (and `tw`, normally an LDS copy of ax.tw); the rows are synchronised again
+// on return.
 template <bool ROW_FASTEST, class Acc>
-__device__ void fft_rows(const Acc &acc, int nrows, const FftAxis &ax, int dir) {
+__device__ void fft_rows(const Acc &acc, int nrows, const FftAxis &ax, const float2 *tw, int dir) {
     int ns = 1;
     for (int s = 0; s < ax.nstages; ++s) {
         const int R = ax.radix[s];
         switch (R) {
-            case 8: fft_stage<8, ROW_FASTEST>(acc, nrows, ax.n, ns, ax.tw, dir); break;
-            case 4: fft_stage<4, ROW_FASTEST>(acc, nrows, ax.n, ns, ax.tw, dir); break;
-            case 2: fft_stage<2, ROW_FASTEST>(acc, nrows, ax.n, ns, ax.tw, dir); break;
-            case 3: fft_stage<3, ROW_FASTEST>(acc, nrows, ax.n, ns, ax.tw, dir); break;
-            default: fft_stage<5, ROW_FASTEST>(acc, nrows, ax.n, ns, ax.tw, dir); break;
+            case 8: fft_stage<8, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
+            case 4: fft_stage<4, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
+            case 2: fft_stage<2, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
+            case 3: fft_stage<3, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
+            default: fft_stage<5, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
         }
         ns *= R;
     }
+}
+
+// Copy an axis's twiddle table (n <= 512 entries) into LDS; the caller
+// synchronises before use.
+__device__ __forceinline__ void load_twiddles(float2 *dst, const FftAxis &ax) {
+    for (int i = threadIdx.x; i < ax.n; i += blockDim.x) dst[i] = ax.tw[i];
 }
 
 // Signed wavenumber of DFT bin k of length n (the Nyquist bin n/2 maps to -n/2).

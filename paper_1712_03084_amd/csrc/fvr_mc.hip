@@ -30,7 +30,6 @@ constexpr int kMcPpt = 4;                       // grid points per thread
 constexpr int kMcPerBlock = kMcThreads * kMcPpt;
 constexpr int kLevelThreads = 256;
 constexpr int kLevelPpt = 4;
-constexpr int kScanThreads = 1024;
 
 // ---------------------------------------------------------------------------
 // Utilities
@@ -40,24 +39,29 @@ __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void reset_status_kernel(DevStatus *st) {
-    if (threadIdx.x == 0) {
+__global__ void prep_kernel(DevStatus *st, int32_t *bins, int nbins) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
         st->flags = 0;
         st->rejected = 0;
         st->mc_total[0] = st->mc_total[1] = st->mc_total[2] = 0;
         st->n_used = 0;
         st->level = 0.0;
+        st->wmax_bits = 0;
+        st->wnmax_bits = 0;
     }
+    if (bins && i < nbins) bins[i] = 0;
+}
+
+hipError_t launch_prep(DevStatus *st, int32_t *bins, int nbins, hipStream_t s) {
+    const int blocks = nbins > 0 ? (nbins + 255) / 256 : 1;
+    prep_kernel<<<dim3(blocks), dim3(256), 0, s>>>(st, bins, nbins);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     fill_i32_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_reset_status(DevStatus *st, hipStream_t s) {
-    reset_status_kernel<<<1, 64, 0, s>>>(st);
     return hipGetLastError();
 }
 
@@ -72,56 +76,107 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
-// Single-block exclusive scan of n items of C interleaved components.
+// Exclusive scan of n items of C interleaved components in two kernels:
+//   scan_reduce  block b sums items [b T, (b+1) T) -> partial[b]
+//   scan_down    block b adds partial[0..b) (at most a few hundred) and scans
+//                its tile; the last block also writes the totals.
+// Each thread owns kScanIpt consecutive items.
+constexpr int kScanBlock = 256;
+constexpr int kScanIpt = 8;
+constexpr int kScanTile = kScanBlock * kScanIpt;
+
 template <int C>
-__global__ void __launch_bounds__(kScanThreads)
-scan_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int n, int32_t *totals) {
-    __shared__ int wsum[C][kScanThreads / 64];
-    __shared__ int carry[C];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (threadIdx.x < C) carry[threadIdx.x] = 0;
-    __syncthreads();
-    for (int base = 0; base < n; base += blockDim.x) {
-        const int i = base + threadIdx.x;
-        int v[C], incl[C];
+__global__ void __launch_bounds__(kScanBlock)
+scan_reduce_kernel(const int32_t *__restrict__ in, int n, int32_t *__restrict__ partial) {
+    __shared__ int red[C][kScanBlock / 64];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
+    int s[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            v[c] = i < n ? in[(size_t)i * C + c] : 0;
-            incl[c] = wave_incl_scan(v[c]);
-            if (lane == 63) wsum[c][wid] = incl[c];
+    for (int c = 0; c < C; ++c) s[c] = 0;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j) {
+        const int i = base + j;
+        if (i < n) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] += in[(size_t)i * C + c];
         }
-        __syncthreads();
-        if (wid == 0) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int t = lane < nw ? wsum[c][lane] : 0;
-                const int ti = wave_incl_scan(t);
-                if (lane < nw) wsum[c][lane] = ti - t;  // exclusive wave offsets
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (i < n) out[(size_t)i * C + c] = carry[c] + wsum[c][wid] + incl[c] - v[c];
-        __syncthreads();
-        if (threadIdx.x == blockDim.x - 1) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) carry[c] += wsum[c][wid] + incl[c];
-        }
-        __syncthreads();
     }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        int v = s[c];
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0) red[c][wid] = v;
+    }
+    __syncthreads();
     if (threadIdx.x < C) {
-        out[(size_t)n * C + threadIdx.x] = carry[threadIdx.x];
-        if (totals) totals[threadIdx.x] = carry[threadIdx.x];
+        int t = 0;
+        for (int w = 0; w < kScanBlock / 64; ++w) t += red[threadIdx.x][w];
+        partial[blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
-hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *totals,
-                       hipStream_t s) {
-    if (C == 1)
-        scan_kernel<1><<<1, kScanThreads, 0, s>>>(in, out, n, totals);
-    else
-        scan_kernel<3><<<1, kScanThreads, 0, s>>>(in, out, n, totals);
+template <int C>
+__global__ void __launch_bounds__(kScanBlock)
+scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int n,
+                 const int32_t *__restrict__ partial, int32_t *totals) {
+    __shared__ int wsum[C][kScanBlock / 64];
+    __shared__ int boff[C];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x < C) {
+        int t = 0;
+        for (int b = 0; b < (int)blockIdx.x; ++b) t += partial[b * C + threadIdx.x];
+        boff[threadIdx.x] = t;
+    }
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
+    int v[kScanIpt][C], s[C], incl[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = 0;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j) {
+        const int i = base + j;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            v[j][c] = i < n ? in[(size_t)i * C + c] : 0;
+            s[c] += v[j][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        incl[c] = wave_incl_scan(s[c]);
+        if (lane == 63) wsum[c][wid] = incl[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        int run = boff[c] + incl[c] - s[c];
+        for (int w = 0; w < wid; ++w) run += wsum[c][w];
+#pragma unroll
+        for (int j = 0; j < kScanIpt; ++j) {
+            const int i = base + j;
+            if (i < n) out[(size_t)i * C + c] = run;
+            run += v[j][c];
+        }
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) {
+            out[(size_t)n * C + c] = run;
+            if (totals) totals[c] = run;
+        }
+    }
+}
+
+int scan_partials(int n) { return (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *partial,
+                       int32_t *totals, hipStream_t s) {
+    const int nb = n > 0 ? scan_partials(n) : 1;
+    if (C == 1) {
+        scan_reduce_kernel<1><<<nb, kScanBlock, 0, s>>>(in, n, partial);
+        scan_down_kernel<1><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
+    } else {
+        scan_reduce_kernel<3><<<nb, kScanBlock, 0, s>>>(in, n, partial);
+        scan_down_kernel<3><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
+    }
     return hipGetLastError();
 }
 
@@ -191,7 +246,7 @@ level_partial_kernel(const float *__restrict__ pts, int m, const float *__restri
 
 __global__ void __launch_bounds__(kLevelThreads)
 level_final_kernel(const double *__restrict__ psum, const int32_t *__restrict__ pcnt, int nb,
-                   DevStatus *st) {
+                   DevStatus *st, float *level_f32) {
     __shared__ double ssum[kLevelThreads];
     __shared__ int scnt[kLevelThreads];
     double sum = 0.0, comp = 0.0;
@@ -214,31 +269,24 @@ level_final_kernel(const double *__restrict__ psum, const int32_t *__restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        const double L = scnt[0] > 0 ? ssum[0] / (double)scnt[0] : 0.0;
         st->n_used = scnt[0];
-        st->level = scnt[0] > 0 ? ssum[0] / (double)scnt[0] : 0.0;
+        st->level = L;
+        *level_f32 = (float)L;
     }
 }
 
 int level_blocks(int m) { return (m + kLevelThreads * kLevelPpt - 1) / (kLevelThreads * kLevelPpt); }
 
 hipError_t launch_level(const float *pts, int m, const float *A, const Grid &g, double *psum,
-                        int32_t *pcnt, DevStatus *st, hipStream_t s) {
+                        int32_t *pcnt, DevStatus *st, float *level_f32, hipStream_t s) {
     const int nb = level_blocks(m);
     if (nb > 0) {
         level_partial_kernel<<<dim3(nb), dim3(kLevelThreads), 0, s>>>(pts, m, A, g, psum, pcnt);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    level_final_kernel<<<1, kLevelThreads, 0, s>>>(psum, pcnt, nb, st);
-    return hipGetLastError();
-}
-
-__global__ void level_to_f32_kernel(const DevStatus *st, float *lf) {
-    if (threadIdx.x == 0) *lf = (float)st->level;
-}
-
-hipError_t launch_level_to_f32(const DevStatus *st, float *level_f32, hipStream_t s) {
-    level_to_f32_kernel<<<1, 64, 0, s>>>(st, level_f32);
+    level_final_kernel<<<1, kLevelThreads, 0, s>>>(psum, pcnt, nb, st, level_f32);
     return hipGetLastError();
 }
 
@@ -307,22 +355,24 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
         size_t r = l0 / g.n[0];
         int qy = (int)(r % g.n[1]);
         int qz = (int)(r / g.n[1]);
+#pragma unroll
         for (int i = 0; i < kMcPpt; ++i) {
             const size_t l = l0 + i;
-            if (l >= n) break;
-            int eb, cs;
-            mc_point(A, g, qx, qy, qz, l, L, eb, cs);
-            nv += __popc(eb);
-            if (cs >= 0) {
-                const int c = c_mc_count[cs];
-                nt += c;
-                na += c > 0;
-                if (cases_out)
-                    cases_out[qx + (size_t)(g.n[0] - 1) * (qy + (size_t)(g.n[1] - 1) * qz)] = (uint8_t)cs;
+            if (l < n) {
+                int eb, cs;
+                mc_point(A, g, qx, qy, qz, l, L, eb, cs);
+                nv += __popc(eb);
+                if (cs >= 0) {
+                    const int c = c_mc_count[cs];
+                    nt += c;
+                    na += c > 0;
+                    if (cases_out)
+                        cases_out[qx + (size_t)(g.n[0] - 1) * (qy + (size_t)(g.n[1] - 1) * qz)] = (uint8_t)cs;
+                }
+                const bool border = qx == 0 || qy == 0 || qz == 0 || qx == g.n[0] - 1 ||
+                                    qy == g.n[1] - 1 || qz == g.n[2] - 1;
+                if (border && A[l] > L) open = true;
             }
-            const bool border = qx == 0 || qy == 0 || qz == 0 || qx == g.n[0] - 1 ||
-                                qy == g.n[1] - 1 || qz == g.n[2] - 1;
-            if (border && A[l] > L) open = true;
             if (++qx == g.n[0]) {
                 qx = 0;
                 if (++qy == g.n[1]) {

@@ -23,7 +23,8 @@
 
 namespace fvr {
 
-constexpr int kSplatThreads = 256;
+constexpr int kSplatThreads = 512;
+constexpr int kSplatMaxPlane = 4096;  // voxels per channel plane of a tile, at most
 constexpr int kMaxSegs = 16;
 
 // Footprint origin floor((x - bmin)/h - 1/2) in float32, each operation
@@ -42,33 +43,74 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
                  const float *__restrict__ w, int m, Grid g, int32_t *__restrict__ bin_count,
                  int32_t *__restrict__ key, int32_t *__restrict__ rank, DevStatus *st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     bool bad = false, rej = false;
+    int k = -1;
+    float wmax = 0.0f, wnmax = 0.0f;
     if (i < m) {
         const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+        const float nx = nrm[3 * i], ny = nrm[3 * i + 1], nz = nrm[3 * i + 2];
         const float wi = w ? w[i] : 1.0f;
-        bad = !(finite3(x, y, z) && finite3(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]) &&
-                isfinite(wi) && wi >= 0.0f);
-        int k = -1;
+        bad = !(finite3(x, y, z) && finite3(nx, ny, nz) && isfinite(wi) && wi >= 0.0f);
         if (!bad) {
             const bool acc = x >= g.bmin[0] && x <= g.bmax[0] && y >= g.bmin[1] &&
                              y <= g.bmax[1] && z >= g.bmin[2] && z <= g.bmax[2];
             if (acc) {
+                wmax = wi;
+                wnmax = wi * fmaxf(fabsf(nx), fmaxf(fabsf(ny), fabsf(nz)));
                 int iy = (int)floorf(voxel_coord(y, g.bmin[1], g.h[1]));
                 int iz = (int)floorf(voxel_coord(z, g.bmin[2], g.h[2]));
                 iy = min(max(iy, -1), g.n[1] - 1);
                 iz = min(max(iz, -1), g.n[2] - 1);
                 k = (iz + 1) * (g.n[1] + 1) + (iy + 1);
-                rank[i] = atomicAdd(&bin_count[k], 1);
             } else {
                 rej = true;
             }
         }
+    }
+    // Wave-aggregated histogram: points arrive in capture (scanline) order, so
+    // a wave holds few distinct bins; one atomic per distinct bin, and each
+    // lane's rank is the group's base plus its position within the group.
+    unsigned long long todo = __ballot(k >= 0);
+    int myrank = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int lk = __shfl(k, leader, 64);
+        const unsigned long long grp = __ballot(k == lk);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&bin_count[lk], __popcll(grp));
+        base = __shfl(base, leader, 64);
+        if (k == lk) myrank = base + __popcll(grp & ((1ull << lane) - 1ull));
+        todo &= ~grp;
+    }
+    if (i < m) {
         key[i] = k;
+        if (k >= 0) rank[i] = myrank;
     }
     const unsigned long long brej = __ballot(rej), bbad = __ballot(bad);
-    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
+        wnmax = fmaxf(wnmax, __shfl_xor(wnmax, d, 64));
+    }
+    __shared__ float red[2][4];
+    const int wid = threadIdx.x >> 6;
+    if (lane == 0) {
         if (brej) atomicAdd(&st->rejected, (uint32_t)__popcll(brej));
         if (bbad) atomicOr(&st->flags, kFlagInvalid);
+        red[0][wid] = wmax;
+        red[1][wid] = wnmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // one atomic per block, and none once a larger maximum is published;
+        // non-negative floats order like their bit patterns
+        const float bw = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+        const float bn = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+        const uint32_t cw = __hip_atomic_load(&st->wmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t cn = __hip_atomic_load(&st->wnmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__float_as_uint(bw) > cw) atomicMax(&st->wmax_bits, __float_as_uint(bw));
+        if (__float_as_uint(bn) > cn) atomicMax(&st->wnmax_bits, __float_as_uint(bn));
     }
 }
 
@@ -87,10 +129,19 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
     rec[2 * pos + 1] = make_float4(wi * nrm[3 * i], wi * nrm[3 * i + 1], wi * nrm[3 * i + 2], 0.0f);
 }
 
+// Accumulation is in 64-bit fixed point with integer LDS atomics (gfx950's
+// LDS float atomics run ~30x slower than its integer ones).  Every term
+// g W N_c (or g W for D) is rounded to an int32 count of a power-of-two unit
+// chosen per frame from the largest |W N_c| (or W), so |term| < 2^30 units
+// and an int64 voxel sum cannot overflow for fewer than 2^31 points.  The sums
+// are exact, hence independent of the order of the additions: the splat is
+// bit-reproducible.  V = (sigma2/sigma1) (S unit_S) / (D unit_D).
+template <bool CHUNKED>
 __global__ void __launch_bounds__(kSplatThreads)
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
-                   SplatConsts sc, FftAxis ax, float2 *__restrict__ spec, float *__restrict__ v_out) {
-    extern __shared__ float smem[];
+                   SplatConsts sc, FftAxis ax, const DevStatus *__restrict__ st,
+                   float2 *__restrict__ spec, float *__restrict__ v_out) {
+    extern __shared__ unsigned long long acc[];
     __shared__ int seg_start[kMaxSegs];
     __shared__ int seg_pre[kMaxSegs + 1];
 
@@ -98,11 +149,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     const int TY = sc.ty, TZ = sc.tz, R = TY * TZ;
     const int by = blockIdx.x % sc.tiles_y, bz = blockIdx.x / sc.tiles_y;
     const int y0 = by * TY, z0 = bz * TZ;
-    const int plane = R * Nx;            // floats per channel plane
-    float *S = smem;                     // 3 planes: S_x, S_y, S_z, then D
-    float *D = smem + 3 * plane;
-
-    for (int i = threadIdx.x; i < 4 * plane; i += blockDim.x) smem[i] = 0.0f;
+    const int plane = R * Nx;  // voxels per channel plane
 
     // candidate points: bins of footprint origins (iy, iz) whose 4-row
     // footprints overlap the tile, i.e. iy in [y0-2, y0+TY], iz in [z0-2, z0+TZ]
@@ -123,12 +170,70 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     }
     __syncthreads();
     const int total = seg_pre[nseg];
+    const int H = g.H;
+    const size_t pl = (size_t)Nz * Ny * H;
+    if (total == 0) {
+        // no point reaches this tile: V = 0 and so is its spectrum
+        for (int i = threadIdx.x; i < 3 * R * H; i += blockDim.x) {
+            const int rr = i / H, k = i - rr * H;
+            const int c = rr / R, r = rr - c * R;
+            const int y = y0 + r % TY, z = z0 + r / TY;
+            if (y < Ny && z < Nz) spec[c * pl + ((size_t)z * Ny + y) * H + k] = make_float2(0.f, 0.f);
+        }
+        if (v_out) {
+            const size_t n = (size_t)Nx * Ny * Nz;
+            for (int i = threadIdx.x; i < 3 * plane; i += blockDim.x) {
+                const int c = i / plane, l = i - c * plane;
+                const int row = l / Nx, qx = l - row * Nx;
+                const int qy = y0 + row % TY, qz = z0 + row / TY;
+                if (qy < Ny && qz < Nz) v_out[c * n + qx + (size_t)Nx * (qy + (size_t)Ny * qz)] = 0.f;
+            }
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < 4 * plane; i += blockDim.x) acc[i] = 0ull;
+    float2 *twl = reinterpret_cast<float2 *>(acc + 4 * plane);
+    load_twiddles(twl, ax);
 
-    for (int j = threadIdx.x; j < total; j += blockDim.x) {
+    // fixed-point units: 2^(e-30) with max < 2^e, so every rounded term fits int32
+    int eS, eD;
+    (void)frexpf(__uint_as_float(st->wnmax_bits), &eS);
+    (void)frexpf(__uint_as_float(st->wmax_bits), &eD);
+    const float qS = ldexpf(1.0f, 30 - eS), qD = ldexpf(1.0f, 30 - eD);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    const int chunk = (total + 63) / 64;
+    // candidate of this thread's k-th iteration, or -1 when it has no more
+    auto cand = [&](int k) -> int {
+        int j;
+        if (CHUNKED) {
+            // lane l owns candidates [l chunk, (l+1) chunk); the waves interleave
+            const int kk = wv + k * nwv;
+            if (kk >= chunk) return -1;
+            j = lane * chunk + kk;
+        } else {
+            j = k * (int)blockDim.x + threadIdx.x;
+        }
+        if (j >= total) return -1;
         int s = 0;
         while (seg_pre[s + 1] <= j) ++s;
-        const int p = seg_start[s] + (j - seg_pre[s]);
-        const float4 r0 = rec[2 * p], r1 = rec[2 * p + 1];
+        return seg_start[s] + (j - seg_pre[s]);
+    };
+
+    int p = cand(0), k = 0;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+    if (p >= 0) {
+        r0 = rec[2 * p];
+        r1 = rec[2 * p + 1];
+    }
+    while (p >= 0) {
+        const int pn = cand(k + 1);
+        float4 n0 = r0, n1 = r1;
+        if (pn >= 0) {  // prefetch the next record while this one is splatted
+            n0 = rec[2 * pn];
+            n1 = rec[2 * pn + 1];
+        }
         const float X[3] = {r0.x, r0.y, r0.z};
         float v[3];
         int i0[3];
@@ -150,6 +255,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
             wz1[o] = __builtin_amdgcn_exp2f(sc.e1[2] * dz * dz);
             wz2[o] = __builtin_amdgcn_exp2f(sc.e2[2] * dz * dz);
         }
+        const float nxq = r1.x * qS, nyq = r1.y * qS, nzq = r1.z * qS, wq = r0.w * qD;
 #pragma unroll
         for (int oz = 0; oz < 4; ++oz) {
             const int qz = i0[2] + oz - 1;
@@ -166,33 +272,61 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
                     if (qx < 0 || qx >= Nx) continue;
                     const int l = row * Nx + qx;
                     const float g1 = wx1[ox] * a1;
-                    atomicAdd(&S[l], g1 * r1.x);
-                    atomicAdd(&S[plane + l], g1 * r1.y);
-                    atomicAdd(&S[2 * plane + l], g1 * r1.z);
-                    atomicAdd(&D[l], wx2[ox] * a2 * r0.w);
+                    atomicAdd(&acc[l], (unsigned long long)(long long)__float2int_rn(g1 * nxq));
+                    atomicAdd(&acc[plane + l], (unsigned long long)(long long)__float2int_rn(g1 * nyq));
+                    atomicAdd(&acc[2 * plane + l], (unsigned long long)(long long)__float2int_rn(g1 * nzq));
+                    atomicAdd(&acc[3 * plane + l],
+                              (unsigned long long)(long long)__float2int_rn(wx2[ox] * a2 * wq));
                 }
+            }
+        }
+        r0 = n0;
+        r1 = n1;
+        p = pn;
+        ++k;
+    }
+    __syncthreads();
+
+    // V = (sigma2/sigma1) (S / qS) / (D / qD), 0 where D = 0; converted in
+    // registers first, then written as float planes over the front of the
+    // accumulator buffer (the float rows overlap int64 slots still unread by
+    // other threads, hence the barrier in between)
+    constexpr int kVpt = kSplatMaxPlane / kSplatThreads;
+    float vv[kVpt][3];
+    const float ratio = sc.vscale * (qD / qS);
+#pragma unroll
+    for (int t = 0; t < kVpt; ++t) {
+        const int l = threadIdx.x + t * blockDim.x;
+        vv[t][0] = vv[t][1] = vv[t][2] = 0.f;
+        if (l < plane) {
+            const long long d = (long long)acc[3 * plane + l];
+            if (d > 0) {
+                const float inv = ratio / (float)d;
+                vv[t][0] = (float)(long long)acc[l] * inv;
+                vv[t][1] = (float)(long long)acc[plane + l] * inv;
+                vv[t][2] = (float)(long long)acc[2 * plane + l] * inv;
             }
         }
     }
     __syncthreads();
-
-    // V = (sigma2/sigma1) S' / D' (the Gaussians' 1/sigma prefactors), 0 where D = 0
-    for (int l = threadIdx.x; l < plane; l += blockDim.x) {
-        const float d = D[l];
-        const float inv = d > 0.0f ? sc.vscale / d : 0.0f;
-        const float vx = S[l] * inv, vy = S[plane + l] * inv, vz = S[2 * plane + l] * inv;
-        S[l] = vx;
-        S[plane + l] = vy;
-        S[2 * plane + l] = vz;
-        if (v_out) {
-            const int row = l / Nx, qx = l - row * Nx;
-            const int qy = y0 + row % TY, qz = z0 + row / TY;
-            if (qy < Ny && qz < Nz) {
-                const size_t n = (size_t)Nx * Ny * Nz;
-                const size_t o = qx + (size_t)Nx * (qy + (size_t)Ny * qz);
-                v_out[o] = vx;
-                v_out[n + o] = vy;
-                v_out[2 * n + o] = vz;
+    float *S = reinterpret_cast<float *>(acc);
+    const size_t n = (size_t)Nx * Ny * Nz;
+#pragma unroll
+    for (int t = 0; t < kVpt; ++t) {
+        const int l = threadIdx.x + t * blockDim.x;
+        if (l < plane) {
+            S[l] = vv[t][0];
+            S[plane + l] = vv[t][1];
+            S[2 * plane + l] = vv[t][2];
+            if (v_out) {
+                const int row = l / Nx, qx = l - row * Nx;
+                const int qy = y0 + row % TY, qz = z0 + row / TY;
+                if (qy < Ny && qz < Nz) {
+                    const size_t o = qx + (size_t)Nx * (qy + (size_t)Ny * qz);
+                    v_out[o] = vv[t][0];
+                    v_out[n + o] = vv[t][1];
+                    v_out[2 * n + o] = vv[t][2];
+                }
             }
         }
     }
@@ -201,41 +335,46 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     // Real FFT along x: real rows (2j, 2j+1) of the flat (channel, row) order
     // - always the same channel since R is even - form complex row j.
     const int ncx = 3 * R / 2;
-    fft_rows<false>(RowsS{S, 2 * Nx, Nx}, ncx, ax, -1);
+    fft_rows<false>(RowsS{S, 2 * Nx, Nx}, ncx, ax, twl, -1);
 
     // Unpack X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = (Z[k] - conj Z[N-k]) / 2i,
     // k = 0..Nx/2, and store; the x component is multiplied by j w_x.
-    const int H = g.H;
     const unsigned mH = div_magic(H);
-    const size_t pl = (size_t)Nz * Ny * H;
     for (int i = threadIdx.x; i < ncx * H; i += blockDim.x) {
-        const int jr = udiv(i, H, mH), k = i - jr * H;
+        const int jr = udiv(i, H, mH), kx = i - jr * H;
         const float *re = S + 2 * jr * Nx, *im = re + Nx;
-        const int km = k == 0 ? 0 : Nx - k;
-        const float zr = re[k == Nx ? 0 : k], zi = im[k == Nx ? 0 : k];
+        const int km = kx == 0 ? 0 : Nx - kx;
+        const float zr = re[kx], zi = im[kx];
         const float mr = re[km], mi = im[km];
         float2 xa = make_float2(0.5f * (zr + mr), 0.5f * (zi - mi));
         float2 xb = make_float2(0.5f * (zi + mi), 0.5f * (mr - zr));
         const int ra = (2 * jr) % R, c = (2 * jr) / R;
         if (c == 0) {
-            const float wx = deriv_w(k, Nx, g.wstep[0]);
+            const float wx = deriv_w(kx, Nx, g.wstep[0]);
             xa = make_float2(-wx * xa.y, wx * xa.x);
             xb = make_float2(-wx * xb.y, wx * xb.x);
         }
         const int ya = y0 + ra % TY, za = z0 + ra / TY;
         const int yb = y0 + (ra + 1) % TY, zb = z0 + (ra + 1) / TY;
-        if (ya < Ny && za < Nz) spec[c * pl + ((size_t)za * Ny + ya) * H + k] = xa;
-        if (yb < Ny && zb < Nz) spec[c * pl + ((size_t)zb * Ny + yb) * H + k] = xb;
+        if (ya < Ny && za < Nz) spec[c * pl + ((size_t)za * Ny + ya) * H + kx] = xa;
+        if (yb < Ny && zb < Nz) spec[c * pl + ((size_t)zb * Ny + yb) * H + kx] = xb;
     }
 }
 
+#ifndef FVR_SPLAT_CHUNKED
+#define FVR_SPLAT_CHUNKED true
+#endif
+
 hipError_t splat_configure() {
-    return hipFuncSetAttribute((const void *)splat_fft_x_kernel,
+    hipError_t e = hipFuncSetAttribute((const void *)splat_fft_x_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)splat_fft_x_kernel<false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
 }
 
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
-    return (size_t)4 * sc.ty * sc.tz * g.n[0] * sizeof(float);
+    return (size_t)4 * sc.ty * sc.tz * g.n[0] * sizeof(unsigned long long) + g.n[0] * sizeof(float2);
 }
 
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
@@ -257,12 +396,12 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 }
 
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
-                              const SplatConsts &sc, const FftAxis &ax, float2 *spec,
-                              float *v_out, hipStream_t s) {
+                              const SplatConsts &sc, const FftAxis &ax, const DevStatus *st,
+                              float2 *spec, float *v_out, hipStream_t s) {
     const int tiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     const size_t lds = splat_lds_bytes(g, sc);
-    splat_fft_x_kernel<<<dim3(tiles), dim3(kSplatThreads), lds, s>>>(rec, bin_off, g, sc, ax, spec,
-                                                                     v_out);
+    splat_fft_x_kernel<FVR_SPLAT_CHUNKED><<<dim3(tiles), dim3(kSplatThreads), lds, s>>>(
+        rec, bin_off, g, sc, ax, st, spec, v_out);
     return hipGetLastError();
 }
 

@@ -66,6 +66,22 @@ def frame_alg_bytes(dims, m, nv, nt):
     return 8 * F + 8 * S + 40 * m + 12 * nv + 12 * nt
 
 
+def _load_frame(synth, config, seed, cache):
+    """Generate a seeded frame, or reuse a copy saved by an earlier run."""
+    import numpy as np
+    path = os.path.join(cache, f"{config}_{seed}.npz") if cache else None
+    if path and os.path.exists(path):
+        z = np.load(path)
+        return synth.Frame(z["points"], z["normals"], z["weights"], tuple(int(x) for x in z["dims"]),
+                           tuple(float(x) for x in z["bbox"]), name=f"{config}_{seed}")
+    f = synth.config_frame(config, seed=seed)
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        np.savez(path, points=f.points, normals=f.normals, weights=f.weights,
+                 dims=np.asarray(f.dims), bbox=np.asarray(f.bbox))
+    return f
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +91,11 @@ def main():
     ap.add_argument("--pool", type=int, default=2, help="distinct seeded frames cycled through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="before the timed region, copy a 256 MiB float32 buffer once (a plain copy "
+                         "kernel of known size, for scaling profiler byte counters)")
+    ap.add_argument("--cache", default=None,
+                    help="directory to keep generated frames in (.npz), reused on later runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the frame-parallel "
@@ -89,7 +110,7 @@ def main():
 
     print(f"[bench] generating {args.pool} frame(s) of {args.config}", file=sys.stderr, flush=True)
     base_seed = synth.CONFIGS[args.config]["seed"]
-    frames = [synth.config_frame(args.config, seed=base_seed + i) for i in range(args.pool)]
+    frames = [_load_frame(synth, args.config, base_seed + i, args.cache) for i in range(args.pool)]
     dev = torch.device("cuda:0")
     pool = [tuple(torch.from_numpy(a).to(dev) for a in (f.points, f.normals, f.weights))
             for f in frames]
@@ -99,6 +120,14 @@ def main():
     vcap = 2_000_000
     out = (torch.empty((vcap, 3), dtype=torch.float32, device=dev),
            torch.empty((2 * vcap, 3), dtype=torch.int32, device=dev))
+
+    if args.calib_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     print("[bench] warmup", file=sys.stderr, flush=True)
     for k in range(args.warmup):

@@ -195,6 +195,7 @@ Grid make_grid(const int32_t dims[3], const float bbox[6]) {
         g.wstep[a] = (float)(2.0 * M_PI / ((double)bbox[a + 3] - (double)bbox[a]));
     }
     g.H = dims[0] / 2 + 1;
+    g.Hp = (g.H + 15) / 16 * 16;
     return g;
 }
 
@@ -267,7 +268,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g, flo
                      float *v_out, bool splat_only) {
     const int m = (int)f->n_points;
     const int nbins = (g.n[2] + 1) * (g.n[1] + 1);
-    const size_t nspec = (size_t)g.n[2] * g.n[1] * g.H;
+    const size_t nspec = (size_t)g.n[2] * g.n[1] * g.Hp;
     HIP_TRY(c, ensure(c->bin_count, sizeof(int32_t) * nbins), "alloc bins");
     HIP_TRY(c, ensure(c->bin_off, sizeof(int32_t) * (nbins + 1)), "alloc bin offsets");
     HIP_TRY(c, ensure(c->key, sizeof(int32_t) * (size_t)m), "alloc keys");
@@ -288,7 +289,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g, flo
       HIP_TRY(c, launch_scan(P<int32_t>(c->bin_count), P<int32_t>(c->bin_off), nbins, 1,
                              P<int32_t>(c->scan_part), nullptr, s), "bin_scan"); }
     { Timed t(c, K_BIN_SCATTER);
-      HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, P<int32_t>(c->key),
+      HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, g, P<int32_t>(c->key),
                                     P<int32_t>(c->rank), P<int32_t>(c->bin_off), P<float4>(c->rec), s),
               "bin_scatter"); }
     { Timed t(c, K_SPLAT_FFT_X);

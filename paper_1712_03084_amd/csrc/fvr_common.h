@@ -11,7 +11,16 @@ constexpr int kMaxDim = 512;
 constexpr int kMaxStages = 8;
 constexpr int kMcMaxTris = 5;         // triangles per marching-cubes case, at most
 constexpr int kMcRow = 3 * kMcMaxTris;
-constexpr int kMaxDynLds = 160 * 1024 - 4096;  // gfx950: 160 KiB of LDS per workgroup
+constexpr int kLdsPerWorkgroup = 160 * 1024;  // gfx950: 160 KiB of LDS per workgroup
+
+// Allow a kernel all LDS beyond its static allocation as dynamic LDS.
+inline hipError_t raise_dynamic_lds(const void *kernel) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, kernel);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kLdsPerWorkgroup - (int)a.sharedSizeBytes);
+}
 
 // One axis of the 3D FFT: length n = prod(radix[0..nstages)), radices from
 // {2, 3, 4, 5, 8}; tw[t] = exp(-2 pi i t / n) for t < n, float32 values
@@ -27,6 +36,7 @@ struct FftAxis {
 struct Grid {
     int n[3];          // Nx, Ny, Nz
     int H;             // Nx/2 + 1: length of a half-spectrum row
+    int Hp;            // row pitch of the spectrum planes: H rounded up to 16 (128-byte rows)
     float bmin[3];
     float bmax[3];
     float h[3];        // (bmax - bmin) / N, float32
@@ -79,10 +89,11 @@ hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *p
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
                             const Grid &g, int32_t *bin_count, int32_t *key, int32_t *rank,
                             DevStatus *st, hipStream_t s);
-// Splat, stage 2: scatter packed records (x, y, z, W, W*N) into bin order.
+// Splat, stage 2: scatter packed records (fractional voxel offsets, W, W N,
+// x footprint origin) into bin order.
 hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
-                              const int32_t *key, const int32_t *rank, const int32_t *bin_off,
-                              float4 *rec, hipStream_t s);
+                              const Grid &g, const int32_t *key, const int32_t *rank,
+                              const int32_t *bin_off, float4 *rec, hipStream_t s);
 // Splat, stage 3 fused with the forward real FFT along x: each block owns
 // ty x tz full x-rows, accumulates S_x, S_y, S_z and D in LDS (64-bit fixed
 // point, scaled per frame from st->wmax_bits / wnmax_bits), forms

@@ -26,56 +26,76 @@ namespace fvr {
 constexpr int kChunk = 16;
 constexpr int kPassThreads = 256;
 constexpr int kC2rRows = 16;   // real rows per C2R block (pairs -> 8 complex rows)
-constexpr int kBatch = 8;      // global loads kept in flight per thread
+constexpr int kBatch = 8;      // 16-byte global loads kept in flight per thread
 
 __device__ __forceinline__ int nchunks(int H) { return (H + kChunk - 1) / kChunk; }
 
-// Stage a [len][kChunk] pencil tile of one spectrum plane into LDS: element
-// (t, c) from src[t * stride + kx0 + c], zero for kx0 + c >= H.  Loads are
-// issued kBatch at a time into registers before any LDS store, so each
-// thread keeps several global loads in flight instead of one.
-__device__ __forceinline__ void load_pencils(float2 *dst, const float2 *__restrict__ src,
-                                             size_t stride, int len, int kx0, int H) {
-    const int tot = len * kChunk;
-    for (int base = 0; base < tot; base += kBatch * kPassThreads) {
-        float2 v[kBatch];
+// Pencil tiles.  A tile is [len][kChunk] complex values of one spectrum
+// plane, element (t, c) at src[t * stride + kx0 + c] (zero for kx0 + c >= H);
+// rows are 128-byte aligned (stride and kx0 are multiples of 16), so a thread
+// moves two complex values per 16-byte access.  prefetch() issues all of a
+// thread's loads of one tile (PF = len * kChunk / 2 / kPassThreads of them)
+// into registers; commit() writes them to LDS.  Issuing the loads of two or
+// three tiles before the first commit keeps one memory round trip per block.
+template <int PF>
+__device__ __forceinline__ void prefetch(float4 (&v)[PF], const float2 *__restrict__ src,
+                                         size_t stride, int len, int kx0, int H) {
+    const int tot2 = len * (kChunk / 2);
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int i = base + u * kPassThreads + threadIdx.x;
-            const int t = i / kChunk, c = i % kChunk;
-            v[u] = (i < tot && kx0 + c < H) ? src[t * stride + kx0 + c] : make_float2(0.f, 0.f);
+    for (int u = 0; u < PF; ++u) {
+        const int i = u * kPassThreads + threadIdx.x;
+        const int t = i / (kChunk / 2), c = 2 * (i % (kChunk / 2));
+        v[u] = (i < tot2 && kx0 + c < H) ? *reinterpret_cast<const float4 *>(src + t * stride + kx0 + c)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (kx0 + c + 1 >= H) {  // the pair's second column is row padding
+            v[u].z = 0.f;
+            v[u].w = 0.f;
         }
+    }
+}
+
+template <int PF>
+__device__ __forceinline__ void commit(float2 *dst, const float4 (&v)[PF], int len) {
+    const int tot2 = len * (kChunk / 2);
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int i = base + u * kPassThreads + threadIdx.x;
-            if (i < tot) dst[i] = v[u];
-        }
+    for (int u = 0; u < PF; ++u) {
+        const int i = u * kPassThreads + threadIdx.x;
+        if (i < tot2) reinterpret_cast<float4 *>(dst)[i] = v[u];
     }
 }
 
 __device__ __forceinline__ void store_pencils(float2 *__restrict__ dstg, const float2 *src,
                                               size_t stride, int len, int kx0, int H) {
-    const int tot = len * kChunk;
-    for (int i = threadIdx.x; i < tot; i += kPassThreads) {
-        const int t = i / kChunk, c = i % kChunk;
-        if (kx0 + c < H) dstg[t * stride + kx0 + c] = src[i];
+    const int tot2 = len * (kChunk / 2);
+    for (int i = threadIdx.x; i < tot2; i += kPassThreads) {
+        const int t = i / (kChunk / 2), c = 2 * (i % (kChunk / 2));
+        const float4 v = reinterpret_cast<const float4 *>(src)[i];
+        if (kx0 + c + 1 < H)
+            *reinterpret_cast<float4 *>(dstg + t * stride + kx0 + c) = v;
+        else if (kx0 + c < H)
+            dstg[t * stride + kx0 + c] = make_float2(v.x, v.y);
     }
 }
 
+template <int PF>
 __global__ void __launch_bounds__(kPassThreads)
 fft_y_fwd_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
-    extern __shared__ float2 lds[];
-    const int Ny = g.n[1], H = g.H;
-    const size_t plane = (size_t)g.n[2] * Ny * H;
+    extern __shared__ __attribute__((aligned(16))) float2 lds[];
+    const int Ny = g.n[1], H = g.H, Hp = g.Hp;
+    const size_t plane = (size_t)g.n[2] * Ny * Hp;
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
     float2 *A = lds, *B = lds + Ny * kChunk, *tw = lds + 2 * Ny * kChunk;
     const int tot = Ny * kChunk;
-    const size_t zoff = (size_t)z * Ny * H;
+    const size_t zoff = (size_t)z * Ny * Hp;
+    float4 va[PF], vb[PF], vc[PF];
+    prefetch<PF>(va, spec + zoff, Hp, Ny, k0, H);
+    prefetch<PF>(vb, spec + plane + zoff, Hp, Ny, k0, H);
     load_twiddles(tw, ay);
-    load_pencils(A, spec + zoff, H, Ny, k0, H);
-    load_pencils(B, spec + plane + zoff, H, Ny, k0, H);
+    commit<PF>(A, va, Ny);
+    commit<PF>(B, vb, Ny);
+    prefetch<PF>(vc, spec + 2 * plane + zoff, Hp, Ny, k0, H);  // in flight during the transforms
     __syncthreads();
     fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, ay, tw, -1);
     fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, tw, -1);
@@ -86,28 +106,32 @@ fft_y_fwd_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
         A[i] = make_float2(A[i].x - w * b.y, A[i].y + w * b.x);
     }
     __syncthreads();
-    store_pencils(spec + zoff, A, H, Ny, k0, H);
-    load_pencils(B, spec + 2 * plane + zoff, H, Ny, k0, H);
+    store_pencils(spec + zoff, A, Hp, Ny, k0, H);
+    commit<PF>(B, vc, Ny);
     __syncthreads();
     fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, tw, -1);
-    store_pencils(spec + 2 * plane + zoff, B, H, Ny, k0, H);
+    store_pencils(spec + 2 * plane + zoff, B, Hp, Ny, k0, H);
 }
 
+template <int PF>
 __global__ void __launch_bounds__(kPassThreads)
 fft_z_solve_kernel(float2 *__restrict__ spec, Grid g, FftAxis az) {
-    extern __shared__ float2 lds[];
-    const int Ny = g.n[1], Nz = g.n[2], H = g.H;
-    const size_t plane = (size_t)Nz * Ny * H;
-    const size_t zstride = (size_t)Ny * H;
+    extern __shared__ __attribute__((aligned(16))) float2 lds[];
+    const int Ny = g.n[1], Nz = g.n[2], H = g.H, Hp = g.Hp;
+    const size_t plane = (size_t)Nz * Ny * Hp;
+    const size_t zstride = (size_t)Ny * Hp;
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
     float2 *A = lds, *B = lds + Nz * kChunk, *tw = lds + 2 * Nz * kChunk;
     const int tot = Nz * kChunk;
-    const size_t yoff = (size_t)ky * H;
+    const size_t yoff = (size_t)ky * Hp;
+    float4 va[PF], vb[PF];
+    prefetch<PF>(va, spec + yoff, zstride, Nz, k0, H);
+    prefetch<PF>(vb, spec + 2 * plane + yoff, zstride, Nz, k0, H);
     load_twiddles(tw, az);
-    load_pencils(A, spec + yoff, zstride, Nz, k0, H);
-    load_pencils(B, spec + 2 * plane + yoff, zstride, Nz, k0, H);
+    commit<PF>(A, va, Nz);
+    commit<PF>(B, vb, Nz);
     __syncthreads();
     fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, tw, -1);
     fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, az, tw, -1);
@@ -128,20 +152,23 @@ fft_z_solve_kernel(float2 *__restrict__ spec, Grid g, FftAxis az) {
     store_pencils(spec + yoff, A, zstride, Nz, k0, H);
 }
 
+template <int PF>
 __global__ void __launch_bounds__(kPassThreads)
 fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
-    extern __shared__ float2 lds[];
-    const int Ny = g.n[1], H = g.H;
+    extern __shared__ __attribute__((aligned(16))) float2 lds[];
+    const int Ny = g.n[1], H = g.H, Hp = g.Hp;
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
-    const size_t zoff = (size_t)z * Ny * H;
+    const size_t zoff = (size_t)z * Ny * Hp;
     float2 *tw = lds + Ny * kChunk;
+    float4 va[PF];
+    prefetch<PF>(va, spec + zoff, Hp, Ny, k0, H);
     load_twiddles(tw, ay);
-    load_pencils(lds, spec + zoff, H, Ny, k0, H);
+    commit<PF>(lds, va, Ny);
     __syncthreads();
     fft_rows<true>(RowsC{lds, 1, kChunk}, kChunk, ay, tw, +1);
-    store_pencils(spec + zoff, lds, H, Ny, k0, H);
+    store_pencils(spec + zoff, lds, Hp, Ny, k0, H);
 }
 
 // Inverse real transform along x.  Two real rows a, b (consecutive linear
@@ -152,8 +179,8 @@ fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
 __global__ void __launch_bounds__(kPassThreads)
 fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g, FftAxis ax,
                  float scale) {
-    extern __shared__ float2 lds[];
-    const int Nx = g.n[0], H = g.H;
+    extern __shared__ __attribute__((aligned(16))) float2 lds[];
+    const int Nx = g.n[0], Hp = g.Hp;
     const int nrows = g.n[1] * g.n[2];
     const int row0 = blockIdx.x * kC2rRows;
     const int ncx = kC2rRows / 2;
@@ -171,8 +198,8 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
             xa[u] = xb[u] = make_float2(0.f, 0.f);
             if (i < tot && ra < nrows) {
                 const int kk = k > Nx / 2 ? Nx - k : k;
-                xa[u] = spec[(size_t)ra * H + kk];
-                xb[u] = spec[(size_t)(ra + 1) * H + kk];
+                xa[u] = spec[(size_t)ra * Hp + kk];
+                xb[u] = spec[(size_t)(ra + 1) * Hp + kk];
             }
         }
 #pragma unroll
@@ -205,11 +232,30 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
     }
 }
 
+// Per-thread prefetch depth for a pencil length: len * kChunk / 2 / 256 16-byte loads.
+static int prefetch_depth(int len) {
+    const int need = (len * (kChunk / 2) + kPassThreads - 1) / kPassThreads;
+    return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+}
+
+#define FVR_PF_SWITCH(len, KERNEL, ...)                                                   \
+    switch (prefetch_depth(len)) {                                                        \
+        case 2: KERNEL<2><<<__VA_ARGS__>>>(spec, g, ax); break;                          \
+        case 4: KERNEL<4><<<__VA_ARGS__>>>(spec, g, ax); break;                          \
+        case 8: KERNEL<8><<<__VA_ARGS__>>>(spec, g, ax); break;                          \
+        default: KERNEL<16><<<__VA_ARGS__>>>(spec, g, ax); break;                        \
+    }
+
 hipError_t fft_configure() {
-    const void *k[] = {(const void *)fft_y_fwd_kernel, (const void *)fft_z_solve_kernel,
-                       (const void *)fft_y_inv_kernel, (const void *)fft_x_c2r_kernel};
+    const void *k[] = {(const void *)fft_y_fwd_kernel<2>,   (const void *)fft_y_fwd_kernel<4>,
+                       (const void *)fft_y_fwd_kernel<8>,   (const void *)fft_y_fwd_kernel<16>,
+                       (const void *)fft_z_solve_kernel<2>, (const void *)fft_z_solve_kernel<4>,
+                       (const void *)fft_z_solve_kernel<8>, (const void *)fft_z_solve_kernel<16>,
+                       (const void *)fft_y_inv_kernel<2>,   (const void *)fft_y_inv_kernel<4>,
+                       (const void *)fft_y_inv_kernel<8>,   (const void *)fft_y_inv_kernel<16>,
+                       (const void *)fft_x_c2r_kernel};
     for (const void *f : k) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        hipError_t e = raise_dynamic_lds(f);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -218,21 +264,21 @@ hipError_t fft_configure() {
 // pencil buffers plus the twiddle table
 static size_t pass_lds(int n, int bufs) { return ((size_t)bufs * n * kChunk + n) * sizeof(float2); }
 
-hipError_t launch_fft_y_fwd(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s) {
+hipError_t launch_fft_y_fwd(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
-    fft_y_fwd_kernel<<<dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 2), s>>>(spec, g, ay);
+    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 2), s)
     return hipGetLastError();
 }
 
-hipError_t launch_fft_z_solve(float2 *spec, const Grid &g, const FftAxis &az, hipStream_t s) {
+hipError_t launch_fft_z_solve(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
-    fft_z_solve_kernel<<<dim3(nch * g.n[1]), dim3(kPassThreads), pass_lds(g.n[2], 2), s>>>(spec, g, az);
+    FVR_PF_SWITCH(g.n[2], fft_z_solve_kernel, dim3(nch * g.n[1]), dim3(kPassThreads), pass_lds(g.n[2], 2), s)
     return hipGetLastError();
 }
 
-hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s) {
+hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
-    fft_y_inv_kernel<<<dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 1), s>>>(spec, g, ay);
+    FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 1), s)
     return hipGetLastError();
 }
 

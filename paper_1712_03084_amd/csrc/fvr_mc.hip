@@ -329,6 +329,51 @@ __device__ __forceinline__ void mc_point(const float *__restrict__ A, const Grid
     }
 }
 
+// Edge bits and cell cases of the 4 consecutive grid points (qx..qx+3, qy, qz)
+// of one row (Nx % 4 == 0, qx % 4 == 0), from the 4 rows (y or y+1) x (z or
+// z+1) loaded as one float4 plus the fifth value each.  a0[i] = A(qx+i, qy, qz),
+// a1[a][i] = A at the far end of point i's edge along axis a (for vertices).
+__device__ __forceinline__ void mc_quad(const float *__restrict__ A, const Grid &g, int qx, int qy,
+                                        int qz, size_t l, float L, int eb[4], int cs[4],
+                                        float a0[4], float a1[3][4]) {
+    const size_t sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
+    const bool hy = qy + 1 < g.n[1], hz = qz + 1 < g.n[2], hx4 = qx + 4 < g.n[0];
+    float r[4][5];  // rows (dy, dz) = (0,0), (1,0), (0,1), (1,1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool have = (k & 1 ? hy : true) && (k & 2 ? hz : true);
+        const size_t o = l + (k & 1 ? sy : 0) + (k & 2 ? sz : 0);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        float e = 0.f;
+        if (have) {
+            v = *reinterpret_cast<const float4 *>(A + o);
+            if (hx4) e = A[o + 4];
+        }
+        r[k][0] = v.x;
+        r[k][1] = v.y;
+        r[k][2] = v.z;
+        r[k][3] = v.w;
+        r[k][4] = e;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool hx = qx + i + 1 < g.n[0];
+        a0[i] = r[0][i];
+        a1[0][i] = r[0][i + 1];
+        a1[1][i] = r[1][i];
+        a1[2][i] = r[2][i];
+        const bool in0 = r[0][i] > L;
+        eb[i] = (hx && ((r[0][i + 1] > L) != in0) ? 1 : 0) | (hy && ((r[1][i] > L) != in0) ? 2 : 0) |
+                (hz && ((r[2][i] > L) != in0) ? 4 : 0);
+        cs[i] = -1;
+        if (hx && hy && hz) {
+            cs[i] = (in0 ? 1 : 0) | (r[0][i + 1] > L ? 2 : 0) | (r[1][i] > L ? 4 : 0) |
+                    (r[1][i + 1] > L ? 8 : 0) | (r[2][i] > L ? 16 : 0) | (r[2][i + 1] > L ? 32 : 0) |
+                    (r[3][i] > L ? 64 : 0) | (r[3][i + 1] > L ? 128 : 0);
+        }
+    }
+}
+
 __device__ __forceinline__ int block_sum(int v, int *red) {
     // 256 threads = 4 waves
 #pragma unroll
@@ -355,29 +400,52 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
         size_t r = l0 / g.n[0];
         int qy = (int)(r % g.n[1]);
         int qz = (int)(r / g.n[1]);
+        if ((g.n[0] & 3) == 0 && ((uintptr_t)A & 15) == 0) {
+            // the 4 points share a row: vector loads of the 4 neighbouring rows
+            int eb[4], cs[4];
+            float a0[4], a1[3][4];
+            mc_quad(A, g, qx, qy, qz, l0, L, eb, cs, a0, a1);
+            const bool yzb = qy == 0 || qz == 0 || qy == g.n[1] - 1 || qz == g.n[2] - 1;
 #pragma unroll
-        for (int i = 0; i < kMcPpt; ++i) {
-            const size_t l = l0 + i;
-            if (l < n) {
-                int eb, cs;
-                mc_point(A, g, qx, qy, qz, l, L, eb, cs);
-                nv += __popc(eb);
-                if (cs >= 0) {
-                    const int c = c_mc_count[cs];
+            for (int i = 0; i < kMcPpt; ++i) {
+                nv += __popc(eb[i]);
+                if (cs[i] >= 0) {
+                    const int c = c_mc_count[cs[i]];
                     nt += c;
                     na += c > 0;
                     if (cases_out)
-                        cases_out[qx + (size_t)(g.n[0] - 1) * (qy + (size_t)(g.n[1] - 1) * qz)] = (uint8_t)cs;
+                        cases_out[qx + i + (size_t)(g.n[0] - 1) * (qy + (size_t)(g.n[1] - 1) * qz)] =
+                            (uint8_t)cs[i];
                 }
-                const bool border = qx == 0 || qy == 0 || qz == 0 || qx == g.n[0] - 1 ||
-                                    qy == g.n[1] - 1 || qz == g.n[2] - 1;
-                if (border && A[l] > L) open = true;
+                const bool border = yzb || qx + i == 0 || qx + i == g.n[0] - 1;
+                if (border && a0[i] > L) open = true;
             }
-            if (++qx == g.n[0]) {
-                qx = 0;
-                if (++qy == g.n[1]) {
-                    qy = 0;
-                    ++qz;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kMcPpt; ++i) {
+                const size_t l = l0 + i;
+                if (l < n) {
+                    int eb, cs;
+                    mc_point(A, g, qx, qy, qz, l, L, eb, cs);
+                    nv += __popc(eb);
+                    if (cs >= 0) {
+                        const int c = c_mc_count[cs];
+                        nt += c;
+                        na += c > 0;
+                        if (cases_out)
+                            cases_out[qx + (size_t)(g.n[0] - 1) * (qy + (size_t)(g.n[1] - 1) * qz)] =
+                                (uint8_t)cs;
+                    }
+                    const bool border = qx == 0 || qy == 0 || qz == 0 || qx == g.n[0] - 1 ||
+                                        qy == g.n[1] - 1 || qz == g.n[2] - 1;
+                    if (border && A[l] > L) open = true;
+                }
+                if (++qx == g.n[0]) {
+                    qx = 0;
+                    if (++qy == g.n[1]) {
+                        qy = 0;
+                        ++qz;
+                    }
                 }
             }
         }
@@ -426,6 +494,7 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
     const size_t l0 = (size_t)blockIdx.x * kMcPerBlock + (size_t)threadIdx.x * kMcPpt;
     int eb[kMcPpt], cs[kMcPpt];
+    float a0[kMcPpt], a1[3][kMcPpt];
     int cnt[3] = {0, 0, 0};
     int qx = 0, qy = 0, qz = 0;
     if (l0 < n) {
@@ -434,21 +503,25 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
         qy = (int)(r % g.n[1]);
         qz = (int)(r / g.n[1]);
     }
-    {
+    const bool quad = (g.n[0] & 3) == 0 && ((uintptr_t)A & 15) == 0;
+    if (quad && l0 < n) {
+        mc_quad(A, g, qx, qy, qz, l0, L, eb, cs, a0, a1);
+    } else {
+        const size_t sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
         int x = qx, y = qy, z = qz;
 #pragma unroll
         for (int i = 0; i < kMcPpt; ++i) {
             eb[i] = 0;
             cs[i] = -1;
+            a0[i] = 0.f;
+            a1[0][i] = a1[1][i] = a1[2][i] = 0.f;
             const size_t l = l0 + i;
             if (l < n) {
                 mc_point(A, g, x, y, z, l, L, eb[i], cs[i]);
-                cnt[0] += __popc(eb[i]);
-                if (cs[i] >= 0) {
-                    const int c = c_mc_count[cs[i]];
-                    cnt[1] += c;
-                    cnt[2] += c > 0;
-                }
+                a0[i] = A[l];
+                if (eb[i] & 1) a1[0][i] = A[l + 1];
+                if (eb[i] & 2) a1[1][i] = A[l + sy];
+                if (eb[i] & 4) a1[2][i] = A[l + sz];
             }
             if (++x == g.n[0]) {
                 x = 0;
@@ -459,25 +532,31 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
             }
         }
     }
+#pragma unroll
+    for (int i = 0; i < kMcPpt; ++i) {
+        cnt[0] += __popc(eb[i]);
+        if (cs[i] >= 0) {
+            const int c = c_mc_count[cs[i]];
+            cnt[1] += c;
+            cnt[2] += c > 0;
+        }
+    }
     block_excl_scan3(cnt, red);
     int vbase = blk_off[3 * blockIdx.x + 0] + cnt[0];
     int tbase = blk_off[3 * blockIdx.x + 1] + cnt[1];
     int abase = blk_off[3 * blockIdx.x + 2] + cnt[2];
-    const size_t sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
     int x = qx, y = qy, z = qz;
     for (int i = 0; i < kMcPpt; ++i) {
         const size_t l = l0 + i;
         if (l >= n) break;
         if (eb[i]) {
-            const float a0 = A[l];
             const float px = fmaf((float)x + 0.5f, g.h[0], g.bmin[0]);
             const float py = fmaf((float)y + 0.5f, g.h[1], g.bmin[1]);
             const float pz = fmaf((float)z + 0.5f, g.h[2], g.bmin[2]);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (!((eb[i] >> a) & 1)) continue;
-                const float a1 = A[l + (a == 0 ? 1 : a == 1 ? sy : sz)];
-                const float t = (L - a0) / (a1 - a0);
+                const float t = (L - a0[i]) / (a1[a][i] - a0[i]);
                 float p[3] = {px, py, pz};
                 p[a] += t * g.h[a];
                 verts[3 * (size_t)vbase + 0] = p[0];

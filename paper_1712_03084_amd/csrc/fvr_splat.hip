@@ -25,7 +25,7 @@ namespace fvr {
 
 constexpr int kSplatThreads = 512;
 constexpr int kSplatMaxPlane = 4096;  // voxels per channel plane of a tile, at most
-constexpr int kMaxSegs = 16;
+constexpr int kMaxBins = 128;   // (ty+3)(tz+3) footprint-origin bins per tile, at most
 
 // Footprint origin floor((x - bmin)/h - 1/2) in float32, each operation
 // correctly rounded (no contraction), so every implementation that follows
@@ -114,9 +114,13 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
     }
 }
 
+// Record of a binned point: (f_x, f_y, f_z, W), (W N_x, W N_y, W N_z, i0_x),
+// with v = (X - bmin)/h - 1/2 the voxel-centre coordinate (float32 formula
+// above), i0 = floor(v) the footprint origin and f = v - i0 in [0, 1).  The
+// (i0_y, i0_z) pair is the record's bin; i0_x travels as integer bits.
 __global__ void __launch_bounds__(256)
 bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
-                   const float *__restrict__ w, int m, const int32_t *__restrict__ key,
+                   const float *__restrict__ w, int m, Grid g, const int32_t *__restrict__ key,
                    const int32_t *__restrict__ rank, const int32_t *__restrict__ bin_off,
                    float4 *__restrict__ rec) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -125,8 +129,18 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
     if (k < 0) return;
     const int pos = bin_off[k] + rank[i];
     const float wi = w ? w[i] : 1.0f;
-    rec[2 * pos] = make_float4(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], wi);
-    rec[2 * pos + 1] = make_float4(wi * nrm[3 * i], wi * nrm[3 * i + 1], wi * nrm[3 * i + 2], 0.0f);
+    float f[3];
+    int ix = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float v = voxel_coord(pts[3 * i + a], g.bmin[a], g.h[a]);
+        const float fl = floorf(v);
+        f[a] = v - fl;
+        if (a == 0) ix = (int)fl;
+    }
+    rec[2 * pos] = make_float4(f[0], f[1], f[2], wi);
+    rec[2 * pos + 1] = make_float4(wi * nrm[3 * i], wi * nrm[3 * i + 1], wi * nrm[3 * i + 2],
+                                   __int_as_float(ix));
 }
 
 // Accumulation is in 64-bit fixed point with integer LDS atomics (gfx950's
@@ -136,49 +150,71 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
 // and an int64 voxel sum cannot overflow for fewer than 2^31 points.  The sums
 // are exact, hence independent of the order of the additions: the splat is
 // bit-reproducible.  V = (sigma2/sigma1) (S unit_S) / (D unit_D).
+// Work decomposition: the candidate points of a tile come in bins of equal
+// footprint origin (i0_y, i0_z), and all points of one bin reach the same
+// in-tile rows.  The block enumerates (bin, point, row) items - only rows
+// that exist in the tile - and each item adds one point's 4 x-voxels of one
+// row: 10 exponentials (4 x offsets and 1 (y, z) pair, two Gaussians) and 16
+// integer atomics, none masked off.
 template <bool CHUNKED>
 __global__ void __launch_bounds__(kSplatThreads)
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
                    SplatConsts sc, FftAxis ax, const DevStatus *__restrict__ st,
                    float2 *__restrict__ spec, float *__restrict__ v_out) {
     extern __shared__ unsigned long long acc[];
-    __shared__ int seg_start[kMaxSegs];
-    __shared__ int seg_pre[kMaxSegs + 1];
+    __shared__ int b_start[kMaxBins], b_pre[kMaxBins + 1], b_rows[kMaxBins], b_ny[kMaxBins];
+    __shared__ int b_qy[kMaxBins], b_qz[kMaxBins], b_iy[kMaxBins], b_iz[kMaxBins];
+    __shared__ unsigned b_mrows[kMaxBins], b_mny[kMaxBins];
 
     const int Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
     const int TY = sc.ty, TZ = sc.tz, R = TY * TZ;
     const int by = blockIdx.x % sc.tiles_y, bz = blockIdx.x / sc.tiles_y;
     const int y0 = by * TY, z0 = bz * TZ;
     const int plane = R * Nx;  // voxels per channel plane
+    // int64 accumulators use a row pitch of Nx + 1: with Nx a multiple of the
+    // bank count, an unpadded row would put a voxel's bank on x alone, and the
+    // points of a tile cluster in x (the surface crossings)
+    const int P = Nx + 1, aplane = R * P;
 
-    // candidate points: bins of footprint origins (iy, iz) whose 4-row
-    // footprints overlap the tile, i.e. iy in [y0-2, y0+TY], iz in [z0-2, z0+TZ]
+    // bins of footprint origins (iy, iz) whose 4-row footprints overlap the
+    // tile: iy in [y0-2, y0+TY], iz in [z0-2, z0+TZ] (clipped to [-1, N-1])
     const int iz_lo = max(z0 - 2, -1), iz_hi = min(z0 + TZ, Nz - 1);
     const int iy_lo = max(y0 - 2, -1), iy_hi = min(y0 + TY, Ny - 1);
-    const int nseg = iz_hi - iz_lo + 1;
-    if (threadIdx.x < nseg) {
-        const int iz = iz_lo + threadIdx.x;
-        const int k0 = (iz + 1) * (Ny + 1) + (iy_lo + 1);
-        const int k1 = (iz + 1) * (Ny + 1) + (iy_hi + 1) + 1;
-        seg_start[threadIdx.x] = bin_off[k0];
-        seg_pre[threadIdx.x + 1] = bin_off[k1] - bin_off[k0];
+    const int nby = iy_hi - iy_lo + 1, nbins = nby * (iz_hi - iz_lo + 1);
+    for (int t = threadIdx.x; t < nbins; t += blockDim.x) {
+        const int iy = iy_lo + t % nby, iz = iz_lo + t / nby;
+        const int kb = (iz + 1) * (Ny + 1) + (iy + 1);
+        const int qy0 = max(iy - 1, y0), qy1 = min(min(iy + 2, y0 + TY - 1), Ny - 1);
+        const int qz0 = max(iz - 1, z0), qz1 = min(min(iz + 2, z0 + TZ - 1), Nz - 1);
+        const int ny = max(qy1 - qy0 + 1, 0), nz = max(qz1 - qz0 + 1, 0);
+        const int cnt = bin_off[kb + 1] - bin_off[kb];
+        b_start[t] = bin_off[kb];
+        b_rows[t] = ny * nz;
+        b_ny[t] = max(ny, 1);
+        b_qy[t] = qy0;
+        b_qz[t] = qz0;
+        b_iy[t] = iy;
+        b_iz[t] = iz;
+        b_mrows[t] = div_magic(max(ny * nz, 1));
+        b_mny[t] = div_magic(max(ny, 1));
+        b_pre[t + 1] = cnt * ny * nz;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        seg_pre[0] = 0;
-        for (int s = 0; s < nseg; ++s) seg_pre[s + 1] += seg_pre[s];
+        b_pre[0] = 0;
+        for (int t = 0; t < nbins; ++t) b_pre[t + 1] += b_pre[t];
     }
     __syncthreads();
-    const int total = seg_pre[nseg];
-    const int H = g.H;
-    const size_t pl = (size_t)Nz * Ny * H;
+    const int total = b_pre[nbins];
+    const int H = g.H, Hp = g.Hp;
+    const size_t pl = (size_t)Nz * Ny * Hp;
     if (total == 0) {
         // no point reaches this tile: V = 0 and so is its spectrum
         for (int i = threadIdx.x; i < 3 * R * H; i += blockDim.x) {
             const int rr = i / H, k = i - rr * H;
             const int c = rr / R, r = rr - c * R;
             const int y = y0 + r % TY, z = z0 + r / TY;
-            if (y < Ny && z < Nz) spec[c * pl + ((size_t)z * Ny + y) * H + k] = make_float2(0.f, 0.f);
+            if (y < Ny && z < Nz) spec[c * pl + ((size_t)z * Ny + y) * Hp + k] = make_float2(0.f, 0.f);
         }
         if (v_out) {
             const size_t n = (size_t)Nx * Ny * Nz;
@@ -191,8 +227,8 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         }
         return;
     }
-    for (int i = threadIdx.x; i < 4 * plane; i += blockDim.x) acc[i] = 0ull;
-    float2 *twl = reinterpret_cast<float2 *>(acc + 4 * plane);
+    for (int i = threadIdx.x; i < 4 * aplane; i += blockDim.x) acc[i] = 0ull;
+    float2 *twl = reinterpret_cast<float2 *>(acc + 4 * aplane);
     load_twiddles(twl, ax);
 
     // fixed-point units: 2^(e-30) with max < 2^e, so every rounded term fits int32
@@ -204,85 +240,81 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
     const int chunk = (total + 63) / 64;
-    // candidate of this thread's k-th iteration, or -1 when it has no more
-    auto cand = [&](int k) -> int {
+    // item of this thread's k-th iteration, or -1 when it has no more
+    auto item = [&](int k) -> int {
         int j;
         if (CHUNKED) {
-            // lane l owns candidates [l chunk, (l+1) chunk); the waves interleave
+            // lane l owns items [l chunk, (l+1) chunk); the waves interleave, so
+            // a wave's lanes work far apart in the item list (distinct voxels)
             const int kk = wv + k * nwv;
             if (kk >= chunk) return -1;
             j = lane * chunk + kk;
         } else {
             j = k * (int)blockDim.x + threadIdx.x;
         }
-        if (j >= total) return -1;
-        int s = 0;
-        while (seg_pre[s + 1] <= j) ++s;
-        return seg_start[s] + (j - seg_pre[s]);
+        return j < total ? j : -1;
+    };
+    auto decode = [&](int j, int &bin, int &p, int &ry, int &rz) {
+        int lo = 0, hi = nbins - 1;  // last bin with b_pre[bin] <= j
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b_pre[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        bin = lo;
+        const int local = j - b_pre[lo];
+        const int pi = udiv(local, b_rows[lo], b_mrows[lo]);
+        const int r = local - pi * b_rows[lo];
+        const int rzi = udiv(r, b_ny[lo], b_mny[lo]);
+        p = b_start[lo] + pi;
+        rz = b_qz[lo] + rzi;
+        ry = b_qy[lo] + (r - rzi * b_ny[lo]);
     };
 
-    int p = cand(0), k = 0;
+    int j = item(0), k = 0;
+    int bin = 0, p = 0, qy = 0, qz = 0;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-    if (p >= 0) {
+    if (j >= 0) {
+        decode(j, bin, p, qy, qz);
         r0 = rec[2 * p];
         r1 = rec[2 * p + 1];
     }
-    while (p >= 0) {
-        const int pn = cand(k + 1);
+    while (j >= 0) {
+        const int jn = item(k + 1);
+        int binn = bin, pn = p, qyn = qy, qzn = qz;
         float4 n0 = r0, n1 = r1;
-        if (pn >= 0) {  // prefetch the next record while this one is splatted
+        if (jn >= 0) {  // prefetch the next item's record while this one is splatted
+            decode(jn, binn, pn, qyn, qzn);
             n0 = rec[2 * pn];
             n1 = rec[2 * pn + 1];
         }
-        const float X[3] = {r0.x, r0.y, r0.z};
-        float v[3];
-        int i0[3];
+        // offsets of this row's centre and of the 4 x centres from the point, in voxels
+        const float dy = r0.y + (float)(b_iy[bin] - qy);
+        const float dz = r0.z + (float)(b_iz[bin] - qz);
+        const float a1 = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy + sc.e1[2] * dz * dz);
+        const float a2 = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy + sc.e2[2] * dz * dz) * (r0.w * qD);
+        const float sx = a1 * r1.x * qS, sy = a1 * r1.y * qS, sz = a1 * r1.z * qS;
+        const int ix = __float_as_int(r1.w);
+        const int row = (qz - z0) * TY + (qy - y0);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            v[a] = voxel_coord(X[a], g.bmin[a], g.h[a]);
-            i0[a] = (int)floorf(v[a]);
-        }
-        float wx1[4], wx2[4], wy1[4], wy2[4], wz1[4], wz2[4];
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            const float dx = v[0] - (float)(i0[0] + o - 1);
-            const float dy = v[1] - (float)(i0[1] + o - 1);
-            const float dz = v[2] - (float)(i0[2] + o - 1);
-            wx1[o] = __builtin_amdgcn_exp2f(sc.e1[0] * dx * dx);
-            wx2[o] = __builtin_amdgcn_exp2f(sc.e2[0] * dx * dx);
-            wy1[o] = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy);
-            wy2[o] = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy);
-            wz1[o] = __builtin_amdgcn_exp2f(sc.e1[2] * dz * dz);
-            wz2[o] = __builtin_amdgcn_exp2f(sc.e2[2] * dz * dz);
-        }
-        const float nxq = r1.x * qS, nyq = r1.y * qS, nzq = r1.z * qS, wq = r0.w * qD;
-#pragma unroll
-        for (int oz = 0; oz < 4; ++oz) {
-            const int qz = i0[2] + oz - 1;
-            if (qz < z0 || qz >= z0 + TZ || qz >= Nz) continue;
-#pragma unroll
-            for (int oy = 0; oy < 4; ++oy) {
-                const int qy = i0[1] + oy - 1;
-                if (qy < y0 || qy >= y0 + TY || qy >= Ny) continue;
-                const int row = (qz - z0) * TY + (qy - y0);
-                const float a1 = wy1[oy] * wz1[oz], a2 = wy2[oy] * wz2[oz];
-#pragma unroll
-                for (int ox = 0; ox < 4; ++ox) {
-                    const int qx = i0[0] + ox - 1;
-                    if (qx < 0 || qx >= Nx) continue;
-                    const int l = row * Nx + qx;
-                    const float g1 = wx1[ox] * a1;
-                    atomicAdd(&acc[l], (unsigned long long)(long long)__float2int_rn(g1 * nxq));
-                    atomicAdd(&acc[plane + l], (unsigned long long)(long long)__float2int_rn(g1 * nyq));
-                    atomicAdd(&acc[2 * plane + l], (unsigned long long)(long long)__float2int_rn(g1 * nzq));
-                    atomicAdd(&acc[3 * plane + l],
-                              (unsigned long long)(long long)__float2int_rn(wx2[ox] * a2 * wq));
-                }
-            }
+        for (int ox = 0; ox < 4; ++ox) {
+            const int qx = ix + ox - 1;
+            if (qx < 0 || qx >= Nx) continue;
+            const float dx = r0.x - (float)(ox - 1);
+            const float g1 = __builtin_amdgcn_exp2f(sc.e1[0] * dx * dx);
+            const float g2 = __builtin_amdgcn_exp2f(sc.e2[0] * dx * dx);
+            const int l = row * P + qx;
+            atomicAdd(&acc[l], (unsigned long long)(long long)__float2int_rn(g1 * sx));
+            atomicAdd(&acc[aplane + l], (unsigned long long)(long long)__float2int_rn(g1 * sy));
+            atomicAdd(&acc[2 * aplane + l], (unsigned long long)(long long)__float2int_rn(g1 * sz));
+            atomicAdd(&acc[3 * aplane + l], (unsigned long long)(long long)__float2int_rn(g2 * a2));
         }
         r0 = n0;
         r1 = n1;
+        j = jn;
+        bin = binn;
         p = pn;
+        qy = qyn;
+        qz = qzn;
         ++k;
     }
     __syncthreads();
@@ -299,12 +331,13 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         const int l = threadIdx.x + t * blockDim.x;
         vv[t][0] = vv[t][1] = vv[t][2] = 0.f;
         if (l < plane) {
-            const long long d = (long long)acc[3 * plane + l];
+            const int row = l / Nx, la = l + row;  // padded accumulator index
+            const long long d = (long long)acc[3 * aplane + la];
             if (d > 0) {
                 const float inv = ratio / (float)d;
-                vv[t][0] = (float)(long long)acc[l] * inv;
-                vv[t][1] = (float)(long long)acc[plane + l] * inv;
-                vv[t][2] = (float)(long long)acc[2 * plane + l] * inv;
+                vv[t][0] = (float)(long long)acc[la] * inv;
+                vv[t][1] = (float)(long long)acc[aplane + la] * inv;
+                vv[t][2] = (float)(long long)acc[2 * aplane + la] * inv;
             }
         }
     }
@@ -356,8 +389,8 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         }
         const int ya = y0 + ra % TY, za = z0 + ra / TY;
         const int yb = y0 + (ra + 1) % TY, zb = z0 + (ra + 1) / TY;
-        if (ya < Ny && za < Nz) spec[c * pl + ((size_t)za * Ny + ya) * H + kx] = xa;
-        if (yb < Ny && zb < Nz) spec[c * pl + ((size_t)zb * Ny + yb) * H + kx] = xb;
+        if (ya < Ny && za < Nz) spec[c * pl + ((size_t)za * Ny + ya) * Hp + kx] = xa;
+        if (yb < Ny && zb < Nz) spec[c * pl + ((size_t)zb * Ny + yb) * Hp + kx] = xb;
     }
 }
 
@@ -366,15 +399,14 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
 #endif
 
 hipError_t splat_configure() {
-    hipError_t e = hipFuncSetAttribute((const void *)splat_fft_x_kernel<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+    hipError_t e = raise_dynamic_lds((const void *)splat_fft_x_kernel<true>);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)splat_fft_x_kernel<false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+    return raise_dynamic_lds((const void *)splat_fft_x_kernel<false>);
 }
 
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
-    return (size_t)4 * sc.ty * sc.tz * g.n[0] * sizeof(unsigned long long) + g.n[0] * sizeof(float2);
+    return (size_t)4 * sc.ty * sc.tz * (g.n[0] + 1) * sizeof(unsigned long long) +
+           g.n[0] * sizeof(float2);
 }
 
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
@@ -387,10 +419,10 @@ hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, 
 }
 
 hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
-                              const int32_t *key, const int32_t *rank, const int32_t *bin_off,
-                              float4 *rec, hipStream_t s) {
+                              const Grid &g, const int32_t *key, const int32_t *rank,
+                              const int32_t *bin_off, float4 *rec, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    bin_scatter_kernel<<<dim3((m + 255) / 256), dim3(256), 0, s>>>(pts, nrm, w, m, key, rank,
+    bin_scatter_kernel<<<dim3((m + 255) / 256), dim3(256), 0, s>>>(pts, nrm, w, m, g, key, rank,
                                                                    bin_off, rec);
     return hipGetLastError();
 }

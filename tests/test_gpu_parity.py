@@ -144,14 +144,29 @@ def test_marching_cubes_bit_exact_on_oracle_field_sphere(ctx):
     _mc_compare(ctx, r["A"], r["level"], f.dims, f.bbox)
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_marching_cubes_bit_exact_random_fields(ctx, seed):
-    """Random fields exercise every case family, ragged block tails and
-    surfaces that reach the grid border."""
+@pytest.mark.parametrize("seed,dims", [(0, (36, 22, 30)), (1, (36, 22, 30)), (2, (30, 14, 18)),
+                                       (3, (7, 5, 9))])
+def test_marching_cubes_bit_exact_random_fields(ctx, seed, dims):
+    """Random fields exercise every case family, ragged block tails, surfaces
+    that reach the grid border, and rows whose length is not a multiple of 4."""
     rng = np.random.default_rng(seed)
-    dims = (36, 22, 30)
     A = rng.standard_normal(dims[::-1])
-    _mc_compare(ctx, A, 0.1, dims, (0.0, 0.0, 0.0, 3.6, 2.2, 3.0))
+    _mc_compare(ctx, A, 0.1, dims, (0.0, 0.0, 0.0) + tuple(0.1 * d for d in dims))
+
+
+def test_marching_cubes_unaligned_field(ctx):
+    """A field view starting one float into its allocation (not 16-byte aligned)."""
+    rng = np.random.default_rng(8)
+    dims = (16, 12, 10)
+    A = rng.standard_normal(dims[::-1]).astype(np.float32)
+    buf = torch.empty(A.size + 1, dtype=torch.float32, device="cuda")
+    view = buf[1:].view(dims[::-1])
+    view.copy_(torch.from_numpy(A).cuda())
+    bbox = (0.0, 0.0, 0.0, 1.6, 1.2, 1.0)
+    mesh, cases = ctx.extract(view, bbox, 0.2, with_cases=True)
+    vo, to, co = oracle.extract(A.astype(np.float64), float(np.float32(0.2)), dims, bbox)
+    assert np.array_equal(cases.cpu().numpy(), co)
+    assert np.array_equal(mesh.triangles.cpu().numpy(), to)
 
 
 def test_marching_cubes_ties_are_outside(ctx):

@@ -23,7 +23,7 @@
 
 namespace fvr {
 
-constexpr int kSplatThreads = 512;
+constexpr int kSplatThreads = 1024;
 constexpr int kSplatMaxPlane = 4096;  // voxels per channel plane of a tile, at most
 constexpr int kMaxBins = 128;   // (ty+3)(tz+3) footprint-origin bins per tile, at most
 
@@ -254,42 +254,72 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         }
         return j < total ? j : -1;
     };
-    auto decode = [&](int j, int &bin, int &p, int &ry, int &rz) {
+
+    // A lane's items increase monotonically, so it keeps the decode parameters
+    // of its current bin in registers and reads the bin tables only when it
+    // moves to a later bin.  (An LDS read in the steady-state loop would wait
+    // for the previous item's queued atomics: LDS operations retire in order.)
+    struct BinState {
+        int b, lo, hi, start, rows, ny, qy0, qz0, iy, iz;
+        unsigned mrows, mny;
+    };
+    auto enter_bin = [&](BinState &st, int b) {
+        st.b = b;
+        st.lo = b_pre[b];
+        st.hi = b_pre[b + 1];
+        st.start = b_start[b];
+        st.rows = b_rows[b];
+        st.ny = b_ny[b];
+        st.qy0 = b_qy[b];
+        st.qz0 = b_qz[b];
+        st.iy = b_iy[b];
+        st.iz = b_iz[b];
+        st.mrows = b_mrows[b];
+        st.mny = b_mny[b];
+    };
+    BinState bs;
+    int j = item(0), k = 0;
+    if (j >= 0) {
         int lo = 0, hi = nbins - 1;  // last bin with b_pre[bin] <= j
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (b_pre[mid] <= j) lo = mid; else hi = mid - 1;
         }
-        bin = lo;
-        const int local = j - b_pre[lo];
-        const int pi = udiv(local, b_rows[lo], b_mrows[lo]);
-        const int r = local - pi * b_rows[lo];
-        const int rzi = udiv(r, b_ny[lo], b_mny[lo]);
-        p = b_start[lo] + pi;
-        rz = b_qz[lo] + rzi;
-        ry = b_qy[lo] + (r - rzi * b_ny[lo]);
+        enter_bin(bs, lo);
+    }
+    // decode item jj (in bin bs, advancing it as needed) into point index and row
+    auto decode = [&](int jj, int &p, int &qy, int &qz, int &iy, int &iz) {
+        while (jj >= bs.hi) enter_bin(bs, bs.b + 1);
+        const int local = jj - bs.lo;
+        const int pi = udiv(local, bs.rows, bs.mrows);
+        const int r = local - pi * bs.rows;
+        const int rzi = udiv(r, bs.ny, bs.mny);
+        p = bs.start + pi;
+        qz = bs.qz0 + rzi;
+        qy = bs.qy0 + (r - rzi * bs.ny);
+        iy = bs.iy;
+        iz = bs.iz;
     };
 
-    int j = item(0), k = 0;
-    int bin = 0, p = 0, qy = 0, qz = 0;
+    int p = 0, qy = 0, qz = 0, iy = 0, iz = 0;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
     if (j >= 0) {
-        decode(j, bin, p, qy, qz);
+        decode(j, p, qy, qz, iy, iz);
         r0 = rec[2 * p];
         r1 = rec[2 * p + 1];
     }
     while (j >= 0) {
         const int jn = item(k + 1);
-        int binn = bin, pn = p, qyn = qy, qzn = qz;
+        int pn = p, qyn = qy, qzn = qz, iyn = iy, izn = iz;
         float4 n0 = r0, n1 = r1;
         if (jn >= 0) {  // prefetch the next item's record while this one is splatted
-            decode(jn, binn, pn, qyn, qzn);
+            decode(jn, pn, qyn, qzn, iyn, izn);
             n0 = rec[2 * pn];
             n1 = rec[2 * pn + 1];
         }
         // offsets of this row's centre and of the 4 x centres from the point, in voxels
-        const float dy = r0.y + (float)(b_iy[bin] - qy);
-        const float dz = r0.z + (float)(b_iz[bin] - qz);
+        const float dy = r0.y + (float)(iy - qy);
+        const float dz = r0.z + (float)(iz - qz);
         const float a1 = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy + sc.e1[2] * dz * dz);
         const float a2 = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy + sc.e2[2] * dz * dz) * (r0.w * qD);
         const float sx = a1 * r1.x * qS, sy = a1 * r1.y * qS, sz = a1 * r1.z * qS;
@@ -311,10 +341,11 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         r0 = n0;
         r1 = n1;
         j = jn;
-        bin = binn;
         p = pn;
         qy = qyn;
         qz = qzn;
+        iy = iyn;
+        iz = izn;
         ++k;
     }
     __syncthreads();

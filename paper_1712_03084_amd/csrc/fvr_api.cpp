@@ -69,7 +69,7 @@ struct fvr_ctx {
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off,
-        lvl_sum, lvl_cnt, status, level_f32, scan_part;
+        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc;
     DevStatus *host_status = nullptr;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -196,6 +196,8 @@ Grid make_grid(const int32_t dims[3], const float bbox[6]) {
     }
     g.H = dims[0] / 2 + 1;
     g.Hp = (g.H + 15) / 16 * 16;
+    g.ty = g.tz = 1;  // splat tiling, filled in from the plan where it matters
+    g.tiles_y = dims[1];
     return g;
 }
 
@@ -264,8 +266,13 @@ fvr_status check_frame(fvr_ctx *c, const fvr_frame *f) {
 
 // Stages 1-4 (and optionally 5): status reset, binning, splat + x FFT and,
 // unless splat_only, the remaining transform passes into `field`.
-fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g, float *field,
+fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, float *field,
                      float *v_out, bool splat_only) {
+    Grid g = g0;
+    g.ty = p->sc.ty;
+    g.tz = p->sc.tz;
+    g.tiles_y = p->sc.tiles_y;
+    const int ntiles = p->sc.tiles_y * ((g.n[2] + p->sc.tz - 1) / p->sc.tz);
     const int m = (int)f->n_points;
     const int nbins = (g.n[2] + 1) * (g.n[1] + 1);
     const size_t nspec = (size_t)g.n[2] * g.n[1] * g.Hp;
@@ -276,6 +283,8 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g, flo
     HIP_TRY(c, ensure(c->rec, sizeof(float4) * 2 * (size_t)m), "alloc records");
     HIP_TRY(c, ensure(c->spec, sizeof(float2) * 3 * nspec), "alloc spectra");
     HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
+    HIP_TRY(c, ensure(c->occ, (size_t)ntiles), "alloc tile occupancy");
+    HIP_TRY(c, ensure(c->zocc, (size_t)g.n[2]), "alloc plane occupancy");
     // sized for both scans of the frame before anything is enqueued
     const int scan_items = std::max(scan_partials(nbins), scan_partials(mc_blocks(g)));
     HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_items), "alloc scan scratch");
@@ -294,11 +303,13 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g, flo
               "bin_scatter"); }
     { Timed t(c, K_SPLAT_FFT_X);
       HIP_TRY(c, launch_splat_fft_x(P<float4>(c->rec), P<int32_t>(c->bin_off), g, p->sc, p->ax[0],
-                                    st, P<float2>(c->spec), v_out, s), "splat_fft_x"); }
+                                    st, P<float2>(c->spec), P<uint8_t>(c->occ), v_out, s), "splat_fft_x"); }
     if (splat_only) return FVR_OK;
     float2 *sp = P<float2>(c->spec);
-    { Timed t(c, K_FFT_Y_FWD); HIP_TRY(c, launch_fft_y_fwd(sp, g, p->ax[1], s), "fft_y_fwd"); }
-    { Timed t(c, K_FFT_Z_SOLVE); HIP_TRY(c, launch_fft_z_solve(sp, g, p->ax[2], s), "fft_z_solve"); }
+    { Timed t(c, K_FFT_Y_FWD);
+      HIP_TRY(c, launch_fft_y_fwd(sp, P<uint8_t>(c->occ), P<uint8_t>(c->zocc), g, p->ax[1], s), "fft_y_fwd"); }
+    { Timed t(c, K_FFT_Z_SOLVE);
+      HIP_TRY(c, launch_fft_z_solve(sp, P<uint8_t>(c->zocc), g, p->ax[2], s), "fft_z_solve"); }
     { Timed t(c, K_FFT_Y_INV); HIP_TRY(c, launch_fft_y_inv(sp, g, p->ax[1], s), "fft_y_inv"); }
     { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, g, p->ax[0], s), "fft_x_c2r"); }
     return FVR_OK;
@@ -407,7 +418,7 @@ void fvr_destroy(fvr_ctx *c) {
     for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_part};
+                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {

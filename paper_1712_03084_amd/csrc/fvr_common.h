@@ -37,6 +37,8 @@ struct Grid {
     int n[3];          // Nx, Ny, Nz
     int H;             // Nx/2 + 1: length of a half-spectrum row
     int Hp;            // row pitch of the spectrum planes: H rounded up to 16 (128-byte rows)
+    int ty, tz;        // splat tile rows along y and z (full x rows per tile)
+    int tiles_y;       // ceil(Ny / ty)
     float bmin[3];
     float bmax[3];
     float h[3];        // (bmax - bmin) / N, float32
@@ -63,6 +65,7 @@ struct DevStatus {
     double level;
     uint32_t wmax_bits;   // float bits of max W over accepted points (W >= 0)
     uint32_t wnmax_bits;  // float bits of max W |N_c| over accepted points
+    int32_t tile_ticket;  // next splat tile to claim (persistent splat blocks)
 };
 constexpr uint32_t kFlagInvalid = 1u;
 constexpr uint32_t kFlagOpen = 2u;
@@ -99,17 +102,25 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 // point, scaled per frame from st->wmax_bits / wnmax_bits), forms
 // V = S/D, transforms along x and writes three half-spectrum planes
 // (the x-component already multiplied by j w_x).  v_out (optional) receives V.
+// Tiles no point reaches are skipped: occ[tile] = 0 and their spectrum rows
+// are left unwritten (they are zero); occupied tiles set occ[tile] = 1.
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
-                              const SplatConsts &sc, const FftAxis &ax, const DevStatus *st,
-                              float2 *spec, float *v_out, hipStream_t s);
+                              const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
+                              float2 *spec, uint8_t *occ, float *v_out, hipStream_t s);
+int splat_blocks();
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc);
 
 // Forward y transform of the three planes, combining the x and y
 // derivative terms: plane0 <- F_y(plane0) + j w_y F_y(plane1); plane2 <- F_y(plane2).
-hipError_t launch_fft_y_fwd(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
+// Rows of unoccupied tiles are read as zero; a z plane with no occupied tile
+// is neither read nor written and gets zocc[z] = 0 (1 otherwise).
+hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, const Grid &g,
+                            const FftAxis &ay, hipStream_t s);
 // Forward z transform of planes 0 and 2, the spectral solve, inverse z:
 // plane0 <- F_z^-1[(F_z plane0 + j w_z F_z plane2) / |w|^2], DC -> 0.
-hipError_t launch_fft_z_solve(float2 *spec, const Grid &g, const FftAxis &az, hipStream_t s);
+// Planes with zocc[z] = 0 are read as zero.
+hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, const FftAxis &az,
+                              hipStream_t s);
 // Inverse y transform of plane 0.
 hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
 // Inverse real FFT along x of plane 0, scaled by 1/n -> A (Nz, Ny, Nx).

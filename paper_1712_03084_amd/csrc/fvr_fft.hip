@@ -54,6 +54,27 @@ __device__ __forceinline__ void prefetch(float4 (&v)[PF], const float2 *__restri
     }
 }
 
+// prefetch() for a tile whose rows t with keep[t] == 0 are known to be zero:
+// those rows are not read.
+template <int PF>
+__device__ __forceinline__ void prefetch_rows(float4 (&v)[PF], const float2 *__restrict__ src,
+                                              size_t stride, int len, int kx0, int H,
+                                              const uint8_t *keep) {
+    const int tot2 = len * (kChunk / 2);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int i = u * kPassThreads + threadIdx.x;
+        const int t = i / (kChunk / 2), c = 2 * (i % (kChunk / 2));
+        v[u] = (i < tot2 && kx0 + c < H && keep[t])
+                   ? *reinterpret_cast<const float4 *>(src + t * stride + kx0 + c)
+                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (kx0 + c + 1 >= H) {
+            v[u].z = 0.f;
+            v[u].w = 0.f;
+        }
+    }
+}
+
 template <int PF>
 __device__ __forceinline__ void commit(float2 *dst, const float4 (&v)[PF], int len) {
     const int tot2 = len * (kChunk / 2);
@@ -79,23 +100,38 @@ __device__ __forceinline__ void store_pencils(float2 *__restrict__ dstg, const f
 
 template <int PF>
 __global__ void __launch_bounds__(kPassThreads)
-fft_y_fwd_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
+fft_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
+                 uint8_t *__restrict__ zocc, Grid g, FftAxis ay) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
+    __shared__ uint8_t keep[kMaxDim];
+    __shared__ int any;
     const int Ny = g.n[1], H = g.H, Hp = g.Hp;
     const size_t plane = (size_t)g.n[2] * Ny * Hp;
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
+    // rows of this z plane that the splat wrote (their tile holds a point)
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const uint8_t *orow = occ + (size_t)(z / g.tz) * g.tiles_y;
+    for (int y = threadIdx.x; y < Ny; y += blockDim.x) {
+        const uint8_t o = orow[y / g.ty];
+        keep[y] = o;
+        if (o) any = 1;
+    }
+    __syncthreads();
+    if (chunk == 0 && threadIdx.x == 0) zocc[z] = any ? 1 : 0;
+    if (!any) return;  // an all-zero plane stays zero through the y transform
     float2 *A = lds, *B = lds + Ny * kChunk, *tw = lds + 2 * Ny * kChunk;
     const int tot = Ny * kChunk;
     const size_t zoff = (size_t)z * Ny * Hp;
     float4 va[PF], vb[PF], vc[PF];
-    prefetch<PF>(va, spec + zoff, Hp, Ny, k0, H);
-    prefetch<PF>(vb, spec + plane + zoff, Hp, Ny, k0, H);
+    prefetch_rows<PF>(va, spec + zoff, Hp, Ny, k0, H, keep);
+    prefetch_rows<PF>(vb, spec + plane + zoff, Hp, Ny, k0, H, keep);
     load_twiddles(tw, ay);
     commit<PF>(A, va, Ny);
     commit<PF>(B, vb, Ny);
-    prefetch<PF>(vc, spec + 2 * plane + zoff, Hp, Ny, k0, H);  // in flight during the transforms
+    prefetch_rows<PF>(vc, spec + 2 * plane + zoff, Hp, Ny, k0, H, keep);  // in flight during the transforms
     __syncthreads();
     fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, ay, tw, -1);
     fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, tw, -1);
@@ -115,9 +151,12 @@ fft_y_fwd_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
 
 template <int PF>
 __global__ void __launch_bounds__(kPassThreads)
-fft_z_solve_kernel(float2 *__restrict__ spec, Grid g, FftAxis az) {
+fft_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, Grid g, FftAxis az) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
+    __shared__ uint8_t keep[kMaxDim];
     const int Ny = g.n[1], Nz = g.n[2], H = g.H, Hp = g.Hp;
+    for (int z = threadIdx.x; z < Nz; z += blockDim.x) keep[z] = zocc[z];
+    __syncthreads();
     const size_t plane = (size_t)Nz * Ny * Hp;
     const size_t zstride = (size_t)Ny * Hp;
     const int nch = nchunks(H);
@@ -127,8 +166,8 @@ fft_z_solve_kernel(float2 *__restrict__ spec, Grid g, FftAxis az) {
     const int tot = Nz * kChunk;
     const size_t yoff = (size_t)ky * Hp;
     float4 va[PF], vb[PF];
-    prefetch<PF>(va, spec + yoff, zstride, Nz, k0, H);
-    prefetch<PF>(vb, spec + 2 * plane + yoff, zstride, Nz, k0, H);
+    prefetch_rows<PF>(va, spec + yoff, zstride, Nz, k0, H, keep);
+    prefetch_rows<PF>(vb, spec + 2 * plane + yoff, zstride, Nz, k0, H, keep);
     load_twiddles(tw, az);
     commit<PF>(A, va, Nz);
     commit<PF>(B, vb, Nz);
@@ -238,12 +277,12 @@ static int prefetch_depth(int len) {
     return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
 }
 
-#define FVR_PF_SWITCH(len, KERNEL, ...)                                                   \
+#define FVR_PF_SWITCH(len, KERNEL, ARGS, ...)                                             \
     switch (prefetch_depth(len)) {                                                        \
-        case 2: KERNEL<2><<<__VA_ARGS__>>>(spec, g, ax); break;                          \
-        case 4: KERNEL<4><<<__VA_ARGS__>>>(spec, g, ax); break;                          \
-        case 8: KERNEL<8><<<__VA_ARGS__>>>(spec, g, ax); break;                          \
-        default: KERNEL<16><<<__VA_ARGS__>>>(spec, g, ax); break;                        \
+        case 2: KERNEL<2><<<__VA_ARGS__>>> ARGS; break;                                  \
+        case 4: KERNEL<4><<<__VA_ARGS__>>> ARGS; break;                                  \
+        case 8: KERNEL<8><<<__VA_ARGS__>>> ARGS; break;                                  \
+        default: KERNEL<16><<<__VA_ARGS__>>> ARGS; break;                                \
     }
 
 hipError_t fft_configure() {
@@ -264,21 +303,26 @@ hipError_t fft_configure() {
 // pencil buffers plus the twiddle table
 static size_t pass_lds(int n, int bufs) { return ((size_t)bufs * n * kChunk + n) * sizeof(float2); }
 
-hipError_t launch_fft_y_fwd(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
+hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, const Grid &g,
+                            const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
-    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 2), s)
+    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, (spec, occ, zocc, g, ax), dim3(nch * g.n[2]),
+                  dim3(kPassThreads), pass_lds(g.n[1], 2), s)
     return hipGetLastError();
 }
 
-hipError_t launch_fft_z_solve(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
+hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, const FftAxis &ax,
+                              hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
-    FVR_PF_SWITCH(g.n[2], fft_z_solve_kernel, dim3(nch * g.n[1]), dim3(kPassThreads), pass_lds(g.n[2], 2), s)
+    FVR_PF_SWITCH(g.n[2], fft_z_solve_kernel, (spec, zocc, g, ax), dim3(nch * g.n[1]),
+                  dim3(kPassThreads), pass_lds(g.n[2], 2), s)
     return hipGetLastError();
 }
 
 hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
-    FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 1), s)
+    FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, (spec, g, ax), dim3(nch * g.n[2]), dim3(kPassThreads),
+                  pass_lds(g.n[1], 1), s)
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ namespace fvr {
 constexpr int kSplatThreads = 1024;
 constexpr int kSplatMaxPlane = 4096;  // voxels per channel plane of a tile, at most
 constexpr int kMaxBins = 128;   // (ty+3)(tz+3) footprint-origin bins per tile, at most
+constexpr int kChunkPts = 8;    // consecutive points of a bin per splat work item
 
 // Footprint origin floor((x - bmin)/h - 1/2) in float32, each operation
 // correctly rounded (no contraction), so every implementation that follows
@@ -152,29 +153,49 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
 // bit-reproducible.  V = (sigma2/sigma1) (S unit_S) / (D unit_D).
 // Work decomposition: the candidate points of a tile come in bins of equal
 // footprint origin (i0_y, i0_z), and all points of one bin reach the same
-// in-tile rows.  The block enumerates (bin, point, row) items - only rows
-// that exist in the tile - and each item adds one point's 4 x-voxels of one
-// row: 10 exponentials (4 x offsets and 1 (y, z) pair, two Gaussians) and 16
-// integer atomics, none masked off.
+// in-tile rows.  The block enumerates (bin, chunk of up to kChunkPts
+// consecutive points, row) items - only rows that exist in the tile.  Per
+// point an item spends 10 exponentials (4 x offsets and the (y, z) pair, two
+// Gaussians) on its 4 x-voxels of the row.
 template <bool CHUNKED>
 __global__ void __launch_bounds__(kSplatThreads)
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
-                   SplatConsts sc, FftAxis ax, const DevStatus *__restrict__ st,
-                   float2 *__restrict__ spec, float *__restrict__ v_out) {
+                   SplatConsts sc, FftAxis ax, DevStatus *__restrict__ st,
+                   float2 *__restrict__ spec, uint8_t *__restrict__ occ, float *__restrict__ v_out) {
     extern __shared__ unsigned long long acc[];
     __shared__ int b_start[kMaxBins], b_pre[kMaxBins + 1], b_rows[kMaxBins], b_ny[kMaxBins];
+    __shared__ int b_cnt[kMaxBins];
     __shared__ int b_qy[kMaxBins], b_qz[kMaxBins], b_iy[kMaxBins], b_iz[kMaxBins];
     __shared__ unsigned b_mrows[kMaxBins], b_mny[kMaxBins];
 
+    __shared__ int s_tile;
     const int Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
     const int TY = sc.ty, TZ = sc.tz, R = TY * TZ;
-    const int by = blockIdx.x % sc.tiles_y, bz = blockIdx.x / sc.tiles_y;
-    const int y0 = by * TY, z0 = bz * TZ;
+    const int ntiles = sc.tiles_y * ((Nz + TZ - 1) / TZ);
     const int plane = R * Nx;  // voxels per channel plane
     // int64 accumulators use a row pitch of Nx + 1: with Nx a multiple of the
     // bank count, an unpadded row would put a voxel's bank on x alone, and the
     // points of a tile cluster in x (the surface crossings)
     const int P = Nx + 1, aplane = R * P;
+    const int H = g.H, Hp = g.Hp;
+    const size_t pl = (size_t)Nz * Ny * Hp;
+    float2 *twl = reinterpret_cast<float2 *>(acc + 4 * aplane);
+    load_twiddles(twl, ax);
+    // fixed-point units: 2^(e-30) with max < 2^e, so every rounded term fits int32
+    int eS, eD;
+    (void)frexpf(__uint_as_float(st->wnmax_bits), &eS);
+    (void)frexpf(__uint_as_float(st->wmax_bits), &eD);
+    const float qS = ldexpf(1.0f, 30 - eS), qD = ldexpf(1.0f, 30 - eD);
+
+    // Persistent blocks (one per CU) claim tiles from a ticket counter, so the
+    // many tiles that no point reaches cost a few instructions each, not a launch.
+    for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&st->tile_ticket, 1);
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile >= ntiles) break;
+    const int by = tile % sc.tiles_y, bz = tile / sc.tiles_y;
+    const int y0 = by * TY, z0 = bz * TZ;
 
     // bins of footprint origins (iy, iz) whose 4-row footprints overlap the
     // tile: iy in [y0-2, y0+TY], iz in [z0-2, z0+TZ] (clipped to [-1, N-1])
@@ -188,7 +209,9 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         const int qz0 = max(iz - 1, z0), qz1 = min(min(iz + 2, z0 + TZ - 1), Nz - 1);
         const int ny = max(qy1 - qy0 + 1, 0), nz = max(qz1 - qz0 + 1, 0);
         const int cnt = bin_off[kb + 1] - bin_off[kb];
+        const int nchunk = (cnt + kChunkPts - 1) / kChunkPts;
         b_start[t] = bin_off[kb];
+        b_cnt[t] = cnt;
         b_rows[t] = ny * nz;
         b_ny[t] = max(ny, 1);
         b_qy[t] = qy0;
@@ -197,7 +220,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         b_iz[t] = iz;
         b_mrows[t] = div_magic(max(ny * nz, 1));
         b_mny[t] = div_magic(max(ny, 1));
-        b_pre[t + 1] = cnt * ny * nz;
+        b_pre[t + 1] = nchunk * ny * nz;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -206,16 +229,10 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     }
     __syncthreads();
     const int total = b_pre[nbins];
-    const int H = g.H, Hp = g.Hp;
-    const size_t pl = (size_t)Nz * Ny * Hp;
+    if (threadIdx.x == 0) occ[tile] = total > 0 ? 1 : 0;
     if (total == 0) {
-        // no point reaches this tile: V = 0 and so is its spectrum
-        for (int i = threadIdx.x; i < 3 * R * H; i += blockDim.x) {
-            const int rr = i / H, k = i - rr * H;
-            const int c = rr / R, r = rr - c * R;
-            const int y = y0 + r % TY, z = z0 + r / TY;
-            if (y < Ny && z < Nz) spec[c * pl + ((size_t)z * Ny + y) * Hp + k] = make_float2(0.f, 0.f);
-        }
+        // no point reaches this tile: V = 0 and so is its spectrum, which the
+        // y pass reads as zero from occ[] without it being stored
         if (v_out) {
             const size_t n = (size_t)Nx * Ny * Nz;
             for (int i = threadIdx.x; i < 3 * plane; i += blockDim.x) {
@@ -225,17 +242,10 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
                 if (qy < Ny && qz < Nz) v_out[c * n + qx + (size_t)Nx * (qy + (size_t)Ny * qz)] = 0.f;
             }
         }
-        return;
+        __syncthreads();  // the bin tables are rebuilt for the next tile
+        continue;
     }
     for (int i = threadIdx.x; i < 4 * aplane; i += blockDim.x) acc[i] = 0ull;
-    float2 *twl = reinterpret_cast<float2 *>(acc + 4 * aplane);
-    load_twiddles(twl, ax);
-
-    // fixed-point units: 2^(e-30) with max < 2^e, so every rounded term fits int32
-    int eS, eD;
-    (void)frexpf(__uint_as_float(st->wnmax_bits), &eS);
-    (void)frexpf(__uint_as_float(st->wmax_bits), &eD);
-    const float qS = ldexpf(1.0f, 30 - eS), qD = ldexpf(1.0f, 30 - eD);
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
@@ -260,7 +270,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     // moves to a later bin.  (An LDS read in the steady-state loop would wait
     // for the previous item's queued atomics: LDS operations retire in order.)
     struct BinState {
-        int b, lo, hi, start, rows, ny, qy0, qz0, iy, iz;
+        int b, lo, hi, start, cnt, rows, ny, qy0, qz0, iy, iz;
         unsigned mrows, mny;
     };
     auto enter_bin = [&](BinState &st, int b) {
@@ -268,6 +278,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         st.lo = b_pre[b];
         st.hi = b_pre[b + 1];
         st.start = b_start[b];
+        st.cnt = b_cnt[b];
         st.rows = b_rows[b];
         st.ny = b_ny[b];
         st.qy0 = b_qy[b];
@@ -287,66 +298,86 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         }
         enter_bin(bs, lo);
     }
-    // decode item jj (in bin bs, advancing it as needed) into point index and row
-    auto decode = [&](int jj, int &p, int &qy, int &qz, int &iy, int &iz) {
+    // decode item jj (in bin bs, advancing it as needed): its chunk of points
+    // [p, p + len) and its row (qy, qz)
+    auto decode = [&](int jj, int &p, int &len, int &qy, int &qz, int &iy, int &iz) {
         while (jj >= bs.hi) enter_bin(bs, bs.b + 1);
         const int local = jj - bs.lo;
-        const int pi = udiv(local, bs.rows, bs.mrows);
-        const int r = local - pi * bs.rows;
+        const int ci = udiv(local, bs.rows, bs.mrows);
+        const int r = local - ci * bs.rows;
         const int rzi = udiv(r, bs.ny, bs.mny);
-        p = bs.start + pi;
+        p = bs.start + ci * kChunkPts;
+        len = min(kChunkPts, bs.cnt - ci * kChunkPts);
         qz = bs.qz0 + rzi;
         qy = bs.qy0 + (r - rzi * bs.ny);
         iy = bs.iy;
         iz = bs.iz;
     };
 
-    int p = 0, qy = 0, qz = 0, iy = 0, iz = 0;
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-    if (j >= 0) {
-        decode(j, p, qy, qz, iy, iz);
-        r0 = rec[2 * p];
-        r1 = rec[2 * p + 1];
-    }
-    while (j >= 0) {
-        const int jn = item(k + 1);
-        int pn = p, qyn = qy, qzn = qz, iyn = iy, izn = iz;
-        float4 n0 = r0, n1 = r1;
-        if (jn >= 0) {  // prefetch the next item's record while this one is splatted
-            decode(jn, pn, qyn, qzn, iyn, izn);
-            n0 = rec[2 * pn];
-            n1 = rec[2 * pn + 1];
-        }
-        // offsets of this row's centre and of the 4 x centres from the point, in voxels
-        const float dy = r0.y + (float)(iy - qy);
-        const float dz = r0.z + (float)(iz - qz);
-        const float a1 = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy + sc.e1[2] * dz * dz);
-        const float a2 = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy + sc.e2[2] * dz * dz) * (r0.w * qD);
-        const float sx = a1 * r1.x * qS, sy = a1 * r1.y * qS, sz = a1 * r1.z * qS;
-        const int ix = __float_as_int(r1.w);
-        const int row = (qz - z0) * TY + (qy - y0);
+    // Points of one chunk that share a footprint cell (consecutive equal i0_x;
+    // capture order keeps neighbouring samples together) are summed in int64
+    // registers - exact, so the order of summation cannot matter - and reach
+    // LDS as one atomic per voxel and channel when the cell changes.
+    long long run[4][4];
+    int run_ix = 0, run_row = 0;
+    auto flush = [&]() {
 #pragma unroll
         for (int ox = 0; ox < 4; ++ox) {
-            const int qx = ix + ox - 1;
-            if (qx < 0 || qx >= Nx) continue;
-            const float dx = r0.x - (float)(ox - 1);
-            const float g1 = __builtin_amdgcn_exp2f(sc.e1[0] * dx * dx);
-            const float g2 = __builtin_amdgcn_exp2f(sc.e2[0] * dx * dx);
-            const int l = row * P + qx;
-            atomicAdd(&acc[l], (unsigned long long)(long long)__float2int_rn(g1 * sx));
-            atomicAdd(&acc[aplane + l], (unsigned long long)(long long)__float2int_rn(g1 * sy));
-            atomicAdd(&acc[2 * aplane + l], (unsigned long long)(long long)__float2int_rn(g1 * sz));
-            atomicAdd(&acc[3 * aplane + l], (unsigned long long)(long long)__float2int_rn(g2 * a2));
+            const int qx = run_ix + ox - 1;
+            if (qx >= 0 && qx < Nx) {
+                const int l = run_row * P + qx;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (run[ox][c] != 0) atomicAdd(&acc[c * aplane + l], (unsigned long long)run[ox][c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) run[ox][c] = 0;
         }
-        r0 = n0;
-        r1 = n1;
-        j = jn;
-        p = pn;
-        qy = qyn;
-        qz = qzn;
-        iy = iyn;
-        iz = izn;
-        ++k;
+    };
+#pragma unroll
+    for (int ox = 0; ox < 4; ++ox)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) run[ox][c] = 0;
+
+    while (j >= 0) {
+        int p, len, qy, qz, iy, iz;
+        decode(j, p, len, qy, qz, iy, iz);
+        const int row = (qz - z0) * TY + (qy - y0);
+        float4 r0 = rec[2 * p], r1 = rec[2 * p + 1];
+        run_ix = __float_as_int(r1.w);
+        run_row = row;
+        for (int t = 0; t < len; ++t) {
+            float4 n0 = r0, n1 = r1;
+            if (t + 1 < len) {  // prefetch the chunk's next record
+                n0 = rec[2 * (p + t + 1)];
+                n1 = rec[2 * (p + t + 1) + 1];
+            }
+            const int ix = __float_as_int(r1.w);
+            if (ix != run_ix) {
+                flush();
+                run_ix = ix;
+            }
+            // offsets of this row's centre and of the 4 x centres from the point, in voxels
+            const float dy = r0.y + (float)(iy - qy);
+            const float dz = r0.z + (float)(iz - qz);
+            const float a1 = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy + sc.e1[2] * dz * dz);
+            const float a2 = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy + sc.e2[2] * dz * dz) * (r0.w * qD);
+            const float sx = a1 * r1.x * qS, sy = a1 * r1.y * qS, sz = a1 * r1.z * qS;
+#pragma unroll
+            for (int ox = 0; ox < 4; ++ox) {
+                const float dx = r0.x - (float)(ox - 1);
+                const float g1 = __builtin_amdgcn_exp2f(sc.e1[0] * dx * dx);
+                const float g2 = __builtin_amdgcn_exp2f(sc.e2[0] * dx * dx);
+                run[ox][0] += __float2int_rn(g1 * sx);
+                run[ox][1] += __float2int_rn(g1 * sy);
+                run[ox][2] += __float2int_rn(g1 * sz);
+                run[ox][3] += __float2int_rn(g2 * a2);
+            }
+            r0 = n0;
+            r1 = n1;
+        }
+        flush();
+        j = item(++k);
     }
     __syncthreads();
 
@@ -423,17 +454,29 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         if (ya < Ny && za < Nz) spec[c * pl + ((size_t)za * Ny + ya) * Hp + kx] = xa;
         if (yb < Ny && zb < Nz) spec[c * pl + ((size_t)zb * Ny + yb) * Hp + kx] = xb;
     }
+    __syncthreads();  // LDS is reused by the next tile
+    }
 }
 
 #ifndef FVR_SPLAT_CHUNKED
 #define FVR_SPLAT_CHUNKED true
 #endif
 
+static int g_splat_blocks = 256;
+
 hipError_t splat_configure() {
     hipError_t e = raise_dynamic_lds((const void *)splat_fft_x_kernel<true>);
     if (e != hipSuccess) return e;
-    return raise_dynamic_lds((const void *)splat_fft_x_kernel<false>);
+    e = raise_dynamic_lds((const void *)splat_fft_x_kernel<false>);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && cus > 0) g_splat_blocks = cus;  // one persistent block per CU
+    return e;
 }
+
+int splat_blocks() { return g_splat_blocks; }
 
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
     return (size_t)4 * sc.ty * sc.tz * (g.n[0] + 1) * sizeof(unsigned long long) +
@@ -459,12 +502,13 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 }
 
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
-                              const SplatConsts &sc, const FftAxis &ax, const DevStatus *st,
-                              float2 *spec, float *v_out, hipStream_t s) {
+                              const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
+                              float2 *spec, uint8_t *occ, float *v_out, hipStream_t s) {
     const int tiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
+    const int blocks = tiles < g_splat_blocks ? tiles : g_splat_blocks;
     const size_t lds = splat_lds_bytes(g, sc);
-    splat_fft_x_kernel<FVR_SPLAT_CHUNKED><<<dim3(tiles), dim3(kSplatThreads), lds, s>>>(
-        rec, bin_off, g, sc, ax, st, spec, v_out);
+    splat_fft_x_kernel<FVR_SPLAT_CHUNKED><<<dim3(blocks), dim3(kSplatThreads), lds, s>>>(
+        rec, bin_off, g, sc, ax, st, spec, occ, v_out);
     return hipGetLastError();
 }
 

@@ -9,8 +9,10 @@ on a 256^3 grid over a 2.0 m box.  Prints ONE JSON line.
                   [--no-cpu-baseline]
 
 Per-kernel durations come from HIP events the library records on its stream
-around every launch inside the timed region; the dominant kernel's roofline
-uses its algorithmic bytes (defined inputs read once, outputs written once).
+around every launch, in an untimed pass after the warmup; that pass names the
+dominant kernel.  Inside the timed region events surround that kernel only,
+and its roofline uses its average duration there and its algorithmic bytes
+(defined inputs read once, outputs written once).
 """
 from __future__ import annotations
 
@@ -57,6 +59,49 @@ def kernel_alg_bytes(dims, m, nv, nt):
     }
 
 
+# Source files each kernel is compiled from (plus the shared headers and the
+# build flags): a stored counter reading is used only while these are unchanged.
+_CSRC = os.path.join(ROOT, "paper_1712_03084_amd", "csrc")
+KERNEL_SOURCES = {
+    "prep": "fvr_mc.hip", "bin_count": "fvr_splat.hip", "bin_scan": "fvr_mc.hip",
+    "bin_scatter": "fvr_splat.hip", "splat_fft_x": "fvr_splat.hip", "fft_y_fwd": "fvr_fft.hip",
+    "fft_z_solve": "fvr_fft.hip", "fft_y_inv": "fvr_fft.hip", "fft_x_c2r": "fvr_fft.hip",
+    "level": "fvr_mc.hip", "mc_count": "fvr_mc.hip", "mc_scan": "fvr_mc.hip",
+    "mc_generate": "fvr_mc.hip", "mc_triangles": "fvr_mc.hip",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_proxy256.txt")
+
+
+def kernel_source_digest(name):
+    """sha256 over the kernel's source file, the shared device headers and the
+    build script (first 16 hex digits)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (os.path.join(_CSRC, KERNEL_SOURCES[name]), os.path.join(_CSRC, "fvr_common.h"),
+              os.path.join(_CSRC, "fvr_fft_engine.h"),
+              os.path.join(ROOT, "paper_1712_03084_amd", "build.py")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(name, config):
+    """HBM bytes per launch of `name` from the stored rocprofv3 FETCH_SIZE and
+    WRITE_SIZE readings (scaled by the plain-copy calibration), or None when
+    there is no reading for this kernel and workload or its sources changed
+    since the reading was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = kernel_source_digest(name)
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            # kernel workload fetch_bytes write_bytes traffic_bytes digest
+            if len(f) == 6 and f[0] == name and f[1] == config and f[5] == digest:
+                return int(f[4])
+    return None
+
+
 def frame_alg_bytes(dims, m, nv, nt):
     """Whole-frame algorithmic bytes: each stage of the method reads its
     defined input once and writes its output once (8F + 8S + 40m + mesh)."""
@@ -91,6 +136,8 @@ def main():
     ap.add_argument("--pool", type=int, default=2, help="distinct seeded frames cycled through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--breakdown", type=int, default=20,
+                    help="untimed frames with events around every kernel, for the per-kernel table")
     ap.add_argument("--calib-copy", action="store_true",
                     help="before the timed region, copy a 256 MiB float32 buffer once (a plain copy "
                          "kernel of known size, for scaling profiler byte counters)")
@@ -134,8 +181,24 @@ def main():
         ctx.reconstruct(*pool[k % len(pool)], grid_dim=dims, bbox=bbox, out=out)
     torch.cuda.synchronize()
 
-    ctx.timing(not args.no_kernel_timing)
-    ctx.timing_reset()
+    # Per-kernel breakdown from an untimed pass with events around every
+    # launch; it names the dominant kernel.
+    kernels = {}
+    dom = None
+    if not args.no_kernel_timing:
+        ctx.timing(True)
+        ctx.timing_reset()
+        for k in range(args.breakdown):
+            ctx.reconstruct(*pool[k % len(pool)], grid_dim=dims, bbox=bbox, out=out)
+        torch.cuda.synchronize()
+        for name, (ms, cnt) in ctx.timings().items():
+            if cnt:
+                kernels[name] = {"avg_us": round(ms / cnt * 1e3, 2), "launches": cnt}
+        dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
+        # inside the timed region only the dominant kernel carries events
+        ctx.timing_select([dom])
+        ctx.timing_reset()
+
     lat = []
     nv_tot = nt_tot = 0
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
@@ -156,20 +219,17 @@ def main():
     nv_avg = nv_tot / args.steps
     nt_avg = nt_tot / args.steps
 
-    kernels = {}
     roof = None
-    if not args.no_kernel_timing:
-        tim = ctx.timings()
+    if dom is not None:
+        ms, cnt = ctx.timings()[dom]
         alg = kernel_alg_bytes(dims, m, nv_avg, nt_avg)
-        for name, (ms, cnt) in tim.items():
-            if cnt:
-                kernels[name] = {"avg_us": round(ms / cnt * 1e3, 2), "launches": cnt}
-        dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
-        avg_s = kernels[dom]["avg_us"] * 1e-6
+        avg_s = ms / cnt * 1e-3
         ach = alg.get(dom, 0) / avg_s / 1e9 if avg_s > 0 else 0.0
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "alg_bytes_per_launch": alg.get(dom, 0)}
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic(dom, args.config),
+                "alg_bytes_per_launch": alg.get(dom, 0),
+                "avg_us_timed_region": round(ms / cnt * 1e3, 2), "launches": cnt}
 
     fb = frame_alg_bytes(dims, m, nv_avg, nt_avg)
     result = {

@@ -135,8 +135,12 @@ fvr_status fvr_check_grid(const int32_t dims[3], const float bbox[6]);
 fvr_status fvr_mc_table(uint8_t counts[256], int8_t edges[256 * 15]);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch (off by default).  Index i in [0, fvr_timing_count()). */
+ * the launches of the selected kernels (off by default).  Index i in
+ * [0, fvr_timing_count()).  fvr_timing_enable selects all kernels (enable != 0)
+ * or none; fvr_timing_select selects kernel i when bit i of mask is set, so a
+ * caller can time one kernel without paying for events around the others. */
 fvr_status fvr_timing_enable(fvr_ctx *ctx, int enable);
+fvr_status fvr_timing_select(fvr_ctx *ctx, uint32_t mask);
 fvr_status fvr_timing_reset(fvr_ctx *ctx);
 int fvr_timing_count(void);
 const char *fvr_timing_name(int i);

@@ -88,6 +88,7 @@ def load_library():
     lib.fvr_check_grid.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
     lib.fvr_mc_table.argtypes = [P, P]
     lib.fvr_timing_enable.argtypes = [P, I]
+    lib.fvr_timing_select.argtypes = [P, ctypes.c_uint32]
     lib.fvr_timing_reset.argtypes = [P]
     lib.fvr_timing_count.argtypes = []
     lib.fvr_timing_name.argtypes = [I]
@@ -99,7 +100,7 @@ def load_library():
     lib.fvr_last_error.restype = ctypes.c_char_p
     for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_indicator", "fvr_extract",
                "fvr_debug_splat", "fvr_check_grid", "fvr_mc_table", "fvr_timing_enable",
-               "fvr_timing_reset", "fvr_timing_get"):
+               "fvr_timing_select", "fvr_timing_reset", "fvr_timing_get"):
         getattr(lib, fn).restype = I
     _lib = lib
     return lib
@@ -292,6 +293,14 @@ class Context:
     # -- timing -------------------------------------------------------------
     def timing(self, enable: bool = True):
         _check(self.lib, self.lib.fvr_timing_enable(self.handle, 1 if enable else 0), self.handle)
+
+    def timing_select(self, names):
+        """Record HIP events around the named kernels only."""
+        index = {self.lib.fvr_timing_name(i).decode(): i for i in range(self.lib.fvr_timing_count())}
+        mask = 0
+        for n in names:
+            mask |= 1 << index[n]
+        _check(self.lib, self.lib.fvr_timing_select(self.handle, ctypes.c_uint32(mask)), self.handle)
 
     def timing_reset(self):
         _check(self.lib, self.lib.fvr_timing_reset(self.handle), self.handle)

@@ -71,7 +71,7 @@ struct fvr_ctx {
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off,
         lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc;
     DevStatus *host_status = nullptr;
-    bool timing = false;
+    uint32_t timing_mask = 0;  // bit k: time kernel k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<int> ev_kid;
     size_t ev_used = 0;
@@ -118,7 +118,7 @@ struct Timed {
     int kid;
     size_t idx = (size_t)-1;
     Timed(fvr_ctx *ctx, int k) : c(ctx), kid(k) {
-        if (!c->timing) return;
+        if (!((c->timing_mask >> k) & 1u)) return;
         if (c->ev_used == c->ev.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return;
@@ -148,7 +148,7 @@ void collect_timing(fvr_ctx *c) {
 
 fvr_status sync(fvr_ctx *c) {
     HIP_TRY(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-    if (c->timing) collect_timing(c);
+    if (c->ev_used) collect_timing(c);
     return FVR_OK;
 }
 
@@ -215,7 +215,8 @@ fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan
             factor(dims[a], r);
             np.ax[a].n = dims[a];
             np.ax[a].nstages = (int)r.size();
-            for (int s = 0; s < kMaxStages; ++s) np.ax[a].radix[s] = s < (int)r.size() ? r[s] : 1;
+            np.ax[a].radices = 0;
+            for (int s = 0; s < (int)r.size(); ++s) np.ax[a].radices |= (unsigned)r[s] << (4 * s);
             offs.push_back(tab.size());
             for (int t = 0; t < dims[a]; ++t) {
                 const double ang = 2.0 * M_PI * (double)t / (double)dims[a];
@@ -345,6 +346,23 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
     { Timed t(c, K_MC_SCAN);
       HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3,
                              P<int32_t>(c->scan_part), st->mc_total, s), "mc_scan"); }
+    // Generation follows without a host round trip: the kernels check the
+    // totals against the capacities themselves and write nothing on a shortfall.
+    const long long ncell_max = (long long)(g.n[0] - 1) * (g.n[1] - 1) * (g.n[2] - 1);
+    MeshCaps caps;
+    caps.vertices = mesh->vertices ? mesh->vertex_capacity : 0;
+    caps.triangles = mesh->triangles ? mesh->triangle_capacity : 0;
+    // every active cell emits at least one triangle
+    caps.cells = std::max(0LL, std::min((long long)caps.triangles, ncell_max));
+    caps.check_invalid = check_invalid ? 1 : 0;
+    HIP_TRY(c, ensure(c->cells, sizeof(int4) * (size_t)std::max(1LL, caps.cells)), "alloc active cells");
+    { Timed t(c, K_MC_GENERATE);
+      HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_off),
+                                    mesh->vertices, P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, s),
+              "mc_generate"); }
+    { Timed t(c, K_MC_TRIANGLES);
+      HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), P<int32_t>(c->vidx), g, mesh->triangles, st,
+                                     caps, s), "mc_triangles"); }
     HIP_TRY(c, hipMemcpyAsync(c->host_status, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s),
             "status readback");
     fvr_status r = sync(c);
@@ -360,18 +378,7 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
         return fail(c, FVR_E_CAPACITY, "mesh output capacity too small");
     if (hs.mc_total[0] > 0 && !mesh->vertices) return fail(c, FVR_E_INVALID, "vertices is NULL");
     if (hs.mc_total[1] > 0 && !mesh->triangles) return fail(c, FVR_E_INVALID, "triangles is NULL");
-    const int ncells = hs.mc_total[2];
-    HIP_TRY(c, ensure(c->cells, sizeof(int4) * (size_t)ncells), "alloc active cells");
-    if (hs.mc_total[0] > 0) {
-        { Timed t(c, K_MC_GENERATE);
-          HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_off),
-                                        mesh->vertices, P<int32_t>(c->vidx), P<int4>(c->cells), s),
-                  "mc_generate"); }
-        { Timed t(c, K_MC_TRIANGLES);
-          HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), ncells, P<int32_t>(c->vidx), g,
-                                         mesh->triangles, s), "mc_triangles"); }
-    }
-    return sync(c);
+    return FVR_OK;
 }
 
 }  // namespace
@@ -529,7 +536,13 @@ fvr_status fvr_mc_table(uint8_t counts[256], int8_t edges[256 * 15]) {
 
 fvr_status fvr_timing_enable(fvr_ctx *c, int enable) {
     if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
-    c->timing = enable != 0;
+    c->timing_mask = enable ? (1u << K_COUNT) - 1u : 0u;
+    return FVR_OK;
+}
+
+fvr_status fvr_timing_select(fvr_ctx *c, uint32_t mask) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    c->timing_mask = mask & ((1u << K_COUNT) - 1u);
     return FVR_OK;
 }
 

@@ -28,7 +28,9 @@ inline hipError_t raise_dynamic_lds(const void *kernel) {
 struct FftAxis {
     int n;
     int nstages;
-    int radix[kMaxStages];
+    // radix of stage s in bits [4s, 4s + 4): a packed word, since a dynamically
+    // indexed array in a kernel argument is copied to per-lane scratch memory
+    unsigned radices;
     const float2 *tw;
 };
 
@@ -141,11 +143,18 @@ int mc_blocks(const Grid &g);
 hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
                            int32_t *blk_counts, uint8_t *cases_out, DevStatus *st,
                            hipStream_t s);
+// The mesh kernels read the totals of the count scan from `st`; they write
+// nothing when a total exceeds its capacity (vertices, triangles, active
+// cells) or the frame was flagged invalid.
+struct MeshCaps {
+    long long vertices, triangles, cells;
+    int check_invalid;
+};
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
-                              const int32_t *blk_offsets, float *verts, int32_t *vidx,
-                              int4 *cells, hipStream_t s);
-hipError_t launch_mc_triangles(const int4 *cells, int n_cells, const int32_t *vidx,
-                               const Grid &g, int32_t *tris, hipStream_t s);
+                              const int32_t *blk_offsets, float *verts, int32_t *vidx, int4 *cells,
+                              const DevStatus *st, MeshCaps caps, hipStream_t s);
+hipError_t launch_mc_triangles(const int4 *cells, const int32_t *vidx, const Grid &g, int32_t *tris,
+                               const DevStatus *st, MeshCaps caps, hipStream_t s);
 
 // Raise the dynamic-LDS limit of the kernels that stage tiles above 64 KiB.
 hipError_t splat_configure();

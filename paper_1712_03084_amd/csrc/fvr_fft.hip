@@ -271,6 +271,289 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register pencils, for transform lengths N = N1 N2 with N2 dividing N1
+// (16, 32, 64, 128, 256).  A block of 16 N2 threads transforms the 16 columns
+// of one chunk; thread (c, t) = (tid % 16, tid / 16) holds N1 elements of
+// column c in registers:
+//   input    x[n1] = row t + N2 n1, read straight from the spectrum (for a
+//            fixed register the 16 lanes of a row read 128 contiguous bytes)
+//   step 1   N1-point DFT over n1, then the twiddle w_N^(t k1)
+//   LDS      one exchange: thread t takes k1 = t + N2 q (q < Q = N1 / N2)
+//   step 2   N2-point DFTs over n2
+//   output   x[q N2 + k2] = X[k1 + N1 k2] = row t + N2 (q + Q k2)
+// The output rows of thread t have the input form t + N2 m again
+// (m = q + Q k2), so an inverse transform starts from the registers after a
+// register permutation.
+template <int N1, int N2>
+struct Pencil {
+    static constexpr int N = N1 * N2, Q = N1 / N2, THREADS = 16 * N2;
+    // LDS stride of one k1 group: 16 columns per n2 plus 16 padding values,
+    // so the four row groups of a wave's read fall in alternate bank halves
+    static constexpr int KS = 16 * N2 + 16;
+    static constexpr int EX = N1 * KS;
+    static_assert(N1 % N2 == 0, "N2 must divide N1");
+
+    __device__ __forceinline__ static int in_row(int t, int n1) { return t + N2 * n1; }
+    __device__ __forceinline__ static int out_row(int t, int i) {
+        return t + N2 * (i / N2 + Q * (i % N2));
+    }
+
+    // Transform the block's columns; `tw` holds w_N^m = exp(-2 pi i m / N),
+    // m < N; `ex` is free for reuse when this returns.
+    template <int DIR>
+    __device__ __forceinline__ static void run(float2 (&x)[N1], float2 *ex, const float2 *tw, int c,
+                                               int t) {
+        Dft<N1>::run(x, DIR);
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1) {
+            float2 w = tw[t * k1];
+            if (DIR > 0) w.y = -w.y;
+            x[k1] = cmul(x[k1], w);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) ex[k1 * KS + t * 16 + c] = x[k1];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) x[q * N2 + n2] = ex[(t + N2 * q) * KS + n2 * 16 + c];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Dft<N2>::run(x + q * N2, DIR);
+    }
+
+    // Output register q N2 + k2 becomes input register q + Q k2.
+    __device__ __forceinline__ static void to_input(float2 (&x)[N1]) {
+        float2 y[N1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) y[i / N2 + Q * (i % N2)] = x[i];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) x[i] = y[i];
+    }
+};
+
+template <int N1, int N2>
+__global__ void __launch_bounds__(16 * N2)
+pen_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
+                 uint8_t *__restrict__ zocc, Grid g, const float2 *__restrict__ twg) {
+    using Pn = Pencil<N1, N2>;
+    constexpr int N = Pn::N;  // = Ny
+    __shared__ float2 ex[Pn::EX];
+    __shared__ float2 tw[N];
+    __shared__ uint8_t keep[N];
+    __shared__ int any;
+    const int H = g.H, Hp = g.Hp;
+    const size_t plane = (size_t)g.n[2] * N * Hp;
+    const int nch = nchunks(H);
+    const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
+    const int k0 = chunk * kChunk;
+    const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
+    // rows of this z plane that the splat wrote (their tile holds a point)
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const uint8_t *orow = occ + (size_t)(z / g.tz) * g.tiles_y;
+    for (int y = threadIdx.x; y < N; y += Pn::THREADS) {
+        const uint8_t o = orow[y / g.ty];
+        keep[y] = o;
+        if (o) any = 1;
+    }
+    for (int i = threadIdx.x; i < N; i += Pn::THREADS) tw[i] = twg[i];
+    __syncthreads();
+    if (chunk == 0 && threadIdx.x == 0) zocc[z] = any ? 1 : 0;
+    if (!any) return;  // an all-zero plane stays zero through the y transform
+    const bool col = k0 + c < H;
+    float2 *p = spec + (size_t)z * N * Hp + k0 + c;
+    float2 a[N1], b[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+        const int r = Pn::in_row(t, n1);
+        const bool ld = col && keep[r];
+        a[n1] = ld ? p[(size_t)r * Hp] : make_float2(0.f, 0.f);
+        b[n1] = ld ? p[plane + (size_t)r * Hp] : make_float2(0.f, 0.f);
+    }
+    Pn::template run<-1>(a, ex, tw, c, t);
+    Pn::template run<-1>(b, ex, tw, c, t);
+    // P0 <- F_y P0 + j w_y F_y P1
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const int r = Pn::out_row(t, i);
+        const float w = deriv_w(r, N, g.wstep[1]);
+        if (col) p[(size_t)r * Hp] = make_float2(a[i].x - w * b[i].y, a[i].y + w * b[i].x);
+    }
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+        const int r = Pn::in_row(t, n1);
+        b[n1] = (col && keep[r]) ? p[2 * plane + (size_t)r * Hp] : make_float2(0.f, 0.f);
+    }
+    Pn::template run<-1>(b, ex, tw, c, t);
+#pragma unroll
+    for (int i = 0; i < N1; ++i)
+        if (col) p[2 * plane + (size_t)Pn::out_row(t, i) * Hp] = b[i];
+}
+
+template <int N1, int N2>
+__global__ void __launch_bounds__(16 * N2)
+pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, Grid g,
+                   const float2 *__restrict__ twg) {
+    using Pn = Pencil<N1, N2>;
+    constexpr int N = Pn::N;  // = Nz
+    __shared__ float2 ex[Pn::EX];
+    __shared__ float2 tw[N];
+    __shared__ uint8_t keep[N];
+    const int Ny = g.n[1], H = g.H, Hp = g.Hp;
+    for (int i = threadIdx.x; i < N; i += Pn::THREADS) {
+        keep[i] = zocc[i];
+        tw[i] = twg[i];
+    }
+    __syncthreads();
+    const size_t plane = (size_t)N * Ny * Hp;
+    const size_t zs = (size_t)Ny * Hp;
+    const int nch = nchunks(H);
+    const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
+    const int k0 = chunk * kChunk;
+    const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
+    const bool col = k0 + c < H;
+    float2 *p = spec + (size_t)ky * Hp + k0 + c;
+    float2 a[N1], b[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+        const int r = Pn::in_row(t, n1);
+        const bool ld = col && keep[r];
+        a[n1] = ld ? p[(size_t)r * zs] : make_float2(0.f, 0.f);
+        b[n1] = ld ? p[2 * plane + (size_t)r * zs] : make_float2(0.f, 0.f);
+    }
+    Pn::template run<-1>(a, ex, tw, c, t);
+    Pn::template run<-1>(b, ex, tw, c, t);
+    // (F_z P0 + j w_z F_z P2) / |w|^2, zero at the DC bin
+    const float wx = (float)kappa(k0 + c, g.n[0]) * g.wstep[0];
+    const float wy = (float)kappa(ky, Ny) * g.wstep[1];
+    const float wxy = wx * wx + wy * wy;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const int kz = Pn::out_row(t, i);
+        const float wzf = (float)kappa(kz, N) * g.wstep[2];
+        const float w2 = wxy + wzf * wzf;
+        const float inv = w2 > 0.f ? 1.0f / w2 : 0.0f;
+        const float wz = deriv_w(kz, N, g.wstep[2]);
+        a[i] = make_float2((a[i].x - wz * b[i].y) * inv, (a[i].y + wz * b[i].x) * inv);
+    }
+    Pn::to_input(a);
+    Pn::template run<+1>(a, ex, tw, c, t);
+#pragma unroll
+    for (int i = 0; i < N1; ++i)
+        if (col) p[(size_t)Pn::out_row(t, i) * zs] = a[i];
+}
+
+template <int N1, int N2>
+__global__ void __launch_bounds__(16 * N2)
+pen_y_inv_kernel(float2 *__restrict__ spec, Grid g, const float2 *__restrict__ twg) {
+    using Pn = Pencil<N1, N2>;
+    constexpr int N = Pn::N;  // = Ny
+    __shared__ float2 ex[Pn::EX];
+    __shared__ float2 tw[N];
+    for (int i = threadIdx.x; i < N; i += Pn::THREADS) tw[i] = twg[i];
+    __syncthreads();
+    const int H = g.H, Hp = g.Hp;
+    const int nch = nchunks(H);
+    const int chunk = blockIdx.x % nch, z = blockIdx.x / nch;
+    const int k0 = chunk * kChunk;
+    const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
+    const bool col = k0 + c < H;
+    float2 *p = spec + (size_t)z * N * Hp + k0 + c;
+    float2 a[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1)
+        a[n1] = col ? p[(size_t)Pn::in_row(t, n1) * Hp] : make_float2(0.f, 0.f);
+    Pn::template run<+1>(a, ex, tw, c, t);
+#pragma unroll
+    for (int i = 0; i < N1; ++i)
+        if (col) p[(size_t)Pn::out_row(t, i) * Hp] = a[i];
+}
+
+// Inverse real transform along x for pencil lengths: a block takes 32 real
+// rows (a, b) = (row0 + 2c, row0 + 2c + 1), c < 16, packed as complex rows
+// Z_c[k] = X_a[k] + i X_b[k] (X[k] = conj X[N-k] above N/2; the imaginary
+// parts of bins 0 and N/2 dropped), transforms the 16 columns as a pencil and
+// writes Re -> row a, Im -> row b.  Spectra are read once each (both Z[k] and
+// Z[N-k] come from the pair at k) and the real rows leave through LDS as
+// 16-byte stores.
+template <int N1, int N2>
+__global__ void __launch_bounds__(16 * N2)
+pen_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
+                 const float2 *__restrict__ twg, float scale) {
+    using Pn = Pencil<N1, N2>;
+    constexpr int N = Pn::N;  // = Nx
+    constexpr int ZP = N + 1;       // LDS pitch of a packed complex row (float2)
+    constexpr int OP = N + 4;       // LDS pitch of a real output row (float)
+    constexpr int BUF = Pn::EX > 16 * ZP ? Pn::EX : 16 * ZP;
+    static_assert(BUF * 2 >= 32 * OP, "output staging fits the buffer");
+    __shared__ __attribute__((aligned(16))) float2 buf[BUF];
+    __shared__ float2 tw[N];
+    for (int i = threadIdx.x; i < N; i += Pn::THREADS) tw[i] = twg[i];
+    const int Hp = g.Hp, H = N / 2 + 1;
+    const int nrows = g.n[1] * g.n[2];
+    const int row0 = blockIdx.x * 32;
+    for (int i = threadIdx.x; i < 16 * H; i += Pn::THREADS) {
+        const int c = i / H, k = i - c * H;
+        const int ra = row0 + 2 * c;
+        float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
+        if (ra < nrows) {
+            a = spec[(size_t)ra * Hp + k];
+            b = spec[(size_t)(ra + 1) * Hp + k];
+        }
+        if (k == 0 || k == N / 2) {
+            a.y = 0.f;
+            b.y = 0.f;
+        }
+        buf[c * ZP + k] = make_float2(a.x - b.y, a.y + b.x);
+        if (k > 0 && k < N / 2) buf[c * ZP + N - k] = make_float2(a.x + b.y, b.x - a.y);
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
+    float2 x[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) x[n1] = buf[c * ZP + Pn::in_row(t, n1)];
+    __syncthreads();  // buf becomes the exchange buffer
+    Pn::template run<+1>(x, buf, tw, c, t);
+    float *ob = reinterpret_cast<float *>(buf);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const int k = Pn::out_row(t, i);
+        ob[(2 * c) * OP + k] = x[i].x * scale;
+        ob[(2 * c + 1) * OP + k] = x[i].y * scale;
+    }
+    __syncthreads();
+    constexpr int Q4 = N / 4;  // float4 per real row
+    for (int i = threadIdx.x; i < 32 * Q4; i += Pn::THREADS) {
+        const int r = i / Q4, q = i - r * Q4;
+        if (row0 + r < nrows)
+            *reinterpret_cast<float4 *>(A + (size_t)(row0 + r) * N + 4 * q) =
+                *reinterpret_cast<const float4 *>(ob + r * OP + 4 * q);
+    }
+}
+
+// Pencil factorisation of a transform length, or 0 when it has none.
+static int pencil_code(int n) {
+    switch (n) {
+        case 16: return 44;
+        case 32: return 84;
+        case 64: return 88;
+        case 128: return 168;
+        case 256: return 1616;
+        default: return 0;
+    }
+}
+
+#define FVR_PEN_SWITCH(code, KERNEL, ARGS, GRID)                                          \
+    switch (code) {                                                                       \
+        case 44: KERNEL<4, 4><<<GRID, 64, 0, s>>> ARGS; break;                          \
+        case 84: KERNEL<8, 4><<<GRID, 64, 0, s>>> ARGS; break;                          \
+        case 88: KERNEL<8, 8><<<GRID, 128, 0, s>>> ARGS; break;                         \
+        case 168: KERNEL<16, 8><<<GRID, 128, 0, s>>> ARGS; break;                       \
+        default: KERNEL<16, 16><<<GRID, 256, 0, s>>> ARGS; break;                       \
+    }
+
 // Per-thread prefetch depth for a pencil length: len * kChunk / 2 / 256 16-byte loads.
 static int prefetch_depth(int len) {
     const int need = (len * (kChunk / 2) + kPassThreads - 1) / kPassThreads;
@@ -306,6 +589,10 @@ static size_t pass_lds(int n, int bufs) { return ((size_t)bufs * n * kChunk + n)
 hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, const Grid &g,
                             const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
+    if (const int pc = pencil_code(g.n[1])) {
+        FVR_PEN_SWITCH(pc, pen_y_fwd_kernel, (spec, occ, zocc, g, ax.tw), dim3(nch * g.n[2]))
+        return hipGetLastError();
+    }
     FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, (spec, occ, zocc, g, ax), dim3(nch * g.n[2]),
                   dim3(kPassThreads), pass_lds(g.n[1], 2), s)
     return hipGetLastError();
@@ -314,6 +601,10 @@ hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, con
 hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, const FftAxis &ax,
                               hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
+    if (const int pc = pencil_code(g.n[2])) {
+        FVR_PEN_SWITCH(pc, pen_z_solve_kernel, (spec, zocc, g, ax.tw), dim3(nch * g.n[1]))
+        return hipGetLastError();
+    }
     FVR_PF_SWITCH(g.n[2], fft_z_solve_kernel, (spec, zocc, g, ax), dim3(nch * g.n[1]),
                   dim3(kPassThreads), pass_lds(g.n[2], 2), s)
     return hipGetLastError();
@@ -321,6 +612,10 @@ hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, 
 
 hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
+    if (const int pc = pencil_code(g.n[1])) {
+        FVR_PEN_SWITCH(pc, pen_y_inv_kernel, (spec, g, ax.tw), dim3(nch * g.n[2]))
+        return hipGetLastError();
+    }
     FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, (spec, g, ax), dim3(nch * g.n[2]), dim3(kPassThreads),
                   pass_lds(g.n[1], 1), s)
     return hipGetLastError();
@@ -329,6 +624,11 @@ hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ax, hipS
 hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const FftAxis &ax,
                             hipStream_t s) {
     const int nrows = g.n[1] * g.n[2];
+    if (const int pc = pencil_code(g.n[0])) {
+        const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
+        FVR_PEN_SWITCH(pc, pen_x_c2r_kernel, (spec, A, g, ax.tw, scale), dim3((nrows + 31) / 32))
+        return hipGetLastError();
+    }
     const int blocks = (nrows + kC2rRows - 1) / kC2rRows;
     const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
     const size_t lds = ((size_t)(kC2rRows / 2) * g.n[0] + g.n[0]) * sizeof(float2);

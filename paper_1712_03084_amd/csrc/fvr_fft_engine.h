@@ -106,6 +106,40 @@ template <> struct Dft<8> {
     }
 };
 
+template <> struct Dft<16> {
+    // 16 = 4 x 4: DFT over n1 of x[4 n1 + n2], twiddle w16^(n2 k1), DFT over n2;
+    // output k1 + 4 k2 in natural order
+    __device__ __forceinline__ static void run(float2 *a, int dir) {
+        const float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f;  // cos, sin of pi/8
+        const float r = 0.70710678118654752f;
+        float2 y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            float2 b[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+            Dft<4>::run(b, dir);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = b[k1];
+        }
+        // w16^m = (cos(2 pi m / 16), dir sin(2 pi m / 16)) for m = n2 k1 in {1, 2, 3, 4, 6, 9}
+        y[1][1] = cmul(y[1][1], make_float2(c1, dir * s1));
+        y[1][2] = cmul(y[1][2], make_float2(r, dir * r));
+        y[1][3] = cmul(y[1][3], make_float2(s1, dir * c1));
+        y[2][1] = cmul(y[2][1], make_float2(r, dir * r));
+        y[2][2] = mul_i(y[2][2], dir);
+        y[2][3] = cmul(y[2][3], make_float2(-r, dir * r));
+        y[3][1] = cmul(y[3][1], make_float2(s1, dir * c1));
+        y[3][2] = cmul(y[3][2], make_float2(-r, dir * r));
+        y[3][3] = cmul(y[3][3], make_float2(-c1, -dir * s1));
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 b[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<4>::run(b, dir);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = b[k2];
+        }
+    }
+};
+
 // floor(x / d) for x < 2^16, d < 2^16 via a multiply-high: m = ceil(2^32 / d).
 __device__ __forceinline__ unsigned div_magic(unsigned d) { return d == 1 ? 0u : 0xFFFFFFFFu / d + 1u; }
 __device__ __forceinline__ int udiv(int x, int d, unsigned m) {
@@ -190,11 +224,14 @@ __device__ __forceinline__ void fft_stage(const Acc &acc, int nrows, int n, int 
 // Transform all rows.  The caller has synchronised after filling the rows
 // (and `tw`, normally an LDS copy of ax.tw); the rows are synchronised again
 // on return.
+// Inlined into the kernel, so that the axis description (a kernel argument)
+// is never addressed through memory.
 template <bool ROW_FASTEST, class Acc>
-__device__ void fft_rows(const Acc &acc, int nrows, const FftAxis &ax, const float2 *tw, int dir) {
+__device__ __forceinline__ void fft_rows(const Acc &acc, int nrows, const FftAxis &ax, const float2 *tw,
+                                         int dir) {
     int ns = 1;
     for (int s = 0; s < ax.nstages; ++s) {
-        const int R = ax.radix[s];
+        const int R = (ax.radices >> (4 * s)) & 15u;
         switch (R) {
             case 8: fft_stage<8, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
             case 4: fft_stage<4, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;

@@ -18,6 +18,8 @@
 //               every crossing edge, and compact the active cells
 //               (linear index, case, first triangle)
 //   mc_triangles one thread per active cell emits its table triangles
+#include <algorithm>
+
 #include "fvr_common.h"
 
 namespace fvr {
@@ -393,14 +395,15 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
     __shared__ int red[4];
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
-    const size_t l0 = (size_t)blockIdx.x * kMcPerBlock + (size_t)threadIdx.x * kMcPpt;
+    const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
+    const size_t l0 = l0u;
     int nv = 0, nt = 0, na = 0;
     bool open = false;
     if (l0 < n) {
-        int qx = (int)(l0 % g.n[0]);
-        size_t r = l0 / g.n[0];
-        int qy = (int)(r % g.n[1]);
-        int qz = (int)(r / g.n[1]);
+        const unsigned ru = l0u / (unsigned)g.n[0];
+        int qx = (int)(l0u - ru * (unsigned)g.n[0]);
+        int qz = (int)(ru / (unsigned)g.n[1]);
+        int qy = (int)(ru - (unsigned)qz * (unsigned)g.n[1]);
         if ((g.n[0] & 3) == 0 && ((uintptr_t)A & 15) == 0) {
             // the 4 points share a row: vector loads of the 4 neighbouring rows
             int eb[4], cs[4];
@@ -486,23 +489,31 @@ __device__ __forceinline__ void block_excl_scan3(int v[3], int *red /* [3][4] */
     __syncthreads();
 }
 
+__device__ __forceinline__ bool mesh_fits(const DevStatus *st, const MeshCaps &caps) {
+    return st->mc_total[0] <= caps.vertices && st->mc_total[1] <= caps.triangles &&
+           st->mc_total[2] <= caps.cells && !(caps.check_invalid && (st->flags & kFlagInvalid));
+}
+
 __global__ void __launch_bounds__(kMcThreads)
 mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
                    const int32_t *__restrict__ blk_off, float *__restrict__ verts,
-                   int32_t *__restrict__ vidx, int4 *__restrict__ cells) {
+                   int32_t *__restrict__ vidx, int4 *__restrict__ cells, const DevStatus *st,
+                   MeshCaps caps) {
     __shared__ int red[12];
+    if (!mesh_fits(st, caps)) return;
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
-    const size_t l0 = (size_t)blockIdx.x * kMcPerBlock + (size_t)threadIdx.x * kMcPpt;
+    const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
+    const size_t l0 = l0u;
     int eb[kMcPpt], cs[kMcPpt];
     float a0[kMcPpt], a1[3][kMcPpt];
     int cnt[3] = {0, 0, 0};
     int qx = 0, qy = 0, qz = 0;
     if (l0 < n) {
-        qx = (int)(l0 % g.n[0]);
-        const size_t r = l0 / g.n[0];
-        qy = (int)(r % g.n[1]);
-        qz = (int)(r / g.n[1]);
+        const unsigned ru = l0u / (unsigned)g.n[0];
+        qx = (int)(l0u - ru * (unsigned)g.n[0]);
+        qz = (int)(ru / (unsigned)g.n[1]);
+        qy = (int)(ru - (unsigned)qz * (unsigned)g.n[1]);
     }
     const bool quad = (g.n[0] & 3) == 0 && ((uintptr_t)A & 15) == 0;
     if (quad && l0 < n) {
@@ -586,10 +597,11 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
 }
 
 __global__ void __launch_bounds__(256)
-mc_triangles_kernel(const int4 *__restrict__ cells, int n_cells, const int32_t *__restrict__ vidx,
-                    Grid g, int32_t *__restrict__ tris) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_cells) return;
+mc_triangles_kernel(const int4 *__restrict__ cells, const int32_t *__restrict__ vidx, Grid g,
+                    int32_t *__restrict__ tris, const DevStatus *st, MeshCaps caps) {
+    if (!mesh_fits(st, caps)) return;
+    const int n_cells = st->mc_total[2];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_cells; i += gridDim.x * blockDim.x) {
     const int4 c = cells[i];
     const size_t l = (size_t)(unsigned)c.x;
     const int cs = c.y;
@@ -609,6 +621,7 @@ mc_triangles_kernel(const int4 *__restrict__ cells, int n_cells, const int32_t *
             tris[3 * ((size_t)c.z + t) + j] = vidx[3 * lq + axis];
         }
     }
+    }
 }
 
 hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
@@ -620,17 +633,17 @@ hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g
 
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
                               const int32_t *blk_offsets, float *verts, int32_t *vidx, int4 *cells,
-                              hipStream_t s) {
+                              const DevStatus *st, MeshCaps caps, hipStream_t s) {
     mc_generate_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, g, blk_offsets,
-                                                                       verts, vidx, cells);
+                                                                       verts, vidx, cells, st, caps);
     return hipGetLastError();
 }
 
-hipError_t launch_mc_triangles(const int4 *cells, int n_cells, const int32_t *vidx, const Grid &g,
-                               int32_t *tris, hipStream_t s) {
-    if (n_cells <= 0) return hipSuccess;
-    mc_triangles_kernel<<<dim3((n_cells + 255) / 256), dim3(256), 0, s>>>(cells, n_cells, vidx, g,
-                                                                          tris);
+hipError_t launch_mc_triangles(const int4 *cells, const int32_t *vidx, const Grid &g, int32_t *tris,
+                               const DevStatus *st, MeshCaps caps, hipStream_t s) {
+    const long long want = (caps.cells + 255) / 256;
+    const int blocks = (int)std::max(1LL, std::min(want, 4096LL));
+    mc_triangles_kernel<<<dim3(blocks), dim3(256), 0, s>>>(cells, vidx, g, tris, st, caps);
     return hipGetLastError();
 }
 

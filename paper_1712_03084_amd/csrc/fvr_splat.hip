@@ -13,11 +13,12 @@
 //               the footprint origin, histogram with a per-bin arrival rank
 //   scan        bin offsets
 //   bin_scatter packed 32-byte records (x, y, z, W | W N) in bin order
-//   splat_fft_x one block per tile of ty x tz full x-rows: gathers the points
-//               of the (ty+3) x (tz+3) rows of bins whose footprints reach
-//               the tile, accumulates S and D with LDS float atomics, forms V,
+//   splat_fft_x persistent blocks claim tiles of ty x tz full x-rows: a tile
+//               gathers the points of the (ty+3) x (tz+3) bins whose
+//               footprints reach it, accumulates S and D in LDS, forms V,
 //               runs the real FFT of every x-row in LDS and writes the three
-//               half-spectrum planes, the x component times j w_x.
+//               half-spectrum planes (the x component times j w_x); a tile no
+//               point reaches only clears its occupancy flag.
 #include "fvr_common.h"
 #include "fvr_fft_engine.h"
 
@@ -155,8 +156,9 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
 // footprint origin (i0_y, i0_z), and all points of one bin reach the same
 // in-tile rows.  The block enumerates (bin, chunk of up to kChunkPts
 // consecutive points, row) items - only rows that exist in the tile.  Per
-// point an item spends 10 exponentials (4 x offsets and the (y, z) pair, two
-// Gaussians) on its 4 x-voxels of the row.
+// point an item spends 6 exponentials on its 4 x-voxels of the row: the
+// (y, z) factor of each Gaussian and, per Gaussian, the x factor at the first
+// centre and its ratio to the next (the later x factors follow by products).
 template <bool CHUNKED>
 __global__ void __launch_bounds__(kSplatThreads)
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
@@ -186,6 +188,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     (void)frexpf(__uint_as_float(st->wnmax_bits), &eS);
     (void)frexpf(__uint_as_float(st->wmax_bits), &eD);
     const float qS = ldexpf(1.0f, 30 - eS), qD = ldexpf(1.0f, 30 - eD);
+    const float k1 = exp2f(2.0f * sc.e1[0]), k2 = exp2f(2.0f * sc.e2[0]);
 
     // Persistent blocks (one per CU) claim tiles from a ticket counter, so the
     // many tiles that no point reaches cost a few instructions each, not a launch.
@@ -357,21 +360,31 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
                 flush();
                 run_ix = ix;
             }
-            // offsets of this row's centre and of the 4 x centres from the point, in voxels
+            // offsets of this row's centre from the point, in voxels
             const float dy = r0.y + (float)(iy - qy);
             const float dz = r0.z + (float)(iz - qz);
             const float a1 = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy + sc.e1[2] * dz * dz);
             const float a2 = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy + sc.e2[2] * dz * dz) * (r0.w * qD);
             const float sx = a1 * r1.x * qS, sy = a1 * r1.y * qS, sz = a1 * r1.z * qS;
+            // x factors at the 4 centres ox - 1, offsets d = fx + 1 - ox:
+            // 2^(e (d-1)^2) = 2^(e d^2) 2^(e (1 - 2d)), and that ratio gains 2^(2e) per step
+            const float d0 = r0.x + 1.0f;
+            float g1 = __builtin_amdgcn_exp2f(sc.e1[0] * d0 * d0);
+            float g2 = __builtin_amdgcn_exp2f(sc.e2[0] * d0 * d0);
+            float h1 = __builtin_amdgcn_exp2f(sc.e1[0] * (1.0f - 2.0f * d0));
+            float h2 = __builtin_amdgcn_exp2f(sc.e2[0] * (1.0f - 2.0f * d0));
 #pragma unroll
             for (int ox = 0; ox < 4; ++ox) {
-                const float dx = r0.x - (float)(ox - 1);
-                const float g1 = __builtin_amdgcn_exp2f(sc.e1[0] * dx * dx);
-                const float g2 = __builtin_amdgcn_exp2f(sc.e2[0] * dx * dx);
                 run[ox][0] += __float2int_rn(g1 * sx);
                 run[ox][1] += __float2int_rn(g1 * sy);
                 run[ox][2] += __float2int_rn(g1 * sz);
                 run[ox][3] += __float2int_rn(g2 * a2);
+                if (ox < 3) {
+                    g1 *= h1;
+                    g2 *= h2;
+                    h1 *= k1;
+                    h2 *= k2;
+                }
             }
             r0 = n0;
             r1 = n1;

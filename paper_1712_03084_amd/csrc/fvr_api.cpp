@@ -25,12 +25,12 @@ using namespace fvr;
 namespace {
 
 enum KernelId {
-    K_PREP, K_BIN_COUNT, K_BIN_SCAN, K_BIN_SCATTER, K_SPLAT_FFT_X, K_FFT_Y_FWD,
+    K_PREP, K_BIN_COUNT, K_BIN_SCAN, K_TILE_LIST, K_BIN_SCATTER, K_SPLAT_FFT_X, K_FFT_Y_FWD,
     K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_LEVEL, K_MC_COUNT, K_MC_SCAN,
     K_MC_GENERATE, K_MC_TRIANGLES, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {
-    "prep", "bin_count", "bin_scan", "bin_scatter", "splat_fft_x", "fft_y_fwd",
+    "prep", "bin_count", "bin_scan", "tile_list", "bin_scatter", "splat_fft_x", "fft_y_fwd",
     "fft_z_solve", "fft_y_inv", "fft_x_c2r", "level", "mc_count", "mc_scan",
     "mc_generate", "mc_triangles"};
 
@@ -69,7 +69,7 @@ struct fvr_ctx {
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off,
-        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc;
+        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles;
     DevStatus *host_status = nullptr;
     uint32_t timing_mask = 0;  // bit k: time kernel k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -285,6 +285,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     HIP_TRY(c, ensure(c->spec, sizeof(float2) * 3 * nspec), "alloc spectra");
     HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
     HIP_TRY(c, ensure(c->occ, (size_t)ntiles), "alloc tile occupancy");
+    HIP_TRY(c, ensure(c->tiles, sizeof(int32_t) * (size_t)ntiles), "alloc tile list");
     HIP_TRY(c, ensure(c->zocc, (size_t)g.n[2]), "alloc plane occupancy");
     // sized for both scans of the frame before anything is enqueued
     const int scan_items = std::max(scan_partials(nbins), scan_partials(mc_blocks(g)));
@@ -298,13 +299,16 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     { Timed t(c, K_BIN_SCAN);
       HIP_TRY(c, launch_scan(P<int32_t>(c->bin_count), P<int32_t>(c->bin_off), nbins, 1,
                              P<int32_t>(c->scan_part), nullptr, s), "bin_scan"); }
+    { Timed t(c, K_TILE_LIST);
+      HIP_TRY(c, launch_tile_list(P<int32_t>(c->bin_off), g, p->sc, P<uint8_t>(c->occ),
+                                  P<int32_t>(c->tiles), st, s), "tile_list"); }
     { Timed t(c, K_BIN_SCATTER);
       HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, g, P<int32_t>(c->key),
                                     P<int32_t>(c->rank), P<int32_t>(c->bin_off), P<float4>(c->rec), s),
               "bin_scatter"); }
     { Timed t(c, K_SPLAT_FFT_X);
       HIP_TRY(c, launch_splat_fft_x(P<float4>(c->rec), P<int32_t>(c->bin_off), g, p->sc, p->ax[0],
-                                    st, P<float2>(c->spec), P<uint8_t>(c->occ), v_out, s), "splat_fft_x"); }
+                                    st, P<int32_t>(c->tiles), P<float2>(c->spec), v_out, s), "splat_fft_x"); }
     if (splat_only) return FVR_OK;
     float2 *sp = P<float2>(c->spec);
     { Timed t(c, K_FFT_Y_FWD);
@@ -425,7 +429,7 @@ void fvr_destroy(fvr_ctx *c) {
     for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc};
+                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {
@@ -511,6 +515,9 @@ fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
     Plan *p;
     if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
     const Grid g = make_grid(f->dims, f->bbox);
+    // the splat writes V only on tiles that some point reaches
+    HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(v_out), 3 * (int64_t)g.n[0] * g.n[1] * g.n[2], 0,
+                               c->stream), "clear v_out");
     if ((r = run_field(c, f, p, g, nullptr, v_out, true)) != FVR_OK) return r;
     HIP_TRY(c, hipMemcpyAsync(c->host_status, c->status.p, sizeof(DevStatus), hipMemcpyDeviceToHost,
                               c->stream), "status readback");

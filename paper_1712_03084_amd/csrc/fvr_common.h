@@ -67,7 +67,8 @@ struct DevStatus {
     double level;
     uint32_t wmax_bits;   // float bits of max W over accepted points (W >= 0)
     uint32_t wnmax_bits;  // float bits of max W |N_c| over accepted points
-    int32_t tile_ticket;  // next splat tile to claim (persistent splat blocks)
+    int32_t tile_ticket;  // next entry of the busy-tile list to claim (persistent splat blocks)
+    int32_t n_busy;       // splat tiles that some point reaches
 };
 constexpr uint32_t kFlagInvalid = 1u;
 constexpr uint32_t kFlagOpen = 2u;
@@ -106,9 +107,13 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 // (the x-component already multiplied by j w_x).  v_out (optional) receives V.
 // Tiles no point reaches are skipped: occ[tile] = 0 and their spectrum rows
 // are left unwritten (they are zero); occupied tiles set occ[tile] = 1.
+// Busy splat tiles: occ[tile] = 1 when some point's footprint reaches the
+// tile (0 otherwise), and the indices of those tiles in list[0, st->n_busy).
+hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
+                            uint8_t *occ, int32_t *list, DevStatus *st, hipStream_t s);
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
-                              float2 *spec, uint8_t *occ, float *v_out, hipStream_t s);
+                              const int32_t *list, float2 *spec, float *v_out, hipStream_t s);
 int splat_blocks();
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc);
 

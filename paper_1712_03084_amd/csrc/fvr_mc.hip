@@ -52,6 +52,7 @@ __global__ void prep_kernel(DevStatus *st, int32_t *bins, int nbins) {
         st->wmax_bits = 0;
         st->wnmax_bits = 0;
         st->tile_ticket = 0;
+        st->n_busy = 0;
     }
     if (bins && i < nbins) bins[i] = 0;
 }

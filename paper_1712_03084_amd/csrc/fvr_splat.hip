@@ -13,12 +13,13 @@
 //               the footprint origin, histogram with a per-bin arrival rank
 //   scan        bin offsets
 //   bin_scatter packed 32-byte records (x, y, z, W | W N) in bin order
-//   splat_fft_x persistent blocks claim tiles of ty x tz full x-rows: a tile
-//               gathers the points of the (ty+3) x (tz+3) bins whose
-//               footprints reach it, accumulates S and D in LDS, forms V,
-//               runs the real FFT of every x-row in LDS and writes the three
-//               half-spectrum planes (the x component times j w_x); a tile no
-//               point reaches only clears its occupancy flag.
+//   tile_list   tiles of ty x tz full x-rows that some point reaches, and
+//               their occupancy flags (the later passes skip the others)
+//   splat_fft_x persistent blocks claim the busy tiles: a tile gathers the
+//               points of the (ty+3) x (tz+3) bins whose footprints reach it,
+//               accumulates S and D in LDS, forms V, runs the real FFT of
+//               every x-row in LDS and writes the three half-spectrum planes
+//               (the x component times j w_x).
 #include "fvr_common.h"
 #include "fvr_fft_engine.h"
 
@@ -163,7 +164,8 @@ template <bool CHUNKED>
 __global__ void __launch_bounds__(kSplatThreads)
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
                    SplatConsts sc, FftAxis ax, DevStatus *__restrict__ st,
-                   float2 *__restrict__ spec, uint8_t *__restrict__ occ, float *__restrict__ v_out) {
+                   const int32_t *__restrict__ list, float2 *__restrict__ spec,
+                   float *__restrict__ v_out) {
     extern __shared__ unsigned long long acc[];
     __shared__ int b_start[kMaxBins], b_pre[kMaxBins + 1], b_rows[kMaxBins], b_ny[kMaxBins];
     __shared__ int b_cnt[kMaxBins];
@@ -173,12 +175,15 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     __shared__ int s_tile;
     const int Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
     const int TY = sc.ty, TZ = sc.tz, R = TY * TZ;
-    const int ntiles = sc.tiles_y * ((Nz + TZ - 1) / TZ);
+    const int nbusy = st->n_busy;
     const int plane = R * Nx;  // voxels per channel plane
-    // int64 accumulators use a row pitch of Nx + 1: with Nx a multiple of the
-    // bank count, an unpadded row would put a voxel's bank on x alone, and the
-    // points of a tile cluster in x (the surface crossings)
-    const int P = Nx + 1, aplane = R * P;
+    // int64 accumulator rows hold x = -2 .. Nx + 2 (voxel x at x + 2): a
+    // footprint reaches x = i0_x - 1 .. i0_x + 2 with i0_x in [-1, Nx - 1], so
+    // a flush needs no bounds test; contributions to the pad voxels are
+    // dropped.  The pitch Nx + 5 is odd: with Nx a multiple of the bank count,
+    // an even pitch would put a voxel's bank on x alone, and the points of a
+    // tile cluster in x (the surface crossings).
+    const int P = Nx + 5, aplane = R * P;
     const int H = g.H, Hp = g.Hp;
     const size_t pl = (size_t)Nz * Ny * Hp;
     float2 *twl = reinterpret_cast<float2 *>(acc + 4 * aplane);
@@ -190,13 +195,13 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     const float qS = ldexpf(1.0f, 30 - eS), qD = ldexpf(1.0f, 30 - eD);
     const float k1 = exp2f(2.0f * sc.e1[0]), k2 = exp2f(2.0f * sc.e2[0]);
 
-    // Persistent blocks (one per CU) claim tiles from a ticket counter, so the
-    // many tiles that no point reaches cost a few instructions each, not a launch.
+    // Persistent blocks (one per CU) claim the busy tiles from a ticket counter.
     for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(&st->tile_ticket, 1);
     __syncthreads();
-    const int tile = s_tile;
-    if (tile >= ntiles) break;
+    const int ticket = s_tile;
+    if (ticket >= nbusy) break;
+    const int tile = list[ticket];
     const int by = tile % sc.tiles_y, bz = tile / sc.tiles_y;
     const int y0 = by * TY, z0 = bz * TZ;
 
@@ -226,26 +231,26 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         b_pre[t + 1] = nchunk * ny * nz;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        b_pre[0] = 0;
-        for (int t = 0; t < nbins; ++t) b_pre[t + 1] += b_pre[t];
+    if (threadIdx.x < 64) {
+        // inclusive prefix of the bins' item counts (nbins <= 128: two per lane)
+        const int l = threadIdx.x;
+        const int v0 = 2 * l < nbins ? b_pre[2 * l + 1] : 0;
+        const int v1 = 2 * l + 1 < nbins ? b_pre[2 * l + 2] : 0;
+        int incl = v0 + v1;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl, d, 64);
+            if (l >= d) incl += u;
+        }
+        const int excl = incl - v0 - v1;
+        if (2 * l < nbins) b_pre[2 * l + 1] = excl + v0;
+        if (2 * l + 1 < nbins) b_pre[2 * l + 2] = excl + v0 + v1;
+        if (l == 0) b_pre[0] = 0;
     }
     __syncthreads();
     const int total = b_pre[nbins];
-    if (threadIdx.x == 0) occ[tile] = total > 0 ? 1 : 0;
-    if (total == 0) {
-        // no point reaches this tile: V = 0 and so is its spectrum, which the
-        // y pass reads as zero from occ[] without it being stored
-        if (v_out) {
-            const size_t n = (size_t)Nx * Ny * Nz;
-            for (int i = threadIdx.x; i < 3 * plane; i += blockDim.x) {
-                const int c = i / plane, l = i - c * plane;
-                const int row = l / Nx, qx = l - row * Nx;
-                const int qy = y0 + row % TY, qz = z0 + row / TY;
-                if (qy < Ny && qz < Nz) v_out[c * n + qx + (size_t)Nx * (qy + (size_t)Ny * qz)] = 0.f;
-            }
-        }
-        __syncthreads();  // the bin tables are rebuilt for the next tile
+    if (total == 0) {  // not in the busy list; kept for safety
+        __syncthreads();
         continue;
     }
     for (int i = threadIdx.x; i < 4 * aplane; i += blockDim.x) acc[i] = 0ull;
@@ -324,18 +329,14 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     long long run[4][4];
     int run_ix = 0, run_row = 0;
     auto flush = [&]() {
+        const int l = run_row * P + run_ix + 1;  // voxel x = run_ix - 1 in the padded row
 #pragma unroll
-        for (int ox = 0; ox < 4; ++ox) {
-            const int qx = run_ix + ox - 1;
-            if (qx >= 0 && qx < Nx) {
-                const int l = run_row * P + qx;
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (run[ox][c] != 0) atomicAdd(&acc[c * aplane + l], (unsigned long long)run[ox][c]);
+            for (int ox = 0; ox < 4; ++ox) {
+                atomicAdd(&acc[c * aplane + l + ox], (unsigned long long)run[ox][c]);
+                run[ox][c] = 0;
             }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) run[ox][c] = 0;
-        }
     };
 #pragma unroll
     for (int ox = 0; ox < 4; ++ox)
@@ -406,7 +407,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         const int l = threadIdx.x + t * blockDim.x;
         vv[t][0] = vv[t][1] = vv[t][2] = 0.f;
         if (l < plane) {
-            const int row = l / Nx, la = l + row;  // padded accumulator index
+            const int row = l / Nx, la = l + 5 * row + 2;  // padded accumulator index
             const long long d = (long long)acc[3 * aplane + la];
             if (d > 0) {
                 const float inv = ratio / (float)d;
@@ -492,7 +493,7 @@ hipError_t splat_configure() {
 int splat_blocks() { return g_splat_blocks; }
 
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
-    return (size_t)4 * sc.ty * sc.tz * (g.n[0] + 1) * sizeof(unsigned long long) +
+    return (size_t)4 * sc.ty * sc.tz * (g.n[0] + 5) * sizeof(unsigned long long) +
            g.n[0] * sizeof(float2);
 }
 
@@ -514,14 +515,51 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
     return hipGetLastError();
 }
 
+// One thread per splat tile: the number of points in the bins whose
+// footprints reach the tile (the same bins the splat gathers).
+__global__ void __launch_bounds__(256)
+tile_list_kernel(const int32_t *__restrict__ bin_off, Grid g, SplatConsts sc, int ntiles,
+                 uint8_t *__restrict__ occ, int32_t *__restrict__ list, DevStatus *st) {
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    bool busy = false;
+    if (tile < ntiles) {
+        const int Ny = g.n[1], Nz = g.n[2];
+        const int y0 = (tile % sc.tiles_y) * sc.ty, z0 = (tile / sc.tiles_y) * sc.tz;
+        const int iz_lo = max(z0 - 2, -1), iz_hi = min(z0 + sc.tz, Nz - 1);
+        const int iy_lo = max(y0 - 2, -1), iy_hi = min(y0 + sc.ty, Ny - 1);
+        int total = 0;
+        for (int iz = iz_lo; iz <= iz_hi; ++iz) {
+            const int row = (iz + 1) * (Ny + 1);
+            total += bin_off[row + iy_hi + 2] - bin_off[row + iy_lo + 1];
+        }
+        busy = total > 0;
+        occ[tile] = busy ? 1 : 0;
+    }
+    // one list append per wave
+    const unsigned long long b = __ballot(busy);
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0 && b) base = atomicAdd(&st->n_busy, __popcll(b));
+    base = __shfl(base, 0, 64);
+    if (busy) list[base + __popcll(b & ((1ull << lane) - 1ull))] = tile;
+}
+
+hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
+                            uint8_t *occ, int32_t *list, DevStatus *st, hipStream_t s) {
+    const int ntiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
+    tile_list_kernel<<<dim3((ntiles + 255) / 256), dim3(256), 0, s>>>(bin_off, g, sc, ntiles, occ,
+                                                                      list, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
-                              float2 *spec, uint8_t *occ, float *v_out, hipStream_t s) {
+                              const int32_t *list, float2 *spec, float *v_out, hipStream_t s) {
     const int tiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     const int blocks = tiles < g_splat_blocks ? tiles : g_splat_blocks;
     const size_t lds = splat_lds_bytes(g, sc);
     splat_fft_x_kernel<FVR_SPLAT_CHUNKED><<<dim3(blocks), dim3(kSplatThreads), lds, s>>>(
-        rec, bin_off, g, sc, ax, st, spec, occ, v_out);
+        rec, bin_off, g, sc, ax, st, list, spec, v_out);
     return hipGetLastError();
 }
 

@@ -68,7 +68,7 @@ struct fvr_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
-    DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off,
+    DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
         lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles;
     DevStatus *host_status = nullptr;
     uint32_t timing_mask = 0;  // bit k: time kernel k
@@ -341,12 +341,13 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
     HIP_TRY(c, ensure(c->mc_cnt, sizeof(int32_t) * 3 * (size_t)nb), "alloc mc counts");
     HIP_TRY(c, ensure(c->mc_off, sizeof(int32_t) * 3 * ((size_t)nb + 1)), "alloc mc offsets");
     HIP_TRY(c, ensure(c->vidx, sizeof(int32_t) * 3 * n), "alloc vertex ids");
+    HIP_TRY(c, ensure(c->mc_codes, (size_t)nb * 1024), "alloc point codes");
     HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_partials(nb)), "alloc scan scratch");
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     { Timed t(c, K_MC_COUNT);
-      HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_cnt), cases_out,
-                                 st, s), "mc_count"); }
+      HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_cnt),
+                                 P<uint32_t>(c->mc_codes), cases_out, st, s), "mc_count"); }
     { Timed t(c, K_MC_SCAN);
       HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3,
                              P<int32_t>(c->scan_part), st->mc_total, s), "mc_scan"); }
@@ -361,8 +362,9 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
     caps.check_invalid = check_invalid ? 1 : 0;
     HIP_TRY(c, ensure(c->cells, sizeof(int4) * (size_t)std::max(1LL, caps.cells)), "alloc active cells");
     { Timed t(c, K_MC_GENERATE);
-      HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_off),
-                                    mesh->vertices, P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, s),
+      HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_cnt),
+                                    P<int32_t>(c->mc_off), P<uint32_t>(c->mc_codes), mesh->vertices,
+                                    P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, s),
               "mc_generate"); }
     { Timed t(c, K_MC_TRIANGLES);
       HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), P<int32_t>(c->vidx), g, mesh->triangles, st,
@@ -428,7 +430,7 @@ void fvr_destroy(fvr_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
-                      &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->lvl_sum, &c->lvl_cnt,
+                      &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
                       &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);

@@ -146,7 +146,7 @@ int level_blocks(int m);
 hipError_t mc_upload_table(const uint8_t *counts, const int8_t *edges);
 int mc_blocks(const Grid &g);
 hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
-                           int32_t *blk_counts, uint8_t *cases_out, DevStatus *st,
+                           int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,
                            hipStream_t s);
 // The mesh kernels read the totals of the count scan from `st`; they write
 // nothing when a total exceeds its capacity (vertices, triangles, active
@@ -156,7 +156,8 @@ struct MeshCaps {
     int check_invalid;
 };
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
-                              const int32_t *blk_offsets, float *verts, int32_t *vidx, int4 *cells,
+                              const int32_t *blk_counts, const int32_t *blk_offsets,
+                              const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
                               const DevStatus *st, MeshCaps caps, hipStream_t s);
 hipError_t launch_mc_triangles(const int4 *cells, const int32_t *vidx, const Grid &g, int32_t *tris,
                                const DevStatus *st, MeshCaps caps, hipStream_t s);

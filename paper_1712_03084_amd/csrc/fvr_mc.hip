@@ -12,8 +12,11 @@
 //               the 3 grid edges leaving q that cross the level (vertices),
 //               the case of the cell with lower corner q, its triangle count
 //               and whether it is active; block totals -> blk_counts
+//               and, for blocks the surface passes, one code byte per point
+//               (the case, or the edge bits on the upper borders)
 //   scan        exclusive scan of the block totals
-//   mc_generate recompute, block-scan, write each vertex at its global rank
+//   mc_generate from the codes (blocks without vertices or active cells exit
+//               at once), block-scan, write each vertex at its global rank
 //               (vertex order = (linear index, axis)), record the vertex id of
 //               every crossing edge, and compact the active cells
 //               (linear index, case, first triangle)
@@ -392,8 +395,10 @@ __device__ __forceinline__ int block_sum(int v, int *red) {
 
 __global__ void __launch_bounds__(kMcThreads)
 mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
-                int32_t *__restrict__ blk_counts, uint8_t *__restrict__ cases_out, DevStatus *st) {
+                int32_t *__restrict__ blk_counts, uint32_t *__restrict__ codes,
+                uint8_t *__restrict__ cases_out, DevStatus *st) {
     __shared__ int red[4];
+    uint32_t code4 = 0;  // the 4 point codes, byte i for point l0 + i
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
     const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
@@ -414,6 +419,7 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
 #pragma unroll
             for (int i = 0; i < kMcPpt; ++i) {
                 nv += __popc(eb[i]);
+                code4 |= (uint32_t)(cs[i] >= 0 ? cs[i] : eb[i]) << (8 * i);
                 if (cs[i] >= 0) {
                     const int c = c_mc_count[cs[i]];
                     nt += c;
@@ -433,6 +439,7 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
                     int eb, cs;
                     mc_point(A, g, qx, qy, qz, l, L, eb, cs);
                     nv += __popc(eb);
+                    code4 |= (uint32_t)(cs >= 0 ? cs : eb) << (8 * i);
                     if (cs >= 0) {
                         const int c = c_mc_count[cs];
                         nt += c;
@@ -464,6 +471,8 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
         blk_counts[3 * blockIdx.x + 1] = nt;
         blk_counts[3 * blockIdx.x + 2] = na;
     }
+    // codes only where the surface passes: mc_generate skips the other blocks
+    if (nv > 0 || na > 0) codes[l0 / 4] = code4;
 }
 
 // Exclusive block scan of three counters (256 threads).
@@ -497,44 +506,46 @@ __device__ __forceinline__ bool mesh_fits(const DevStatus *st, const MeshCaps &c
 
 __global__ void __launch_bounds__(kMcThreads)
 mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
-                   const int32_t *__restrict__ blk_off, float *__restrict__ verts,
+                   const int32_t *__restrict__ blk_counts, const int32_t *__restrict__ blk_off,
+                   const uint32_t *__restrict__ codes, float *__restrict__ verts,
                    int32_t *__restrict__ vidx, int4 *__restrict__ cells, const DevStatus *st,
                    MeshCaps caps) {
     __shared__ int red[12];
     if (!mesh_fits(st, caps)) return;
+    // a block without vertices and active cells has nothing to write (and
+    // mc_count stored no codes for it)
+    if (blk_counts[3 * blockIdx.x] == 0 && blk_counts[3 * blockIdx.x + 2] == 0) return;
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
     const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
     const size_t l0 = l0u;
     int eb[kMcPpt], cs[kMcPpt];
-    float a0[kMcPpt], a1[3][kMcPpt];
     int cnt[3] = {0, 0, 0};
     int qx = 0, qy = 0, qz = 0;
+    uint32_t code4 = 0;
     if (l0 < n) {
         const unsigned ru = l0u / (unsigned)g.n[0];
         qx = (int)(l0u - ru * (unsigned)g.n[0]);
         qz = (int)(ru / (unsigned)g.n[1]);
         qy = (int)(ru - (unsigned)qz * (unsigned)g.n[1]);
+        code4 = codes[l0u / 4];
     }
-    const bool quad = (g.n[0] & 3) == 0 && ((uintptr_t)A & 15) == 0;
-    if (quad && l0 < n) {
-        mc_quad(A, g, qx, qy, qz, l0, L, eb, cs, a0, a1);
-    } else {
-        const size_t sy = g.n[0], sz = (size_t)g.n[0] * g.n[1];
+    {
         int x = qx, y = qy, z = qz;
 #pragma unroll
         for (int i = 0; i < kMcPpt; ++i) {
+            const int code = (int)((code4 >> (8 * i)) & 255u);
             eb[i] = 0;
             cs[i] = -1;
-            a0[i] = 0.f;
-            a1[0][i] = a1[1][i] = a1[2][i] = 0.f;
-            const size_t l = l0 + i;
-            if (l < n) {
-                mc_point(A, g, x, y, z, l, L, eb[i], cs[i]);
-                a0[i] = A[l];
-                if (eb[i] & 1) a1[0][i] = A[l + 1];
-                if (eb[i] & 2) a1[1][i] = A[l + sy];
-                if (eb[i] & 4) a1[2][i] = A[l + sz];
+            if (l0 + i < n) {
+                if (x + 1 < g.n[0] && y + 1 < g.n[1] && z + 1 < g.n[2]) {
+                    // the case holds the corners at q and q + e_a
+                    cs[i] = code;
+                    eb[i] = ((code ^ (code >> 1)) & 1) | (((code ^ (code >> 2)) & 1) << 1) |
+                            (((code ^ (code >> 4)) & 1) << 2);
+                } else {
+                    eb[i] = code & 7;
+                }
             }
             if (++x == g.n[0]) {
                 x = 0;
@@ -569,7 +580,9 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (!((eb[i] >> a) & 1)) continue;
-                const float t = (L - a0[i]) / (a1[a][i] - a0[i]);
+                const size_t step = a == 0 ? 1 : a == 1 ? (size_t)g.n[0] : (size_t)g.n[0] * g.n[1];
+                const float a0 = A[l], a1 = A[l + step];
+                const float t = (L - a0) / (a1 - a0);
                 float p[3] = {px, py, pz};
                 p[a] += t * g.h[a];
                 verts[3 * (size_t)vbase + 0] = p[0];
@@ -626,17 +639,19 @@ mc_triangles_kernel(const int4 *__restrict__ cells, const int32_t *__restrict__ 
 }
 
 hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
-                           int32_t *blk_counts, uint8_t *cases_out, DevStatus *st, hipStream_t s) {
+                           int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,
+                           hipStream_t s) {
     mc_count_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, g, blk_counts,
-                                                                    cases_out, st);
+                                                                    codes, cases_out, st);
     return hipGetLastError();
 }
 
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
-                              const int32_t *blk_offsets, float *verts, int32_t *vidx, int4 *cells,
+                              const int32_t *blk_counts, const int32_t *blk_offsets,
+                              const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
                               const DevStatus *st, MeshCaps caps, hipStream_t s) {
-    mc_generate_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, g, blk_offsets,
-                                                                       verts, vidx, cells, st, caps);
+    mc_generate_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(
+        A, level_f32, g, blk_counts, blk_offsets, codes, verts, vidx, cells, st, caps);
     return hipGetLastError();
 }
 

@@ -254,14 +254,16 @@ def test_capacity_shortfall_reports_counts_then_retry(ctx):
     p, n, w = _frame_dev(f)
     full = ctx.reconstruct(p, n, w, grid_dim=f.dims, bbox=f.bbox)
     small = (torch.empty((8, 3), dtype=torch.float32, device="cuda"),
-             torch.empty((8, 3), dtype=torch.int32, device="cuda"))
+             torch.full((8, 3), -7, dtype=torch.int32, device="cuda"))
     with pytest.raises(fvr.FvrError) as e:
         ctx.reconstruct(p, n, w, grid_dim=f.dims, bbox=f.bbox, out=small)
     assert e.value.status == -4
+    # the triangle array is not written on a shortfall
+    assert bool((small[1] == -7).all())
     retried = ctx.reconstruct(p, n, w, grid_dim=f.dims, bbox=f.bbox, vertex_capacity=8,
                               triangle_capacity=8)
-    assert retried.vertices.shape == full.vertices.shape
-    assert retried.triangles.shape == full.triangles.shape
+    assert torch.equal(retried.vertices, full.vertices)
+    assert torch.equal(retried.triangles, full.triangles)
 
 
 @pytest.mark.parametrize("dims", [(512, 16, 16), (16, 512, 16), (16, 16, 512)])

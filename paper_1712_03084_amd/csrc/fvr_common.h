@@ -108,9 +108,10 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 // Tiles no point reaches are skipped: occ[tile] = 0 and their spectrum rows
 // are left unwritten (they are zero); occupied tiles set occ[tile] = 1.
 // Busy splat tiles: occ[tile] = 1 when some point's footprint reaches the
-// tile (0 otherwise), and the indices of those tiles in list[0, st->n_busy).
+// tile (0 otherwise), and the indices of those tiles in list[0, st->n_busy),
+// in decreasing order of work; pend is scratch of one int2 per tile.
 hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
-                            uint8_t *occ, int32_t *list, DevStatus *st, hipStream_t s);
+                            uint8_t *occ, int2 *pend, int32_t *list, DevStatus *st, hipStream_t s);
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
                               const int32_t *list, float2 *spec, float *v_out, hipStream_t s);

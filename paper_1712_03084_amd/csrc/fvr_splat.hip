@@ -515,40 +515,86 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
     return hipGetLastError();
 }
 
-// One thread per splat tile: the number of points in the bins whose
-// footprints reach the tile (the same bins the splat gathers).
+// One thread per splat tile: the point-rows that fall into it (each point of
+// bin (iy, iz) adds one item row per tile row within its footprint rows
+// iy - 1 .. iy + 2, iz - 1 .. iz + 2).  Busy tiles get occ = 1 and an entry
+// (tile, cost) in `pend`, in no particular order.
 __global__ void __launch_bounds__(256)
 tile_list_kernel(const int32_t *__restrict__ bin_off, Grid g, SplatConsts sc, int ntiles,
-                 uint8_t *__restrict__ occ, int32_t *__restrict__ list, DevStatus *st) {
+                 uint8_t *__restrict__ occ, int2 *__restrict__ pend, DevStatus *st) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-    bool busy = false;
+    long long cost = 0;
     if (tile < ntiles) {
         const int Ny = g.n[1], Nz = g.n[2];
         const int y0 = (tile % sc.tiles_y) * sc.ty, z0 = (tile / sc.tiles_y) * sc.tz;
+        const int y1 = min(y0 + sc.ty, Ny) - 1, z1 = min(z0 + sc.tz, Nz) - 1;  // last tile rows
         const int iz_lo = max(z0 - 2, -1), iz_hi = min(z0 + sc.tz, Nz - 1);
         const int iy_lo = max(y0 - 2, -1), iy_hi = min(y0 + sc.ty, Ny - 1);
-        int total = 0;
         for (int iz = iz_lo; iz <= iz_hi; ++iz) {
-            const int row = (iz + 1) * (Ny + 1);
-            total += bin_off[row + iy_hi + 2] - bin_off[row + iy_lo + 1];
+            const int nz = min(iz + 2, z1) - max(iz - 1, z0) + 1;
+            const int row = (iz + 1) * (Ny + 1) + 1;
+            int prev = bin_off[row + iy_lo];
+            long long sum = 0;
+            for (int iy = iy_lo; iy <= iy_hi; ++iy) {
+                const int next = bin_off[row + iy + 1];
+                sum += (long long)(next - prev) * (min(iy + 2, y1) - max(iy - 1, y0) + 1);
+                prev = next;
+            }
+            cost += nz * sum;
         }
-        busy = total > 0;
-        occ[tile] = busy ? 1 : 0;
+        occ[tile] = cost > 0 ? 1 : 0;
     }
+    const bool busy = cost > 0;
     // one list append per wave
     const unsigned long long b = __ballot(busy);
     const int lane = threadIdx.x & 63;
     int base = 0;
     if (lane == 0 && b) base = atomicAdd(&st->n_busy, __popcll(b));
     base = __shfl(base, 0, 64);
-    if (busy) list[base + __popcll(b & ((1ull << lane) - 1ull))] = tile;
+    if (busy)
+        pend[base + __popcll(b & ((1ull << lane) - 1ull))] = make_int2(tile, (int)min(cost, 0x7fffffffLL));
+}
+
+// Busy tiles in decreasing cost (64 logarithmic cost classes, a counting
+// sort in one block), so the persistent splat blocks take the longest tiles
+// first and finish together.
+constexpr int kTileClasses = 64;
+
+__device__ __forceinline__ int tile_class(int cost) {
+    const int msb = 31 - __clz(cost);
+    return 2 * msb + (msb > 0 ? (cost >> (msb - 1)) & 1 : 0);
+}
+
+__global__ void __launch_bounds__(1024)
+tile_order_kernel(const int2 *__restrict__ pend, int32_t *__restrict__ list, const DevStatus *st) {
+    __shared__ int hist[kTileClasses], cursor[kTileClasses];
+    const int n = st->n_busy;
+    if (threadIdx.x < kTileClasses) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&hist[tile_class(pend[i].y)], 1);
+    __syncthreads();
+    if (threadIdx.x < kTileClasses) {
+        // classes in decreasing order: the start of class c is the count of classes above it
+        const int c = threadIdx.x;
+        int above = 0;
+        for (int k = c + 1; k < kTileClasses; ++k) above += hist[k];
+        cursor[c] = above;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int2 e = pend[i];
+        list[atomicAdd(&cursor[tile_class(e.y)], 1)] = e.x;
+    }
 }
 
 hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
-                            uint8_t *occ, int32_t *list, DevStatus *st, hipStream_t s) {
+                            uint8_t *occ, int2 *pend, int32_t *list, DevStatus *st, hipStream_t s) {
     const int ntiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     tile_list_kernel<<<dim3((ntiles + 255) / 256), dim3(256), 0, s>>>(bin_off, g, sc, ntiles, occ,
-                                                                      list, st);
+                                                                      pend, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    tile_order_kernel<<<dim3(1), dim3(1024), 0, s>>>(pend, list, st);
     return hipGetLastError();
 }
 

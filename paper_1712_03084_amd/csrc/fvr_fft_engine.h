@@ -6,7 +6,7 @@
 // applies the twiddles and an R-point DFT, the block synchronises, then every
 // thread stores its R outputs to their auto-sorted positions.  Holding all
 // butterflies of a stage in registers makes the in-place update safe; the
-// caller guarantees nrows * n <= blockDim.x * kFftEpt.
+// caller guarantees nrows * n <= blockDim.x * EPT (kFftEpt by default).
 //
 // Stage with radix R, running product ns of earlier radices, nb = n / R:
 //   butterfly j of a row reads  x[j + r nb], r < R
@@ -169,11 +169,13 @@ struct RowsS {
 
 // ROW_FASTEST: consecutive threads take consecutive rows (rows interleaved in
 // LDS, e.g. columns of a y or z pencil tile); otherwise consecutive threads
-// take consecutive butterflies of one row (rows contiguous in LDS).
-template <int R, bool ROW_FASTEST, class Acc>
+// take consecutive butterflies of one row (rows contiguous in LDS).  EPT bounds
+// the elements per thread (nrows * n <= blockDim.x * EPT); the registers held
+// per thread scale with it.
+template <int R, bool ROW_FASTEST, int EPT, class Acc>
 __device__ __forceinline__ void fft_stage(const Acc &acc, int nrows, int n, int ns,
                                           const float2 *__restrict__ tw, int dir) {
-    constexpr int MAXB = kFftEpt / R;
+    constexpr int MAXB = (EPT + R - 1) / R;
     const int nb = n / R;
     const int total = nrows * nb;
     const int stride = n / (ns * R);
@@ -226,18 +228,18 @@ __device__ __forceinline__ void fft_stage(const Acc &acc, int nrows, int n, int 
 // on return.
 // Inlined into the kernel, so that the axis description (a kernel argument)
 // is never addressed through memory.
-template <bool ROW_FASTEST, class Acc>
+template <bool ROW_FASTEST, int EPT = kFftEpt, class Acc>
 __device__ __forceinline__ void fft_rows(const Acc &acc, int nrows, const FftAxis &ax, const float2 *tw,
                                          int dir) {
     int ns = 1;
     for (int s = 0; s < ax.nstages; ++s) {
         const int R = (ax.radices >> (4 * s)) & 15u;
         switch (R) {
-            case 8: fft_stage<8, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
-            case 4: fft_stage<4, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
-            case 2: fft_stage<2, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
-            case 3: fft_stage<3, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
-            default: fft_stage<5, ROW_FASTEST>(acc, nrows, ax.n, ns, tw, dir); break;
+            case 8: fft_stage<8, ROW_FASTEST, EPT>(acc, nrows, ax.n, ns, tw, dir); break;
+            case 4: fft_stage<4, ROW_FASTEST, EPT>(acc, nrows, ax.n, ns, tw, dir); break;
+            case 2: fft_stage<2, ROW_FASTEST, EPT>(acc, nrows, ax.n, ns, tw, dir); break;
+            case 3: fft_stage<3, ROW_FASTEST, EPT>(acc, nrows, ax.n, ns, tw, dir); break;
+            default: fft_stage<5, ROW_FASTEST, EPT>(acc, nrows, ax.n, ns, tw, dir); break;
         }
         ns *= R;
     }

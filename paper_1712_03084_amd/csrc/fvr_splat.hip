@@ -444,7 +444,9 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     // Real FFT along x: real rows (2j, 2j+1) of the flat (channel, row) order
     // - always the same channel since R is even - form complex row j.
     const int ncx = 3 * R / 2;
-    fft_rows<false>(RowsS{S, 2 * Nx, Nx}, ncx, ax, twl, -1);
+    // at most 1.5 kSplatMaxPlane elements over kSplatThreads threads
+    fft_rows<false, (3 * kSplatMaxPlane / 2 + kSplatThreads - 1) / kSplatThreads>(RowsS{S, 2 * Nx, Nx}, ncx,
+                                                                                  ax, twl, -1);
 
     // Unpack X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = (Z[k] - conj Z[N-k]) / 2i,
     // k = 0..Nx/2, and store; the x component is multiplied by j w_x.

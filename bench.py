@@ -258,15 +258,22 @@ def main():
     }
 
     if not args.no_cpu_baseline:
+        # the oracle as it stands, single-threaded FP64, on whole frames of the
+        # same workload until about 10 s of CPU time have passed
         import oracle
-        f = frames[0]
-        print("[bench] cpu baseline: oracle on one full frame", file=sys.stderr, flush=True)
+        print("[bench] cpu baseline: oracle on full frames", file=sys.stderr, flush=True)
         tc = time.perf_counter()
-        oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+        nf = 0
+        while nf < len(frames) * 4 and (nf == 0 or time.perf_counter() - tc < 10.0):
+            f = frames[nf % len(frames)]
+            oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+            nf += 1
+            print(f"[bench] cpu baseline: {nf} frame(s), {time.perf_counter() - tc:.1f} s",
+                  file=sys.stderr, flush=True)
         tcpu = time.perf_counter() - tc
-        result["cpu_baseline"] = {"value": round(1.0 / tcpu, 5), "unit": "frames/s", "cores": 1,
+        result["cpu_baseline"] = {"value": round(nf / tcpu, 5), "unit": "frames/s", "cores": 1,
                                   "kind": "oracle",
-                                  "sample": f"one full frame of the same workload "
+                                  "sample": f"{nf} full frame(s) of the same workload "
                                             f"({m} points, {dims[0]}x{dims[1]}x{dims[2]}), "
                                             f"{tcpu:.2f} s single-threaded FP64"}
     print(json.dumps(result))

@@ -69,7 +69,7 @@ struct fvr_ctx {
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
-        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend;
+        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max;
     DevStatus *host_status = nullptr;
     uint32_t timing_mask = 0;  // bit k: time kernel k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -287,6 +287,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     HIP_TRY(c, ensure(c->occ, (size_t)ntiles), "alloc tile occupancy");
     HIP_TRY(c, ensure(c->tiles, sizeof(int32_t) * (size_t)ntiles), "alloc tile list");
     HIP_TRY(c, ensure(c->tile_pend, sizeof(int2) * (size_t)ntiles), "alloc tile costs");
+    HIP_TRY(c, ensure(c->blk_max, sizeof(uint2) * (size_t)std::max(1, bin_count_blocks(m))), "alloc block maxima");
     HIP_TRY(c, ensure(c->zocc, (size_t)g.n[2]), "alloc plane occupancy");
     // sized for both scans of the frame before anything is enqueued
     const int scan_items = std::max(scan_partials(nbins), scan_partials(mc_blocks(g)));
@@ -296,13 +297,15 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(st, P<int32_t>(c->bin_count), nbins, s), "prep"); }
     { Timed t(c, K_BIN_COUNT);
       HIP_TRY(c, launch_bin_count(f->points, f->normals, f->weights, m, g, P<int32_t>(c->bin_count),
-                                  P<int32_t>(c->key), P<int32_t>(c->rank), st, s), "bin_count"); }
+                                  P<int32_t>(c->key), P<int32_t>(c->rank), P<uint2>(c->blk_max), st, s),
+              "bin_count"); }
     { Timed t(c, K_BIN_SCAN);
       HIP_TRY(c, launch_scan(P<int32_t>(c->bin_count), P<int32_t>(c->bin_off), nbins, 1,
                              P<int32_t>(c->scan_part), nullptr, s), "bin_scan"); }
     { Timed t(c, K_TILE_LIST);
       HIP_TRY(c, launch_tile_list(P<int32_t>(c->bin_off), g, p->sc, P<uint8_t>(c->occ),
-                                  P<int2>(c->tile_pend), P<int32_t>(c->tiles), st, s), "tile_list"); }
+                                  P<int2>(c->tile_pend), P<int32_t>(c->tiles), P<uint2>(c->blk_max), m, st, s),
+              "tile_list"); }
     { Timed t(c, K_BIN_SCATTER);
       HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, g, P<int32_t>(c->key),
                                     P<int32_t>(c->rank), P<int32_t>(c->bin_off), P<float4>(c->rec), s),
@@ -432,7 +435,7 @@ void fvr_destroy(fvr_ctx *c) {
     for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend};
+                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {

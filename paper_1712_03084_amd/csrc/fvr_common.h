@@ -92,9 +92,12 @@ hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *p
 
 // Splat, stage 1: validate and bin points by the (y, z) row of their
 // footprint origin.  key[i] = -1 for rejected points.
+int bin_count_blocks(int m);
+// blk_max: per bin_count block, the bits of its largest W and W |N_c|
+// (reduced by tile_order into st->wmax_bits, st->wnmax_bits)
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
                             const Grid &g, int32_t *bin_count, int32_t *key, int32_t *rank,
-                            DevStatus *st, hipStream_t s);
+                            uint2 *blk_max, DevStatus *st, hipStream_t s);
 // Splat, stage 2: scatter packed records (fractional voxel offsets, W, W N,
 // x footprint origin) into bin order.
 hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
@@ -111,7 +114,8 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 // tile (0 otherwise), and the indices of those tiles in list[0, st->n_busy),
 // in decreasing order of work; pend is scratch of one int2 per tile.
 hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
-                            uint8_t *occ, int2 *pend, int32_t *list, DevStatus *st, hipStream_t s);
+                            uint8_t *occ, int2 *pend, int32_t *list, const uint2 *blk_max, int m,
+                            DevStatus *st, hipStream_t s);
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
                               const int32_t *list, float2 *spec, float *v_out, hipStream_t s);

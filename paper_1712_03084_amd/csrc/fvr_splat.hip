@@ -44,7 +44,8 @@ __device__ __forceinline__ bool finite3(float a, float b, float c) {
 __global__ void __launch_bounds__(256)
 bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
                  const float *__restrict__ w, int m, Grid g, int32_t *__restrict__ bin_count,
-                 int32_t *__restrict__ key, int32_t *__restrict__ rank, DevStatus *st) {
+                 int32_t *__restrict__ key, int32_t *__restrict__ rank, uint2 *__restrict__ blk_max,
+                 DevStatus *st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     bool bad = false, rej = false;
@@ -106,14 +107,12 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        // one atomic per block, and none once a larger maximum is published;
-        // non-negative floats order like their bit patterns
+        // the block's maxima; tile_order reduces them (atomics of every block on
+        // one status word would serialise in one L2 channel); non-negative
+        // floats order like their bit patterns
         const float bw = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
         const float bn = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
-        const uint32_t cw = __hip_atomic_load(&st->wmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t cn = __hip_atomic_load(&st->wnmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__float_as_uint(bw) > cw) atomicMax(&st->wmax_bits, __float_as_uint(bw));
-        if (__float_as_uint(bn) > cn) atomicMax(&st->wnmax_bits, __float_as_uint(bn));
+        blk_max[blockIdx.x] = make_uint2(__float_as_uint(bw), __float_as_uint(bn));
     }
 }
 
@@ -499,12 +498,14 @@ size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
            g.n[0] * sizeof(float2);
 }
 
+int bin_count_blocks(int m) { return m > 0 ? (m + 255) / 256 : 0; }
+
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
                             const Grid &g, int32_t *bin_count, int32_t *key, int32_t *rank,
-                            DevStatus *st, hipStream_t s) {
+                            uint2 *blk_max, DevStatus *st, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    bin_count_kernel<<<dim3((m + 255) / 256), dim3(256), 0, s>>>(pts, nrm, w, m, g, bin_count, key,
-                                                                 rank, st);
+    bin_count_kernel<<<dim3(bin_count_blocks(m)), dim3(256), 0, s>>>(pts, nrm, w, m, g, bin_count, key,
+                                                                     rank, blk_max, st);
     return hipGetLastError();
 }
 
@@ -568,8 +569,26 @@ __device__ __forceinline__ int tile_class(int cost) {
 }
 
 __global__ void __launch_bounds__(1024)
-tile_order_kernel(const int2 *__restrict__ pend, int32_t *__restrict__ list, const DevStatus *st) {
+tile_order_kernel(const int2 *__restrict__ pend, int32_t *__restrict__ list,
+                  const uint2 *__restrict__ blk_max, int nblk, DevStatus *st) {
     __shared__ int hist[kTileClasses], cursor[kTileClasses];
+    __shared__ unsigned wmax[32], wnmax[32];
+    // the frame's largest W and W |N_c| (fixed-point units of the splat)
+    unsigned mw = 0, mn = 0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        const uint2 v = blk_max[i];
+        mw = max(mw, v.x);
+        mn = max(mn, v.y);
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        mw = max(mw, (unsigned)__shfl_xor((int)mw, d, 64));
+        mn = max(mn, (unsigned)__shfl_xor((int)mn, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wmax[threadIdx.x >> 6] = mw;
+        wnmax[threadIdx.x >> 6] = mn;
+    }
     const int n = st->n_busy;
     if (threadIdx.x < kTileClasses) hist[threadIdx.x] = 0;
     __syncthreads();
@@ -587,16 +606,26 @@ tile_order_kernel(const int2 *__restrict__ pend, int32_t *__restrict__ list, con
         const int2 e = pend[i];
         list[atomicAdd(&cursor[tile_class(e.y)], 1)] = e.x;
     }
+    if (threadIdx.x == 0) {
+        unsigned a = 0, b = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            a = max(a, wmax[w]);
+            b = max(b, wnmax[w]);
+        }
+        st->wmax_bits = a;
+        st->wnmax_bits = b;
+    }
 }
 
 hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
-                            uint8_t *occ, int2 *pend, int32_t *list, DevStatus *st, hipStream_t s) {
+                            uint8_t *occ, int2 *pend, int32_t *list, const uint2 *blk_max, int m,
+                            DevStatus *st, hipStream_t s) {
     const int ntiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     tile_list_kernel<<<dim3((ntiles + 255) / 256), dim3(256), 0, s>>>(bin_off, g, sc, ntiles, occ,
                                                                       pend, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    tile_order_kernel<<<dim3(1), dim3(1024), 0, s>>>(pend, list, st);
+    tile_order_kernel<<<dim3(1), dim3(1024), 0, s>>>(pend, list, blk_max, bin_count_blocks(m), st);
     return hipGetLastError();
 }
 

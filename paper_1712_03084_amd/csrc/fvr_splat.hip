@@ -73,20 +73,28 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
         }
     }
     // Wave-aggregated histogram: points arrive in capture (scanline) order, so
-    // a wave holds few distinct bins; one atomic per distinct bin, and each
-    // lane's rank is the group's base plus its position within the group.
+    // a wave holds few distinct bins.  The wave first splits into groups of
+    // equal bin (no memory traffic), then every group's first lane adds the
+    // group size with one atomic - all groups in the same instruction, a single
+    // round trip - and each lane's rank is the group's base plus its position
+    // within the group.
     unsigned long long todo = __ballot(k >= 0);
-    int myrank = 0;
+    int leader = lane, pos = 0, size = 0;
     while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int lk = __shfl(k, leader, 64);
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const int lk = __shfl(k, l, 64);
         const unsigned long long grp = __ballot(k == lk);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&bin_count[lk], __popcll(grp));
-        base = __shfl(base, leader, 64);
-        if (k == lk) myrank = base + __popcll(grp & ((1ull << lane) - 1ull));
+        if (k == lk) {
+            leader = l;
+            pos = __popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == l) size = __popcll(grp);
         todo &= ~grp;
     }
+    int base = 0;
+    if (k >= 0 && leader == lane) base = atomicAdd(&bin_count[k], size);
+    base = __shfl(base, leader, 64);
+    const int myrank = base + pos;
     if (i < m) {
         key[i] = k;
         if (k >= 0) rank[i] = myrank;

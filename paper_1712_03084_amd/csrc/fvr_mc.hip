@@ -30,6 +30,13 @@ namespace fvr {
 __constant__ uint8_t c_mc_count[256];
 __constant__ int8_t c_mc_edges[256 * kMcRow];
 
+// The classification kernels copy the triangle counts into LDS: a lookup is
+// then an LDS read, so it never waits for the field loads still in flight.
+__device__ __forceinline__ void mc_count_table(uint8_t *t) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) t[i] = c_mc_count[i];
+    __syncthreads();
+}
+
 constexpr int kMcThreads = 256;
 constexpr int kMcPpt = 4;                       // grid points per thread
 constexpr int kMcPerBlock = kMcThreads * kMcPpt;
@@ -398,6 +405,8 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
                 int32_t *__restrict__ blk_counts, uint32_t *__restrict__ codes,
                 uint8_t *__restrict__ cases_out, DevStatus *st) {
     __shared__ int red[4];
+    __shared__ uint8_t s_ntri[256];
+    mc_count_table(s_ntri);
     uint32_t code4 = 0;  // the 4 point codes, byte i for point l0 + i
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -421,7 +430,7 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
                 nv += __popc(eb[i]);
                 code4 |= (uint32_t)(cs[i] >= 0 ? cs[i] : eb[i]) << (8 * i);
                 if (cs[i] >= 0) {
-                    const int c = c_mc_count[cs[i]];
+                    const int c = (int)s_ntri[cs[i]];
                     nt += c;
                     na += c > 0;
                     if (cases_out)
@@ -441,7 +450,7 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
                     nv += __popc(eb);
                     code4 |= (uint32_t)(cs >= 0 ? cs : eb) << (8 * i);
                     if (cs >= 0) {
-                        const int c = c_mc_count[cs];
+                        const int c = (int)s_ntri[cs];
                         nt += c;
                         na += c > 0;
                         if (cases_out)
@@ -511,10 +520,12 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
                    int32_t *__restrict__ vidx, int4 *__restrict__ cells, const DevStatus *st,
                    MeshCaps caps) {
     __shared__ int red[12];
+    __shared__ uint8_t s_ntri[256];
     if (!mesh_fits(st, caps)) return;
     // a block without vertices and active cells has nothing to write (and
     // mc_count stored no codes for it)
     if (blk_counts[3 * blockIdx.x] == 0 && blk_counts[3 * blockIdx.x + 2] == 0) return;
+    mc_count_table(s_ntri);
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
     const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
@@ -560,7 +571,7 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
     for (int i = 0; i < kMcPpt; ++i) {
         cnt[0] += __popc(eb[i]);
         if (cs[i] >= 0) {
-            const int c = c_mc_count[cs[i]];
+            const int c = (int)s_ntri[cs[i]];
             cnt[1] += c;
             cnt[2] += c > 0;
         }
@@ -593,7 +604,7 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
             }
         }
         if (cs[i] >= 0) {
-            const int c = c_mc_count[cs[i]];
+            const int c = (int)s_ntri[cs[i]];
             if (c > 0) {
                 cells[abase] = make_int4((int)l, cs[i], tbase, 0);
                 ++abase;

@@ -525,6 +525,9 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
     // a block without vertices and active cells has nothing to write (and
     // mc_count stored no codes for it)
     if (blk_counts[3 * blockIdx.x] == 0 && blk_counts[3 * blockIdx.x + 2] == 0) return;
+    // the block's global offsets, loaded before anything waits on the codes
+    int vbase = blk_off[3 * blockIdx.x + 0], tbase = blk_off[3 * blockIdx.x + 1],
+        abase = blk_off[3 * blockIdx.x + 2];
     mc_count_table(s_ntri);
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -577,9 +580,9 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
         }
     }
     block_excl_scan3(cnt, red);
-    int vbase = blk_off[3 * blockIdx.x + 0] + cnt[0];
-    int tbase = blk_off[3 * blockIdx.x + 1] + cnt[1];
-    int abase = blk_off[3 * blockIdx.x + 2] + cnt[2];
+    vbase += cnt[0];
+    tbase += cnt[1];
+    abase += cnt[2];
     int x = qx, y = qy, z = qz;
     for (int i = 0; i < kMcPpt; ++i) {
         const size_t l = l0 + i;

@@ -541,16 +541,15 @@ tile_list_kernel(const int32_t *__restrict__ bin_off, Grid g, SplatConsts sc, in
         const int y1 = min(y0 + sc.ty, Ny) - 1, z1 = min(z0 + sc.tz, Nz) - 1;  // last tile rows
         const int iz_lo = max(z0 - 2, -1), iz_hi = min(z0 + sc.tz, Nz - 1);
         const int iy_lo = max(y0 - 2, -1), iy_hi = min(y0 + sc.ty, Ny - 1);
+        // the loads of a bin row are independent: unrolled, they are in flight together
         for (int iz = iz_lo; iz <= iz_hi; ++iz) {
             const int nz = min(iz + 2, z1) - max(iz - 1, z0) + 1;
             const int row = (iz + 1) * (Ny + 1) + 1;
-            int prev = bin_off[row + iy_lo];
             long long sum = 0;
-            for (int iy = iy_lo; iy <= iy_hi; ++iy) {
-                const int next = bin_off[row + iy + 1];
-                sum += (long long)(next - prev) * (min(iy + 2, y1) - max(iy - 1, y0) + 1);
-                prev = next;
-            }
+#pragma unroll 8
+            for (int iy = iy_lo; iy <= iy_hi; ++iy)
+                sum += (long long)(bin_off[row + iy + 1] - bin_off[row + iy]) *
+                       (min(iy + 2, y1) - max(iy - 1, y0) + 1);
             cost += nz * sum;
         }
         occ[tile] = cost > 0 ? 1 : 0;

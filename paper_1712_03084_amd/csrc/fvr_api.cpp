@@ -227,10 +227,11 @@ fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan
         HIP_TRY(c, hipMemcpy(np.tw, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice),
                 "hipMemcpy(twiddles)");
         for (int a = 0; a < 3; ++a) np.ax[a].tw = np.tw + offs[a];
-        // splat tile: ty x tz full x-rows, 4 int64 planes <= 128 KiB of LDS
+        // splat tile: ty x tz full x-rows, R = ty tz rows with R Nx within the
+        // kernel's plane bound (4 <= R <= 64; Nx <= 512 keeps 4 rows in bound)
         const int nx = dims[0];
         int R = 64;
-        while (R > 4 && R * nx > 4096) R /= 2;
+        while (R > 4 && R * nx > splat_max_plane()) R /= 2;
         np.sc.tz = R >= 64 ? 8 : R >= 32 ? 8 : R >= 16 ? 4 : R >= 8 ? 4 : 2;
         np.sc.ty = R / np.sc.tz;
         np.sc.tiles_y = (dims[1] + np.sc.ty - 1) / np.sc.ty;

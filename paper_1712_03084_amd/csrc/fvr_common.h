@@ -120,6 +120,8 @@ hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const G
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
                               const int32_t *list, float2 *spec, float *v_out, hipStream_t s);
 int splat_blocks();
+// Voxels of one channel plane of a splat tile (tile rows x Nx), at most.
+int splat_max_plane();
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc);
 
 // Forward y transform of the three planes, combining the x and y

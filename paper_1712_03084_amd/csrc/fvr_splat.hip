@@ -25,8 +25,8 @@
 
 namespace fvr {
 
-constexpr int kSplatThreads = 1024;
-constexpr int kSplatMaxPlane = 4096;  // voxels per channel plane of a tile, at most
+constexpr int kSplatThreads = 512;
+constexpr int kSplatMaxPlane = 2048;  // voxels per channel plane of a tile, at most
 constexpr int kMaxBins = 128;   // (ty+3)(tz+3) footprint-origin bins per tile, at most
 constexpr int kChunkPts = 8;    // consecutive points of a bin per splat work item
 
@@ -495,11 +495,15 @@ hipError_t splat_configure() {
     int dev = 0, cus = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess && cus > 0) g_splat_blocks = cus;  // one persistent block per CU
+    // two persistent blocks per CU (each takes under half the LDS), so one
+    // block's setup and epilogue overlap the other's accumulation
+    if (e == hipSuccess && cus > 0) g_splat_blocks = 2 * cus;
     return e;
 }
 
 int splat_blocks() { return g_splat_blocks; }
+
+int splat_max_plane() { return kSplatMaxPlane; }
 
 size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
     return (size_t)4 * sc.ty * sc.tz * (g.n[0] + 5) * sizeof(unsigned long long) +

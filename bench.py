@@ -64,11 +64,11 @@ def kernel_alg_bytes(dims, m, nv, nt):
 # build flags): a stored counter reading is used only while these are unchanged.
 _CSRC = os.path.join(ROOT, "paper_1712_03084_amd", "csrc")
 KERNEL_SOURCES = {
-    "prep": "fvr_mc.hip", "bin_count": "fvr_splat.hip", "bin_scan": "fvr_mc.hip", "tile_list": "fvr_splat.hip", "tile_order": "fvr_splat.hip",
-    "bin_scatter": "fvr_splat.hip", "splat_fft_x": "fvr_splat.hip", "fft_y_fwd": "fvr_fft.hip",
-    "fft_z_solve": "fvr_fft.hip", "fft_y_inv": "fvr_fft.hip", "fft_x_c2r": "fvr_fft.hip",
-    "level": "fvr_mc.hip", "mc_count": "fvr_mc.hip", "mc_scan": "fvr_mc.hip",
-    "mc_generate": "fvr_mc.hip", "mc_triangles": "fvr_mc.hip",
+    "prep": "fvr_mc.hip", "bin_count": "fvr_splat.hip", "tile_list": "fvr_splat.hip",
+    "tile_order": "fvr_splat.hip", "bin_scatter": "fvr_splat.hip", "splat_fft_x": "fvr_splat.hip",
+    "fft_y_fwd": "fvr_fft.hip", "fft_z_solve": "fvr_fft.hip", "fft_y_inv": "fvr_fft.hip",
+    "fft_x_c2r": "fvr_fft.hip", "level": "fvr_mc.hip", "mc_count": "fvr_mc.hip",
+    "mc_scan": "fvr_mc.hip", "mc_generate": "fvr_mc.hip", "mc_triangles": "fvr_mc.hip",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_proxy256.txt")
 
@@ -79,7 +79,7 @@ def kernel_source_digest(name):
     import hashlib
     h = hashlib.sha256()
     for f in (os.path.join(_CSRC, KERNEL_SOURCES[name]), os.path.join(_CSRC, "fvr_common.h"),
-              os.path.join(_CSRC, "fvr_fft_engine.h"),
+              os.path.join(_CSRC, "fvr_fft_engine.h"), os.path.join(_CSRC, "fvr_scan.h"),
               os.path.join(ROOT, "paper_1712_03084_amd", "build.py")):
         with open(f, "rb") as fh:
             h.update(fh.read())

@@ -25,12 +25,12 @@ using namespace fvr;
 namespace {
 
 enum KernelId {
-    K_PREP, K_BIN_COUNT, K_BIN_SCAN, K_TILE_LIST, K_BIN_SCATTER, K_SPLAT_FFT_X, K_FFT_Y_FWD,
+    K_PREP, K_BIN_COUNT, K_TILE_LIST, K_BIN_SCATTER, K_SPLAT_FFT_X, K_FFT_Y_FWD,
     K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_LEVEL, K_MC_COUNT, K_MC_SCAN,
     K_MC_GENERATE, K_MC_TRIANGLES, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {
-    "prep", "bin_count", "bin_scan", "tile_list", "bin_scatter", "splat_fft_x", "fft_y_fwd",
+    "prep", "bin_count", "tile_list", "bin_scatter", "splat_fft_x", "fft_y_fwd",
     "fft_z_solve", "fft_y_inv", "fft_x_c2r", "level", "mc_count", "mc_scan",
     "mc_generate", "mc_triangles"};
 
@@ -291,8 +291,8 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     HIP_TRY(c, ensure(c->blk_max, sizeof(uint2) * (size_t)std::max(1, bin_count_blocks(m))), "alloc block maxima");
     HIP_TRY(c, ensure(c->zocc, (size_t)g.n[2]), "alloc plane occupancy");
     // sized for both scans of the frame before anything is enqueued
-    const int scan_items = std::max(scan_partials(nbins), scan_partials(mc_blocks(g)));
-    HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_items), "alloc scan scratch");
+    const int scan_items = std::max(bin_scan_tiles(nbins), 3 * scan_partials(mc_blocks(g)));
+    HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * (size_t)scan_items), "alloc scan scratch");
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(st, P<int32_t>(c->bin_count), nbins, s), "prep"); }
@@ -300,11 +300,9 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
       HIP_TRY(c, launch_bin_count(f->points, f->normals, f->weights, m, g, P<int32_t>(c->bin_count),
                                   P<int32_t>(c->key), P<int32_t>(c->rank), P<uint2>(c->blk_max), st, s),
               "bin_count"); }
-    { Timed t(c, K_BIN_SCAN);
-      HIP_TRY(c, launch_scan(P<int32_t>(c->bin_count), P<int32_t>(c->bin_off), nbins, 1,
-                             P<int32_t>(c->scan_part), nullptr, s), "bin_scan"); }
     { Timed t(c, K_TILE_LIST);
-      HIP_TRY(c, launch_tile_list(P<int32_t>(c->bin_off), g, p->sc, P<uint8_t>(c->occ),
+      HIP_TRY(c, launch_tile_list(P<int32_t>(c->bin_count), P<int32_t>(c->bin_off), nbins,
+                                  P<int32_t>(c->scan_part), g, p->sc, P<uint8_t>(c->occ),
                                   P<int2>(c->tile_pend), P<int32_t>(c->tiles), P<uint2>(c->blk_max), m, st, s),
               "tile_list"); }
     { Timed t(c, K_BIN_SCATTER);

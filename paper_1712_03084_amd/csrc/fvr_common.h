@@ -83,7 +83,7 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 // Reset the status block and zero `nbins` bin counters in one launch.
 hipError_t launch_prep(DevStatus *st, int32_t *bins, int nbins, hipStream_t s);
 
-// Exclusive scan of `n` items of `C` interleaved int32 components (C = 1 or 3):
+// Exclusive scan of `n` items of `C` interleaved int32 components (C = 3):
 // out[i*C + c] = sum_{j<i} in[j*C + c]; out[n*C + c] = total; totals[c] = total.
 // `partial` is scratch of scan_partials(n) * C ints.
 int scan_partials(int n);
@@ -112,10 +112,13 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 // are left unwritten (they are zero); occupied tiles set occ[tile] = 1.
 // Busy splat tiles: occ[tile] = 1 when some point's footprint reaches the
 // tile (0 otherwise), and the indices of those tiles in list[0, st->n_busy),
-// in decreasing order of work; pend is scratch of one int2 per tile.
-hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
-                            uint8_t *occ, int2 *pend, int32_t *list, const uint2 *blk_max, int m,
-                            DevStatus *st, hipStream_t s);
+// in decreasing order of work; pend is scratch of one int2 per tile.  The
+// same two launches scan the bin counts into bin_off (nbins + 1 ints, the
+// last the total); partial is scratch of bin_scan_tiles(nbins) ints.
+int bin_scan_tiles(int nbins);
+hipError_t launch_tile_list(const int32_t *bin_count, int32_t *bin_off, int nbins, int32_t *partial,
+                            const Grid &g, const SplatConsts &sc, uint8_t *occ, int2 *pend,
+                            int32_t *list, const uint2 *blk_max, int m, DevStatus *st, hipStream_t s);
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
                               const int32_t *list, float2 *spec, float *v_out, hipStream_t s);

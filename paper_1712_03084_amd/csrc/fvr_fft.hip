@@ -407,21 +407,24 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
         tw[i] = twg[i];
     }
     __syncthreads();
-    const size_t plane = (size_t)N * Ny * Hp;
-    const size_t zs = (size_t)Ny * Hp;
+    // element offsets from the block's base fit 32 bits (3 planes of at most
+    // 512 * 512 * 272 bins): a uniform 64-bit base plus 32-bit lane offsets
+    const unsigned zs = (unsigned)Ny * Hp;
+    const unsigned plane2 = 2u * (unsigned)N * zs;
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
     const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
     const bool col = k0 + c < H;
-    float2 *p = spec + (size_t)ky * Hp + k0 + c;
+    float2 *p = spec + ((size_t)ky * Hp + k0);
     float2 a[N1], b[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
         const int r = Pn::in_row(t, n1);
         const bool ld = col && keep[r];
-        a[n1] = ld ? p[(size_t)r * zs] : make_float2(0.f, 0.f);
-        b[n1] = ld ? p[2 * plane + (size_t)r * zs] : make_float2(0.f, 0.f);
+        const unsigned o = (unsigned)r * zs + (unsigned)c;
+        a[n1] = ld ? p[o] : make_float2(0.f, 0.f);
+        b[n1] = ld ? p[plane2 + o] : make_float2(0.f, 0.f);
     }
     Pn::template run<-1>(a, ex, tw, c, t);
     Pn::template run<-1>(b, ex, tw, c, t);
@@ -434,7 +437,8 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
         const int kz = Pn::out_row(t, i);
         const float wzf = (float)kappa(kz, N) * g.wstep[2];
         const float w2 = wxy + wzf * wzf;
-        const float inv = w2 > 0.f ? 1.0f / w2 : 0.0f;
+        // v_rcp_f32 (about 1 ulp) in place of a correctly rounded divide
+        const float inv = w2 > 0.f ? __builtin_amdgcn_rcpf(w2) : 0.0f;
         const float wz = deriv_w(kz, N, g.wstep[2]);
         a[i] = make_float2((a[i].x - wz * b[i].y) * inv, (a[i].y + wz * b[i].x) * inv);
     }
@@ -442,7 +446,7 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
     Pn::template run<+1>(a, ex, tw, c, t);
 #pragma unroll
     for (int i = 0; i < N1; ++i)
-        if (col) p[(size_t)Pn::out_row(t, i) * zs] = a[i];
+        if (col) p[(unsigned)Pn::out_row(t, i) * zs + (unsigned)c] = a[i];
 }
 
 template <int N1, int N2>

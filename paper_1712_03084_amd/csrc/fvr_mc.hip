@@ -14,7 +14,10 @@
 //               and whether it is active; block totals -> blk_counts
 //               and, for blocks the surface passes, one code byte per point
 //               (the case, or the edge bits on the upper borders)
-//   scan        exclusive scan of the block totals
+//   scan        exclusive scan of the block totals (two launches; folding it
+//               into the neighbouring kernels with group totals kept by
+//               atomics measured slower: 117 us against 79 us for the four
+//               marching-cubes stages at 256^3)
 //   mc_generate from the codes (blocks without vertices or active cells exit
 //               at once), block-scan, write each vertex at its global rank
 //               (vertex order = (linear index, axis)), record the vertex id of
@@ -24,6 +27,7 @@
 #include <algorithm>
 
 #include "fvr_common.h"
+#include "fvr_scan.h"
 
 namespace fvr {
 
@@ -79,118 +83,31 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Inclusive scan of one int across a 64-lane wave.
-__device__ __forceinline__ int wave_incl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
 // Exclusive scan of n items of C interleaved components in two kernels:
-//   scan_reduce  block b sums items [b T, (b+1) T) -> partial[b]
-//   scan_down    block b adds partial[0..b) (at most a few hundred) and scans
-//                its tile; the last block also writes the totals.
-// Each thread owns kScanIpt consecutive items.
-constexpr int kScanBlock = 256;
-constexpr int kScanIpt = 8;
-constexpr int kScanTile = kScanBlock * kScanIpt;
-
+//   scan_reduce  block b sums scan tile b -> partial[b]
+//   scan_down    block b adds partial[0..b) and scans its tile; the last
+//                block also writes the totals.
 template <int C>
 __global__ void __launch_bounds__(kScanBlock)
 scan_reduce_kernel(const int32_t *__restrict__ in, int n, int32_t *__restrict__ partial) {
-    __shared__ int red[C][kScanBlock / 64];
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
-    int s[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) s[c] = 0;
-#pragma unroll
-    for (int j = 0; j < kScanIpt; ++j) {
-        const int i = base + j;
-        if (i < n) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) s[c] += in[(size_t)i * C + c];
-        }
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        int v = s[c];
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-        if (lane == 0) red[c][wid] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < C) {
-        int t = 0;
-        for (int w = 0; w < kScanBlock / 64; ++w) t += red[threadIdx.x][w];
-        partial[blockIdx.x * C + threadIdx.x] = t;
-    }
+    scan_tile_sum<C>(in, n, blockIdx.x, partial);
 }
 
 template <int C>
 __global__ void __launch_bounds__(kScanBlock)
 scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int n,
                  const int32_t *__restrict__ partial, int32_t *totals) {
-    __shared__ int wsum[C][kScanBlock / 64];
-    __shared__ int boff[C];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (threadIdx.x < C) {
-        int t = 0;
-        for (int b = 0; b < (int)blockIdx.x; ++b) t += partial[b * C + threadIdx.x];
-        boff[threadIdx.x] = t;
-    }
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
-    int v[kScanIpt][C], s[C], incl[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) s[c] = 0;
-#pragma unroll
-    for (int j = 0; j < kScanIpt; ++j) {
-        const int i = base + j;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            v[j][c] = i < n ? in[(size_t)i * C + c] : 0;
-            s[c] += v[j][c];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        incl[c] = wave_incl_scan(s[c]);
-        if (lane == 63) wsum[c][wid] = incl[c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        int run = boff[c] + incl[c] - s[c];
-        for (int w = 0; w < wid; ++w) run += wsum[c][w];
-#pragma unroll
-        for (int j = 0; j < kScanIpt; ++j) {
-            const int i = base + j;
-            if (i < n) out[(size_t)i * C + c] = run;
-            run += v[j][c];
-        }
-        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) {
-            out[(size_t)n * C + c] = run;
-            if (totals) totals[c] = run;
-        }
-    }
+    scan_tile_down<C>(in, out, n, partial, blockIdx.x, gridDim.x, totals);
 }
 
-int scan_partials(int n) { return (n + kScanTile - 1) / kScanTile; }
+int scan_partials(int n) { return scan_tiles(n); }
 
 hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *partial,
                        int32_t *totals, hipStream_t s) {
     const int nb = n > 0 ? scan_partials(n) : 1;
-    if (C == 1) {
-        scan_reduce_kernel<1><<<nb, kScanBlock, 0, s>>>(in, n, partial);
-        scan_down_kernel<1><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
-    } else {
-        scan_reduce_kernel<3><<<nb, kScanBlock, 0, s>>>(in, n, partial);
-        scan_down_kernel<3><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
-    }
+    if (C != 3) return hipErrorInvalidValue;
+    scan_reduce_kernel<3><<<nb, kScanBlock, 0, s>>>(in, n, partial);
+    scan_down_kernel<3><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
     return hipGetLastError();
 }
 

@@ -20,8 +20,11 @@
 //               accumulates S and D in LDS, forms V, runs the real FFT of
 //               every x-row in LDS and writes the three half-spectrum planes
 //               (the x component times j w_x).
+#include <algorithm>
+
 #include "fvr_common.h"
 #include "fvr_fft_engine.h"
+#include "fvr_scan.h"
 
 namespace fvr {
 
@@ -533,10 +536,13 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
 // One thread per splat tile: the point-rows that fall into it (each point of
 // bin (iy, iz) adds one item row per tile row within its footprint rows
 // iy - 1 .. iy + 2, iz - 1 .. iz + 2).  Busy tiles get occ = 1 and an entry
-// (tile, cost) in `pend`, in no particular order.
+// (tile, cost) in `pend`, in no particular order.  Block b < nscan also sums
+// scan tile b of the bin counts into partial[b] (first half of the bin scan).
 __global__ void __launch_bounds__(256)
-tile_list_kernel(const int32_t *__restrict__ bin_off, Grid g, SplatConsts sc, int ntiles,
+tile_list_kernel(const int32_t *__restrict__ bin_count, int nbins, int nscan,
+                 int32_t *__restrict__ partial, Grid g, SplatConsts sc, int ntiles,
                  uint8_t *__restrict__ occ, int2 *__restrict__ pend, DevStatus *st) {
+    if ((int)blockIdx.x < nscan) scan_tile_sum<1>(bin_count, nbins, blockIdx.x, partial);
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     long long cost = 0;
     if (tile < ntiles) {
@@ -552,8 +558,7 @@ tile_list_kernel(const int32_t *__restrict__ bin_off, Grid g, SplatConsts sc, in
             long long sum = 0;
 #pragma unroll 8
             for (int iy = iy_lo; iy <= iy_hi; ++iy)
-                sum += (long long)(bin_off[row + iy + 1] - bin_off[row + iy]) *
-                       (min(iy + 2, y1) - max(iy - 1, y0) + 1);
+                sum += (long long)bin_count[row + iy] * (min(iy + 2, y1) - max(iy - 1, y0) + 1);
             cost += nz * sum;
         }
         occ[tile] = cost > 0 ? 1 : 0;
@@ -579,11 +584,20 @@ __device__ __forceinline__ int tile_class(int cost) {
     return 2 * msb + (msb > 0 ? (cost >> (msb - 1)) & 1 : 0);
 }
 
-__global__ void __launch_bounds__(1024)
-tile_order_kernel(const int2 *__restrict__ pend, int32_t *__restrict__ list,
-                  const uint2 *__restrict__ blk_max, int nblk, DevStatus *st) {
+// Blocks 0 .. nscan - 1 finish the bin scan (scan tile b on top of the
+// partial sums of tile_list); block nscan reduces the weight maxima and sorts
+// the busy tiles.
+__global__ void __launch_bounds__(256)
+tile_order_kernel(const int32_t *__restrict__ bin_count, int32_t *__restrict__ bin_off, int nbins,
+                  int nscan, const int32_t *__restrict__ partial, const int2 *__restrict__ pend,
+                  int32_t *__restrict__ list, const uint2 *__restrict__ blk_max, int nblk,
+                  DevStatus *st) {
+    if ((int)blockIdx.x < nscan) {
+        scan_tile_down<1>(bin_count, bin_off, nbins, partial, blockIdx.x, nscan);
+        return;
+    }
     __shared__ int hist[kTileClasses], cursor[kTileClasses];
-    __shared__ unsigned wmax[32], wnmax[32];
+    __shared__ unsigned wmax[kScanBlock / 64], wnmax[kScanBlock / 64];
     // the frame's largest W and W |N_c| (fixed-point units of the splat)
     unsigned mw = 0, mn = 0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
@@ -628,17 +642,22 @@ tile_order_kernel(const int2 *__restrict__ pend, int32_t *__restrict__ list,
     }
 }
 
-hipError_t launch_tile_list(const int32_t *bin_off, const Grid &g, const SplatConsts &sc,
-                            uint8_t *occ, int2 *pend, int32_t *list, const uint2 *blk_max, int m,
-                            DevStatus *st, hipStream_t s) {
+hipError_t launch_tile_list(const int32_t *bin_count, int32_t *bin_off, int nbins, int32_t *partial,
+                            const Grid &g, const SplatConsts &sc, uint8_t *occ, int2 *pend,
+                            int32_t *list, const uint2 *blk_max, int m, DevStatus *st, hipStream_t s) {
     const int ntiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
-    tile_list_kernel<<<dim3((ntiles + 255) / 256), dim3(256), 0, s>>>(bin_off, g, sc, ntiles, occ,
-                                                                      pend, st);
+    const int nscan = scan_tiles(nbins);
+    const int blocks = std::max((ntiles + 255) / 256, nscan);
+    tile_list_kernel<<<dim3(blocks), dim3(256), 0, s>>>(bin_count, nbins, nscan, partial, g, sc, ntiles,
+                                                       occ, pend, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    tile_order_kernel<<<dim3(1), dim3(1024), 0, s>>>(pend, list, blk_max, bin_count_blocks(m), st);
+    tile_order_kernel<<<dim3(nscan + 1), dim3(kScanBlock), 0, s>>>(bin_count, bin_off, nbins, nscan, partial,
+                                                                 pend, list, blk_max, bin_count_blocks(m), st);
     return hipGetLastError();
 }
+
+int bin_scan_tiles(int nbins) { return scan_tiles(nbins); }
 
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,

@@ -26,12 +26,12 @@ namespace {
 
 enum KernelId {
     K_PREP, K_BIN_COUNT, K_TILE_LIST, K_BIN_SCATTER, K_SPLAT_FFT_X, K_FFT_Y_FWD,
-    K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_LEVEL, K_MC_COUNT, K_MC_SCAN,
+    K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_FFT_YX_INV, K_LEVEL, K_MC_COUNT, K_MC_SCAN,
     K_MC_GENERATE, K_MC_TRIANGLES, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {
     "prep", "bin_count", "tile_list", "bin_scatter", "splat_fft_x", "fft_y_fwd",
-    "fft_z_solve", "fft_y_inv", "fft_x_c2r", "level", "mc_count", "mc_scan",
+    "fft_z_solve", "fft_y_inv", "fft_x_c2r", "fft_yx_inv", "level", "mc_count", "mc_scan",
     "mc_generate", "mc_triangles"};
 
 thread_local std::string g_error;
@@ -120,9 +120,14 @@ struct Timed {
     Timed(fvr_ctx *ctx, int k) : c(ctx), kid(k) {
         if (!((c->timing_mask >> k) & 1u)) return;
         if (c->ev_used == c->ev.size()) {
+            // timing-only events: no system-scope fence (and cache write-back)
+            // at each record; they are read after a stream synchronisation
             hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess) return;
-            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+            if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return;
+            if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
             c->ev.push_back({a, b});
             c->ev_kid.push_back(k);
         }
@@ -318,8 +323,13 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
       HIP_TRY(c, launch_fft_y_fwd(sp, P<uint8_t>(c->occ), P<uint8_t>(c->zocc), g, p->ax[1], s), "fft_y_fwd"); }
     { Timed t(c, K_FFT_Z_SOLVE);
       HIP_TRY(c, launch_fft_z_solve(sp, P<uint8_t>(c->zocc), g, p->ax[2], s), "fft_z_solve"); }
-    { Timed t(c, K_FFT_Y_INV); HIP_TRY(c, launch_fft_y_inv(sp, g, p->ax[1], s), "fft_y_inv"); }
-    { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, g, p->ax[0], s), "fft_x_c2r"); }
+    if (fft_yx_fused(g)) {
+        Timed t(c, K_FFT_YX_INV);
+        HIP_TRY(c, launch_fft_yx_inv(sp, field, g, p->ax[1], s), "fft_yx_inv");
+    } else {
+        { Timed t(c, K_FFT_Y_INV); HIP_TRY(c, launch_fft_y_inv(sp, g, p->ax[1], s), "fft_y_inv"); }
+        { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, g, p->ax[0], s), "fft_x_c2r"); }
+    }
     return FVR_OK;
 }
 

@@ -140,6 +140,11 @@ hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, 
                               hipStream_t s);
 // Inverse y transform of plane 0.
 hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
+// Both inverse passes below in one kernel (one block per z plane; the plane
+// does not go back to HBM between them), for Nx = Ny = 256: fft_yx_fused(g).
+bool fft_yx_fused(const Grid &g);
+hipError_t launch_fft_yx_inv(const float2 *spec, float *A, const Grid &g, const FftAxis &ay,
+                             hipStream_t s);
 // Inverse real FFT along x of plane 0, scaled by 1/n -> A (Nz, Ny, Nx).
 hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const FftAxis &ax,
                             hipStream_t s);

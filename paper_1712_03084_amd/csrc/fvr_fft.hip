@@ -538,6 +538,133 @@ pen_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
 }
 
 // Pencil factorisation of a transform length, or 0 when it has none.
+// Inverse y transform and inverse real x transform of one z plane in one
+// block, for Nx = Ny = 256: the plane's y-inverse spectrum stays on chip
+// (registers, then LDS) instead of making a round trip through HBM between
+// two passes.  1024 threads in 4 groups of 256; group q runs the y pencil on
+// column chunks q and q + 4 (kx < 128).  The kx = 0 and kx = 128 columns are
+// spectra of real sequences along y (Hermitian in ky), so they share one
+// transform: Z = X_0 + i X_128 gives x_0 = Re, x_128 = Im.  Then, for each
+// half of the rows, the y-inverse rows go to LDS, each group packs 16 pairs
+// of real rows as complex rows (as the c2r pass does), transforms them along
+// x and the real rows leave through LDS as 16-byte stores.
+constexpr int kYx = 256;
+constexpr int kYxThreads = 1024;
+constexpr int kYxYP = kYx / 2 + 1;  // LDS pitch of a y-inverse row (complex)
+constexpr int kYxOP = kYx + 4;      // LDS pitch of a real output row (float)
+using PenYx = Pencil<16, 16>;
+constexpr int kYxBuf = 4 * PenYx::EX;  // float2: four exchange buffers
+static_assert(kYxBuf >= (kYx / 2) * kYxYP, "half plane of y-inverse rows fits");
+static_assert(2 * kYxBuf >= (kYx / 2) * kYxOP, "half plane of output rows fits");
+
+__global__ void __launch_bounds__(kYxThreads)
+yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
+                 const float2 *__restrict__ twg, float scale) {
+    using Pn = PenYx;
+    constexpr int N = kYx;
+    extern __shared__ __attribute__((aligned(16))) float2 smem[];
+    float2 *buf = smem;            // exchange buffers / y-inverse rows / output rows
+    float2 *tw = smem + kYxBuf;    // w_256^m (the same table serves x and y)
+    float2 *nyq = tw + N;          // the Nyquist column kx = 128
+    const int grp = threadIdx.x >> 8, lt = threadIdx.x & 255;
+    const int c = lt & 15, t = lt >> 4;
+    const int z = blockIdx.x, Hp = g.Hp;
+    const float2 *P = spec + (size_t)z * N * Hp;
+    float2 *ex = buf + grp * Pn::EX;
+    if (threadIdx.x < N) {
+        tw[threadIdx.x] = twg[threadIdx.x];
+        nyq[threadIdx.x] = P[(size_t)threadIdx.x * Hp + N / 2];
+    }
+
+    // y-inverse of chunks grp and grp + 4 (columns 16 ch + c)
+    // uniform row bases plus one 32-bit lane offset (in_row(t, n1) = t + 16 n1)
+    float2 a[2][16];
+    const unsigned lo = (unsigned)t * Hp + 16u * grp + c;
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+        const float2 *Pr = P + (size_t)(16 * n1) * Hp;
+        a[0][n1] = Pr[lo];
+        a[1][n1] = Pr[lo + 64u];
+    }
+    __syncthreads();  // twiddles and the Nyquist column
+    if (grp == 0 && c == 0) {
+        // column 0 carries the Nyquist column in its imaginary part
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const float2 w = nyq[Pn::in_row(t, n1)];
+            a[0][n1] = make_float2(a[0][n1].x - w.y, a[0][n1].y + w.x);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) Pn::template run<+1>(a[h], ex, tw, c, t);
+    // finish both transforms before the row writes (interleaving them raises
+    // the register peak past 128 and spills)
+    __builtin_amdgcn_sched_barrier(0);
+
+    float *O = reinterpret_cast<float *>(buf);
+    // out_row(t, i) = t + 16 i: row y lies in half y / 128 = i / 8, at
+    // y - 128 half = out_row(t, i mod 8).  The loop body handles a[.][0..7];
+    // the second half's values move down at its end.
+    static_assert(Pn::Q == 1, "output row t + 16 i");
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        __syncthreads();  // exchange buffers (or the previous half's output rows) free
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kx = 16 * (grp + 4 * h) + c;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = Pn::out_row(t, i);
+                if (kx == 0) {
+                    buf[r * kYxYP] = make_float2(a[h][i].x, 0.f);
+                    buf[r * kYxYP + N / 2] = make_float2(a[h][i].y, 0.f);
+                } else {
+                    buf[r * kYxYP + kx] = a[h][i];
+                }
+                a[h][i] = a[h][i + 8];
+            }
+        }
+        __syncthreads();
+        // group grp packs real rows (2p, 2p + 1), p = 16 grp + c, as
+        // Z[k] = X_a[k] + i X_b[k] over the full length (X[N-k] = conj X[k])
+        const int ra = 2 * (16 * grp + c), rb = ra + 1;
+        float2 x[16];
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const int k = Pn::in_row(t, n1);
+            const int kk = k <= N / 2 ? k : N - k;
+            float2 xa = buf[ra * kYxYP + kk], xb = buf[rb * kYxYP + kk];
+            if (kk == 0 || kk == N / 2) {
+                xa.y = 0.f;
+                xb.y = 0.f;
+            }
+            x[n1] = k <= N / 2 ? make_float2(xa.x - xb.y, xa.y + xb.x)
+                               : make_float2(xa.x + xb.y, xb.x - xa.y);
+        }
+        __syncthreads();  // the rows are read: buf becomes the exchange buffers
+        Pn::template run<+1>(x, ex, tw, c, t);
+        // every group is past the exchange (run ends with a block barrier)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int k = Pn::out_row(t, i);
+            O[ra * kYxOP + k] = x[i].x * scale;
+            O[rb * kYxOP + k] = x[i].y * scale;
+        }
+        __syncthreads();
+        constexpr int Q4 = N / 4;  // float4 per real row
+        float *dst = A + ((size_t)z * N + 128 * half) * N;
+#pragma unroll
+        for (int u = 0; u < 128 * Q4 / kYxThreads; ++u) {
+            const int i = u * kYxThreads + threadIdx.x;
+            const int r = i / Q4, q = i - r * Q4;
+            *reinterpret_cast<float4 *>(dst + (unsigned)(r * N + 4 * q)) =
+                *reinterpret_cast<const float4 *>(O + r * kYxOP + 4 * q);
+        }
+    }
+}
+
+size_t yx_inv256_lds() { return (size_t)(kYxBuf + 2 * kYx) * sizeof(float2); }
+
 static int pencil_code(int n) {
     switch (n) {
         case 16: return 44;
@@ -579,7 +706,7 @@ hipError_t fft_configure() {
                        (const void *)fft_z_solve_kernel<8>, (const void *)fft_z_solve_kernel<16>,
                        (const void *)fft_y_inv_kernel<2>,   (const void *)fft_y_inv_kernel<4>,
                        (const void *)fft_y_inv_kernel<8>,   (const void *)fft_y_inv_kernel<16>,
-                       (const void *)fft_x_c2r_kernel};
+                       (const void *)fft_x_c2r_kernel, (const void *)yx_inv256_kernel};
     for (const void *f : k) {
         hipError_t e = raise_dynamic_lds(f);
         if (e != hipSuccess) return e;
@@ -622,6 +749,16 @@ hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ax, hipS
     }
     FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, (spec, g, ax), dim3(nch * g.n[2]), dim3(kPassThreads),
                   pass_lds(g.n[1], 1), s)
+    return hipGetLastError();
+}
+
+bool fft_yx_fused(const Grid &g) { return g.n[0] == kYx && g.n[1] == kYx; }
+
+hipError_t launch_fft_yx_inv(const float2 *spec, float *A, const Grid &g, const FftAxis &ay,
+                             hipStream_t s) {
+    if (!fft_yx_fused(g)) return hipErrorInvalidValue;
+    const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
+    yx_inv256_kernel<<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, g, ay.tw, scale);
     return hipGetLastError();
 }
 

@@ -72,12 +72,22 @@ __device__ __forceinline__ void scan_tile_down(const int32_t *__restrict__ in, i
                                                int n, const int32_t *__restrict__ partial, int tile,
                                                int ntiles, int32_t *totals = nullptr) {
     __shared__ int wsum[C][kScanBlock / 64];
-    __shared__ int boff[C];
+    __shared__ int bsum[C][kScanBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (threadIdx.x < C) {
-        int t = 0;
-        for (int b = 0; b < tile; ++b) t += partial[b * C + threadIdx.x];
-        boff[threadIdx.x] = t;
+    // the totals of the earlier tiles, loaded in parallel and reduced
+    // (a serial loop would wait on one load after another)
+    int pb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) pb[c] = 0;
+    for (int b = threadIdx.x; b < tile; b += blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) pb[c] += partial[b * C + c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) pb[c] += __shfl_xor(pb[c], d, 64);
+        if (lane == 0) bsum[c][wid] = pb[c];
     }
     const int base = tile * kScanTile + threadIdx.x * kScanIpt;
     int v[kScanIpt][C], s[C], incl[C];
@@ -100,7 +110,8 @@ __device__ __forceinline__ void scan_tile_down(const int32_t *__restrict__ in, i
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        int run = boff[c] + incl[c] - s[c];
+        int run = incl[c] - s[c];
+        for (int w = 0; w < kScanBlock / 64; ++w) run += bsum[c][w];
         for (int w = 0; w < wid; ++w) run += wsum[c][w];
 #pragma unroll
         for (int j = 0; j < kScanIpt; ++j) {

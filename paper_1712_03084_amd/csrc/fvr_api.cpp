@@ -69,7 +69,7 @@ struct fvr_ctx {
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
-        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max;
+        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm;
     DevStatus *host_status = nullptr;
     uint32_t timing_mask = 0;  // bit k: time kernel k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -324,8 +324,9 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     { Timed t(c, K_FFT_Z_SOLVE);
       HIP_TRY(c, launch_fft_z_solve(sp, P<uint8_t>(c->zocc), g, p->ax[2], s), "fft_z_solve"); }
     if (fft_yx_fused(g)) {
+        HIP_TRY(c, ensure(c->rowmm, sizeof(float2) * (size_t)g.n[1] * g.n[2]), "alloc row ranges");
         Timed t(c, K_FFT_YX_INV);
-        HIP_TRY(c, launch_fft_yx_inv(sp, field, g, p->ax[1], s), "fft_yx_inv");
+        HIP_TRY(c, launch_fft_yx_inv(sp, field, P<float2>(c->rowmm), g, p->ax[1], s), "fft_yx_inv");
     } else {
         { Timed t(c, K_FFT_Y_INV); HIP_TRY(c, launch_fft_y_inv(sp, g, p->ax[1], s), "fft_y_inv"); }
         { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, g, p->ax[0], s), "fft_x_c2r"); }
@@ -347,7 +348,7 @@ fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float 
 
 // Marching cubes on `field` at the level in c->level_f32; status block must
 // already be reset.  Fills mesh counts; writes arrays only if they fit.
-fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
+fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *rowmm, fvr_mesh *mesh,
                   uint8_t *cases_out, bool check_invalid) {
     const int nb = mc_blocks(g);
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -359,7 +360,7 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, fvr_mesh *mesh,
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     { Timed t(c, K_MC_COUNT);
-      HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_cnt),
+      HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), rowmm, g, P<int32_t>(c->mc_cnt),
                                  P<uint32_t>(c->mc_codes), cases_out, st, s), "mc_count"); }
     { Timed t(c, K_MC_SCAN);
       HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3,
@@ -444,7 +445,7 @@ void fvr_destroy(fvr_ctx *c) {
     for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max};
+                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max, &c->rowmm};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {
@@ -472,7 +473,10 @@ fvr_status fvr_reconstruct(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mesh) {
     HIP_TRY(c, ensure(c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2]), "alloc field");
     if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
     if ((r = run_level(c, f, g, P<float>(c->field))) != FVR_OK) return r;
-    r = run_mc(c, g, P<float>(c->field), mesh, nullptr, true);
+    // the fused inverse pass left each row's range of A: blocks of cells
+    // entirely on one side of the level skip the field
+    r = run_mc(c, g, P<float>(c->field), fft_yx_fused(g) ? P<float2>(c->rowmm) : nullptr, mesh, nullptr,
+               true);
     mesh->level = c->host_status->level;
     return r;
 }
@@ -516,7 +520,7 @@ fvr_status fvr_extract(fvr_ctx *c, const float *field, const int32_t dims[3], co
     { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(P<DevStatus>(c->status), nullptr, 0, c->stream), "prep"); }
     HIP_TRY(c, hipMemcpyAsync(c->level_f32.p, &level, sizeof(float), hipMemcpyHostToDevice, c->stream),
             "level upload");
-    r = run_mc(c, g, field, mesh, cases_out, false);
+    r = run_mc(c, g, field, nullptr, mesh, cases_out, false);
     mesh->level = level;
     mesh->n_rejected = 0;
     return r;

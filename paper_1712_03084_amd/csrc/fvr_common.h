@@ -142,9 +142,10 @@ hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, 
 hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
 // Both inverse passes below in one kernel (one block per z plane; the plane
 // does not go back to HBM between them), for Nx = Ny = 256: fft_yx_fused(g).
+// rowmm[z Ny + y] receives (min, max) of A over the row.
 bool fft_yx_fused(const Grid &g);
-hipError_t launch_fft_yx_inv(const float2 *spec, float *A, const Grid &g, const FftAxis &ay,
-                             hipStream_t s);
+hipError_t launch_fft_yx_inv(const float2 *spec, float *A, float2 *rowmm, const Grid &g,
+                             const FftAxis &ay, hipStream_t s);
 // Inverse real FFT along x of plane 0, scaled by 1/n -> A (Nz, Ny, Nx).
 hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const FftAxis &ax,
                             hipStream_t s);
@@ -160,7 +161,10 @@ int level_blocks(int m);
 // Marching cubes.
 hipError_t mc_upload_table(const uint8_t *counts, const int8_t *edges);
 int mc_blocks(const Grid &g);
-hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
+// rowmm (optional): (min, max) of A per row (z Ny + y); a block whose cells'
+// corner rows lie all above or all at/below the level is settled from it
+// without reading A (no vertices, no active cells).
+hipError_t launch_mc_count(const float *A, const float *level_f32, const float2 *rowmm, const Grid &g,
                            int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,
                            hipStream_t s);
 // The mesh kernels read the totals of the count scan from `st`; they write

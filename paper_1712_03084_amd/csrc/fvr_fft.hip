@@ -300,16 +300,35 @@ struct Pencil {
     }
 
     // Transform the block's columns; `tw` holds w_N^m = exp(-2 pi i m / N),
-    // m < N; `ex` is free for reuse when this returns.
-    template <int DIR>
+    // m < N; `ex` is free for reuse when this returns.  FACTORED (N1 = 16):
+    // w^(t k1) = w^(t (k1 mod 4)) w^(4 t (k1 div 4)) from 6 table entries
+    // instead of 15 (fewer registers held, one more rounding).
+    template <int DIR, bool FACTORED = false>
     __device__ __forceinline__ static void run(float2 (&x)[N1], float2 *ex, const float2 *tw, int c,
                                                int t) {
         Dft<N1>::run(x, DIR);
+        if constexpr (FACTORED) {
+            static_assert(N1 == 16, "factored twiddles for 16 registers");
+            float2 lo[4], hi[4];
 #pragma unroll
-        for (int k1 = 1; k1 < N1; ++k1) {
-            float2 w = tw[t * k1];
-            if (DIR > 0) w.y = -w.y;
-            x[k1] = cmul(x[k1], w);
+            for (int k = 1; k < 4; ++k) {
+                lo[k] = tw[t * k];
+                hi[k] = tw[4 * t * k];
+            }
+#pragma unroll
+            for (int k1 = 1; k1 < N1; ++k1) {
+                const int a = k1 & 3, b = k1 >> 2;
+                float2 w = a == 0 ? hi[b] : b == 0 ? lo[a] : cmul(lo[a], hi[b]);
+                if (DIR > 0) w.y = -w.y;
+                x[k1] = cmul(x[k1], w);
+            }
+        } else {
+#pragma unroll
+            for (int k1 = 1; k1 < N1; ++k1) {
+                float2 w = tw[t * k1];
+                if (DIR > 0) w.y = -w.y;
+                x[k1] = cmul(x[k1], w);
+            }
         }
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) ex[k1 * KS + t * 16 + c] = x[k1];
@@ -558,14 +577,15 @@ static_assert(kYxBuf >= (kYx / 2) * kYxYP, "half plane of y-inverse rows fits");
 static_assert(2 * kYxBuf >= (kYx / 2) * kYxOP, "half plane of output rows fits");
 
 __global__ void __launch_bounds__(kYxThreads)
-yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
-                 const float2 *__restrict__ twg, float scale) {
+yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm,
+                 Grid g, const float2 *__restrict__ twg, float scale) {
     using Pn = PenYx;
     constexpr int N = kYx;
     extern __shared__ __attribute__((aligned(16))) float2 smem[];
     float2 *buf = smem;            // exchange buffers / y-inverse rows / output rows
     float2 *tw = smem + kYxBuf;    // w_256^m (the same table serves x and y)
     float2 *nyq = tw + N;          // the Nyquist column kx = 128
+    float4 *mmr = reinterpret_cast<float4 *>(nyq + N);  // per-wave row ranges [group][wave][c]
     const int grp = threadIdx.x >> 8, lt = threadIdx.x & 255;
     const int c = lt & 15, t = lt >> 4;
     const int z = blockIdx.x, Hp = g.Hp;
@@ -577,15 +597,15 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
     }
 
     // y-inverse of chunks grp and grp + 4 (columns 16 ch + c)
-    // uniform row bases plus one 32-bit lane offset (in_row(t, n1) = t + 16 n1)
+    // uniform row bases plus one 32-bit lane offset (in_row(t, n1) = t + 16 n1);
+    // the first chunk's loads go first, so its transform can start while the
+    // second chunk is still in flight
     float2 a[2][16];
     const unsigned lo = (unsigned)t * Hp + 16u * grp + c;
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) {
-        const float2 *Pr = P + (size_t)(16 * n1) * Hp;
-        a[0][n1] = Pr[lo];
-        a[1][n1] = Pr[lo + 64u];
-    }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) a[h][n1] = P[(size_t)(16 * n1) * Hp + lo + 64u * h];
     __syncthreads();  // twiddles and the Nyquist column
     if (grp == 0 && c == 0) {
         // column 0 carries the Nyquist column in its imaginary part
@@ -596,7 +616,7 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
         }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) Pn::template run<+1>(a[h], ex, tw, c, t);
+    for (int h = 0; h < 2; ++h) Pn::template run<+1, true>(a[h], ex, tw, c, t);
     // finish both transforms before the row writes (interleaving them raises
     // the register peak past 128 and spills)
     __builtin_amdgcn_sched_barrier(0);
@@ -642,16 +662,29 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
                                : make_float2(xa.x + xb.y, xb.x - xa.y);
         }
         __syncthreads();  // the rows are read: buf becomes the exchange buffers
-        Pn::template run<+1>(x, ex, tw, c, t);
+        Pn::template run<+1, true>(x, ex, tw, c, t);
         // every group is past the exchange (run ends with a block barrier)
+        float4 mm = make_float4(x[0].x, x[0].x, x[0].y, x[0].y);  // min, max of rows ra, rb
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int k = Pn::out_row(t, i);
             O[ra * kYxOP + k] = x[i].x * scale;
             O[rb * kYxOP + k] = x[i].y * scale;
+            mm = make_float4(fminf(mm.x, x[i].x), fmaxf(mm.y, x[i].x), fminf(mm.z, x[i].y),
+                             fmaxf(mm.w, x[i].y));
         }
+        // lanes c, c + 16, c + 32, c + 48 of a wave hold the same row pair
+#pragma unroll
+        for (int d = 16; d < 64; d <<= 1) {
+            mm.x = fminf(mm.x, __shfl_xor(mm.x, d, 64));
+            mm.y = fmaxf(mm.y, __shfl_xor(mm.y, d, 64));
+            mm.z = fminf(mm.z, __shfl_xor(mm.z, d, 64));
+            mm.w = fmaxf(mm.w, __shfl_xor(mm.w, d, 64));
+        }
+        if ((lt & 63) < 16) mmr[(grp * 4 + (lt >> 6)) * 16 + c] = mm;
         __syncthreads();
-        constexpr int Q4 = N / 4;  // float4 per real row
+        constexpr int Q4 = N / 4;  // float4 per real row: one wave per row
+        static_assert(Q4 == 64, "a wave stores one row");
         float *dst = A + ((size_t)z * N + 128 * half) * N;
 #pragma unroll
         for (int u = 0; u < 128 * Q4 / kYxThreads; ++u) {
@@ -660,10 +693,23 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
             *reinterpret_cast<float4 *>(dst + (unsigned)(r * N + 4 * q)) =
                 *reinterpret_cast<const float4 *>(O + r * kYxOP + 4 * q);
         }
+        if (threadIdx.x < 128) {
+            // real row r = 2 (16 q + c) + b of this half: its range over the
+            // four waves of group q (A = x scale, scale > 0: the order holds)
+            const int r = threadIdx.x, q = r >> 5, cc = (r & 31) >> 1, b = r & 1;
+            float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float4 e = mmr[(q * 4 + w) * 16 + cc];
+                mn = fminf(mn, b ? e.z : e.x);
+                mx = fmaxf(mx, b ? e.w : e.y);
+            }
+            rowmm[(size_t)z * N + 128 * half + r] = make_float2(mn * scale, mx * scale);
+        }
     }
 }
 
-size_t yx_inv256_lds() { return (size_t)(kYxBuf + 2 * kYx) * sizeof(float2); }
+size_t yx_inv256_lds() { return (size_t)(kYxBuf + 2 * kYx) * sizeof(float2) + 256 * sizeof(float4); }
 
 static int pencil_code(int n) {
     switch (n) {
@@ -754,11 +800,12 @@ hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ax, hipS
 
 bool fft_yx_fused(const Grid &g) { return g.n[0] == kYx && g.n[1] == kYx; }
 
-hipError_t launch_fft_yx_inv(const float2 *spec, float *A, const Grid &g, const FftAxis &ay,
-                             hipStream_t s) {
+hipError_t launch_fft_yx_inv(const float2 *spec, float *A, float2 *rowmm, const Grid &g,
+                             const FftAxis &ay, hipStream_t s) {
     if (!fft_yx_fused(g)) return hipErrorInvalidValue;
     const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
-    yx_inv256_kernel<<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, g, ay.tw, scale);
+    yx_inv256_kernel<<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, rowmm, g, ay.tw,
+                                                                            scale);
     return hipGetLastError();
 }
 

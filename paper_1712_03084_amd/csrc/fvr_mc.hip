@@ -318,15 +318,58 @@ __device__ __forceinline__ int block_sum(int v, int *red) {
 }
 
 __global__ void __launch_bounds__(kMcThreads)
-mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
-                int32_t *__restrict__ blk_counts, uint32_t *__restrict__ codes,
-                uint8_t *__restrict__ cases_out, DevStatus *st) {
+mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32,
+                const float2 *__restrict__ rowmm, Grid g, int32_t *__restrict__ blk_counts,
+                uint32_t *__restrict__ codes, uint8_t *__restrict__ cases_out, DevStatus *st) {
     __shared__ int red[4];
     __shared__ uint8_t s_ntri[256];
-    mc_count_table(s_ntri);
-    uint32_t code4 = 0;  // the 4 point codes, byte i for point l0 + i
+    __shared__ float smm[2][4];
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
+    if (rowmm) {
+        // Rows r0 .. r1 hold the block's points; their cells' corners lie in
+        // rows r0 .. r1 + 1 and the same rows of the next plane (r + Ny).  If A
+        // over those rows is all above L or all at or below it, no edge
+        // crosses and no cell is active.
+        const unsigned nrows = (unsigned)g.n[1] * g.n[2];
+        const unsigned b0 = blockIdx.x * (unsigned)kMcPerBlock;
+        const unsigned r0 = b0 / (unsigned)g.n[0];
+        const unsigned r1 = (unsigned)((min((size_t)b0 + kMcPerBlock, n) - 1) / (unsigned)g.n[0]);
+        const unsigned span = r1 - r0 + 2;
+        float mn = INFINITY, mx = -INFINITY;
+        for (unsigned i = threadIdx.x; i < 2 * span; i += blockDim.x) {
+            const unsigned r = i < span ? r0 + i : r0 + (i - span) + (unsigned)g.n[1];
+            if (r < nrows) {
+                const float2 v = rowmm[r];
+                mn = fminf(mn, v.x);
+                mx = fmaxf(mx, v.y);
+            }
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            mn = fminf(mn, __shfl_xor(mn, d, 64));
+            mx = fmaxf(mx, __shfl_xor(mx, d, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            smm[0][threadIdx.x >> 6] = mn;
+            smm[1][threadIdx.x >> 6] = mx;
+        }
+        __syncthreads();
+        mn = fminf(fminf(smm[0][0], smm[0][1]), fminf(smm[0][2], smm[0][3]));
+        mx = fmaxf(fmaxf(smm[1][0], smm[1][1]), fmaxf(smm[1][2], smm[1][3]));
+        if (mn > L || mx <= L) {
+            if (threadIdx.x == 0) {
+                blk_counts[3 * blockIdx.x + 0] = 0;
+                blk_counts[3 * blockIdx.x + 1] = 0;
+                blk_counts[3 * blockIdx.x + 2] = 0;
+                // every row has points on the x borders: all of them inside
+                if (mn > L) atomicOr(&st->flags, kFlagOpen);
+            }
+            return;
+        }
+    }
+    mc_count_table(s_ntri);
+    uint32_t code4 = 0;  // the 4 point codes, byte i for point l0 + i
     const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
     const size_t l0 = l0u;
     int nv = 0, nt = 0, na = 0;
@@ -569,10 +612,10 @@ mc_triangles_kernel(const int4 *__restrict__ cells, const int32_t *__restrict__ 
     }
 }
 
-hipError_t launch_mc_count(const float *A, const float *level_f32, const Grid &g,
+hipError_t launch_mc_count(const float *A, const float *level_f32, const float2 *rowmm, const Grid &g,
                            int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,
                            hipStream_t s) {
-    mc_count_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, g, blk_counts,
+    mc_count_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, rowmm, g, blk_counts,
                                                                     codes, cases_out, st);
     return hipGetLastError();
 }

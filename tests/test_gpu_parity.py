@@ -217,6 +217,26 @@ def test_full_size_human_proxy_256(ctx):
     assert abs(mesh.vertices.shape[0] - len(r["verts"])) <= 0.001 * len(r["verts"])
     ok, _ = _closed(mesh.triangles.cpu().numpy())
     assert ok
+    # reconstruct settles most marching-cubes blocks from the row ranges of A
+    # without reading it; extract classifies every point of the same field
+    full = ctx.extract(A, f.bbox, L)
+    assert torch.equal(full.vertices, mesh.vertices) and torch.equal(full.triangles, mesh.triangles)
+    assert full.open_surface == mesh.open_surface
+
+
+def test_row_range_skip_on_an_open_surface_256(ctx):
+    """A sphere cut by a 256^3 box: whole blocks of cells lie inside (all above
+    the level), are settled from the row ranges and must raise the open-surface
+    flag; the mesh must equal the full classification of the same field."""
+    f = synth.sphere_frame(seed=4, m=200_000, grid=256, half_extent=0.7)
+    print("[skip] sphere r=0.8 in [-0.7, 0.7]^3, 256^3", flush=True)
+    dev = _frame_dev(f)
+    A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
+    mesh = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox)
+    full = ctx.extract(A, f.bbox, L)
+    assert mesh.open_surface and full.open_surface
+    assert mesh.vertices.shape[0] > 0
+    assert torch.equal(full.vertices, mesh.vertices) and torch.equal(full.triangles, mesh.triangles)
 
 
 def test_empty_and_all_rejected(ctx):

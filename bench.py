@@ -55,6 +55,7 @@ def kernel_alg_bytes(dims, m, nv, nt):
         "fft_x_c2r": S + F,
         "fft_yx_inv": S + F,
         "level": 12 * m,
+        "mc_classify": 0,
         "mc_count": F,
         "mc_generate": F + 12 * nv,
         "mc_triangles": 12 * nt,
@@ -68,7 +69,7 @@ KERNEL_SOURCES = {
     "prep": "fvr_mc.hip", "bin_count": "fvr_splat.hip", "tile_list": "fvr_splat.hip",
     "tile_order": "fvr_splat.hip", "bin_scatter": "fvr_splat.hip", "splat_fft_x": "fvr_splat.hip",
     "fft_y_fwd": "fvr_fft.hip", "fft_z_solve": "fvr_fft.hip", "fft_y_inv": "fvr_fft.hip",
-    "fft_x_c2r": "fvr_fft.hip", "fft_yx_inv": "fvr_fft.hip", "level": "fvr_mc.hip", "mc_count": "fvr_mc.hip",
+    "fft_x_c2r": "fvr_fft.hip", "fft_yx_inv": "fvr_fft.hip", "level": "fvr_mc.hip", "mc_classify": "fvr_mc.hip", "mc_count": "fvr_mc.hip",
     "mc_scan": "fvr_mc.hip", "mc_generate": "fvr_mc.hip", "mc_triangles": "fvr_mc.hip",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_proxy256.txt")

@@ -26,12 +26,12 @@ namespace {
 
 enum KernelId {
     K_PREP, K_BIN_COUNT, K_TILE_LIST, K_BIN_SCATTER, K_SPLAT_FFT_X, K_FFT_Y_FWD,
-    K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_FFT_YX_INV, K_LEVEL, K_MC_COUNT, K_MC_SCAN,
+    K_FFT_Z_SOLVE, K_FFT_Y_INV, K_FFT_X_C2R, K_FFT_YX_INV, K_LEVEL, K_MC_CLASSIFY, K_MC_COUNT, K_MC_SCAN,
     K_MC_GENERATE, K_MC_TRIANGLES, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {
     "prep", "bin_count", "tile_list", "bin_scatter", "splat_fft_x", "fft_y_fwd",
-    "fft_z_solve", "fft_y_inv", "fft_x_c2r", "fft_yx_inv", "level", "mc_count", "mc_scan",
+    "fft_z_solve", "fft_y_inv", "fft_x_c2r", "fft_yx_inv", "level", "mc_classify", "mc_count", "mc_scan",
     "mc_generate", "mc_triangles"};
 
 thread_local std::string g_error;
@@ -69,7 +69,7 @@ struct fvr_ctx {
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
-        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm;
+        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm, mc_list;
     DevStatus *host_status = nullptr;
     uint32_t timing_mask = 0;  // bit k: time kernel k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -359,8 +359,16 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
     HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_partials(nb)), "alloc scan scratch");
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
+    int32_t *list = nullptr;
+    if (rowmm) {
+        HIP_TRY(c, ensure(c->mc_list, sizeof(int32_t) * (size_t)nb), "alloc mc block list");
+        list = P<int32_t>(c->mc_list);
+        Timed t(c, K_MC_CLASSIFY);
+        HIP_TRY(c, launch_mc_classify(P<float>(c->level_f32), rowmm, g, P<int32_t>(c->mc_cnt), list, st, s),
+                "mc_classify");
+    }
     { Timed t(c, K_MC_COUNT);
-      HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), rowmm, g, P<int32_t>(c->mc_cnt),
+      HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
                                  P<uint32_t>(c->mc_codes), cases_out, st, s), "mc_count"); }
     { Timed t(c, K_MC_SCAN);
       HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3,
@@ -376,7 +384,7 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
     caps.check_invalid = check_invalid ? 1 : 0;
     HIP_TRY(c, ensure(c->cells, sizeof(int4) * (size_t)std::max(1LL, caps.cells)), "alloc active cells");
     { Timed t(c, K_MC_GENERATE);
-      HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), g, P<int32_t>(c->mc_cnt),
+      HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
                                     P<int32_t>(c->mc_off), P<uint32_t>(c->mc_codes), mesh->vertices,
                                     P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, s),
               "mc_generate"); }
@@ -445,7 +453,7 @@ void fvr_destroy(fvr_ctx *c) {
     for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max, &c->rowmm};
+                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max, &c->rowmm, &c->mc_list};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {

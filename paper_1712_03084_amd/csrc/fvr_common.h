@@ -69,6 +69,7 @@ struct DevStatus {
     uint32_t wnmax_bits;  // float bits of max W |N_c| over accepted points
     int32_t tile_ticket;  // next entry of the busy-tile list to claim (persistent splat blocks)
     int32_t n_busy;       // splat tiles that some point reaches
+    int32_t mc_active;    // marching-cubes blocks left for the classification (mc_classify)
 };
 constexpr uint32_t kFlagInvalid = 1u;
 constexpr uint32_t kFlagOpen = 2u;
@@ -161,10 +162,13 @@ int level_blocks(int m);
 // Marching cubes.
 hipError_t mc_upload_table(const uint8_t *counts, const int8_t *edges);
 int mc_blocks(const Grid &g);
-// rowmm (optional): (min, max) of A per row (z Ny + y); a block whose cells'
-// corner rows lie all above or all at/below the level is settled from it
-// without reading A (no vertices, no active cells).
-hipError_t launch_mc_count(const float *A, const float *level_f32, const float2 *rowmm, const Grid &g,
+// From rowmm, the (min, max) of A per row (z Ny + y): blocks whose cells'
+// corner rows lie all above or all at/below the level are settled without
+// reading A (zero totals); the others go to list (st->mc_active entries).
+hipError_t launch_mc_classify(const float *level_f32, const float2 *rowmm, const Grid &g,
+                              int32_t *blk_counts, int32_t *list, DevStatus *st, hipStream_t s);
+// list: the blocks mc_classify left (null: every block).
+hipError_t launch_mc_count(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                            int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,
                            hipStream_t s);
 // The mesh kernels read the totals of the count scan from `st`; they write
@@ -174,7 +178,7 @@ struct MeshCaps {
     long long vertices, triangles, cells;
     int check_invalid;
 };
-hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
+hipError_t launch_mc_generate(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                               const int32_t *blk_counts, const int32_t *blk_offsets,
                               const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
                               const DevStatus *st, MeshCaps caps, hipStream_t s);

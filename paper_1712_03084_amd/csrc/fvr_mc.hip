@@ -67,6 +67,7 @@ __global__ void prep_kernel(DevStatus *st, int32_t *bins, int nbins) {
         st->wnmax_bits = 0;
         st->tile_ticket = 0;
         st->n_busy = 0;
+        st->mc_active = 0;
     }
     if (bins && i < nbins) bins[i] = 0;
 }
@@ -317,27 +318,29 @@ __device__ __forceinline__ int block_sum(int v, int *red) {
     return t;
 }
 
-__global__ void __launch_bounds__(kMcThreads)
-mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32,
-                const float2 *__restrict__ rowmm, Grid g, int32_t *__restrict__ blk_counts,
-                uint32_t *__restrict__ codes, uint8_t *__restrict__ cases_out, DevStatus *st) {
-    __shared__ int red[4];
-    __shared__ uint8_t s_ntri[256];
-    __shared__ float smm[2][4];
+// Blocks of the marching cubes whose cells' corner rows lie all above the
+// level or all at or below it have no crossing edge and no active cell: one
+// thread per block settles them from the per-row ranges of A (zero totals,
+// the open-surface flag when above: every row has points on the x borders)
+// and appends the others to `list` (st->mc_active entries, in no particular
+// order).  The rows r0 .. r1 of a block's points and their cells' corners
+// lie in rows r0 .. r1 + 1 and the same rows of the next plane (r + Ny).
+__global__ void __launch_bounds__(256)
+mc_classify_kernel(const float *__restrict__ level_f32, const float2 *__restrict__ rowmm, Grid g,
+                   int nb, int32_t *__restrict__ blk_counts, int32_t *__restrict__ list, DevStatus *st) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const float L = *level_f32;
-    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
-    if (rowmm) {
-        // Rows r0 .. r1 hold the block's points; their cells' corners lie in
-        // rows r0 .. r1 + 1 and the same rows of the next plane (r + Ny).  If A
-        // over those rows is all above L or all at or below it, no edge
-        // crosses and no cell is active.
+    bool active = false, inside = false;
+    if (b < nb) {
+        const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
         const unsigned nrows = (unsigned)g.n[1] * g.n[2];
-        const unsigned b0 = blockIdx.x * (unsigned)kMcPerBlock;
+        const unsigned b0 = (unsigned)b * (unsigned)kMcPerBlock;
         const unsigned r0 = b0 / (unsigned)g.n[0];
         const unsigned r1 = (unsigned)((min((size_t)b0 + kMcPerBlock, n) - 1) / (unsigned)g.n[0]);
         const unsigned span = r1 - r0 + 2;
         float mn = INFINITY, mx = -INFINITY;
-        for (unsigned i = threadIdx.x; i < 2 * span; i += blockDim.x) {
+        for (unsigned i = 0; i < 2 * span; ++i) {
             const unsigned r = i < span ? r0 + i : r0 + (i - span) + (unsigned)g.n[1];
             if (r < nrows) {
                 const float2 v = rowmm[r];
@@ -345,32 +348,40 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
                 mx = fmaxf(mx, v.y);
             }
         }
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) {
-            mn = fminf(mn, __shfl_xor(mn, d, 64));
-            mx = fmaxf(mx, __shfl_xor(mx, d, 64));
-        }
-        if ((threadIdx.x & 63) == 0) {
-            smm[0][threadIdx.x >> 6] = mn;
-            smm[1][threadIdx.x >> 6] = mx;
-        }
-        __syncthreads();
-        mn = fminf(fminf(smm[0][0], smm[0][1]), fminf(smm[0][2], smm[0][3]));
-        mx = fmaxf(fmaxf(smm[1][0], smm[1][1]), fmaxf(smm[1][2], smm[1][3]));
         if (mn > L || mx <= L) {
-            if (threadIdx.x == 0) {
-                blk_counts[3 * blockIdx.x + 0] = 0;
-                blk_counts[3 * blockIdx.x + 1] = 0;
-                blk_counts[3 * blockIdx.x + 2] = 0;
-                // every row has points on the x borders: all of them inside
-                if (mn > L) atomicOr(&st->flags, kFlagOpen);
-            }
-            return;
+            blk_counts[3 * b + 0] = 0;
+            blk_counts[3 * b + 1] = 0;
+            blk_counts[3 * b + 2] = 0;
+            inside = mn > L;
+        } else {
+            active = true;
         }
     }
+    if (__ballot(inside) && lane == 0) atomicOr(&st->flags, kFlagOpen);
+    const unsigned long long m = __ballot(active);
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(&st->mc_active, __popcll(m));
+    base = __shfl(base, 0, 64);
+    if (active) list[base + __popcll(m & ((1ull << lane) - 1ull))] = b;
+}
+
+// Classification of the blocks in `list` (st->mc_active of them; persistent
+// blocks stride over the list), or of block blockIdx.x when list is null.
+__global__ void __launch_bounds__(kMcThreads)
+mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32,
+                const int32_t *__restrict__ list, Grid g, int32_t *__restrict__ blk_counts,
+                uint32_t *__restrict__ codes, uint8_t *__restrict__ cases_out, DevStatus *st) {
+    __shared__ int red[4];
+    __shared__ uint8_t s_ntri[256];
+    const float L = *level_f32;
+    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
+    const int nblk = list ? st->mc_active : (int)gridDim.x;
+    if ((int)blockIdx.x >= nblk) return;
     mc_count_table(s_ntri);
+    for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
+    const unsigned blk = list ? (unsigned)list[it] : (unsigned)it;
     uint32_t code4 = 0;  // the 4 point codes, byte i for point l0 + i
-    const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
+    const unsigned l0u = blk * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
     const size_t l0 = l0u;
     int nv = 0, nt = 0, na = 0;
     bool open = false;
@@ -436,12 +447,13 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
     nt = block_sum(nt, red);
     na = block_sum(na, red);
     if (threadIdx.x == 0) {
-        blk_counts[3 * blockIdx.x + 0] = nv;
-        blk_counts[3 * blockIdx.x + 1] = nt;
-        blk_counts[3 * blockIdx.x + 2] = na;
+        blk_counts[3 * blk + 0] = nv;
+        blk_counts[3 * blk + 1] = nt;
+        blk_counts[3 * blk + 2] = na;
     }
     // codes only where the surface passes: mc_generate skips the other blocks
     if (nv > 0 || na > 0) codes[l0 / 4] = code4;
+    }
 }
 
 // Exclusive block scan of three counters (256 threads).
@@ -475,23 +487,31 @@ __device__ __forceinline__ bool mesh_fits(const DevStatus *st, const MeshCaps &c
 
 __global__ void __launch_bounds__(kMcThreads)
 mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
-                   const int32_t *__restrict__ blk_counts, const int32_t *__restrict__ blk_off,
-                   const uint32_t *__restrict__ codes, float *__restrict__ verts,
-                   int32_t *__restrict__ vidx, int4 *__restrict__ cells, const DevStatus *st,
-                   MeshCaps caps) {
+                   const int32_t *__restrict__ list, const int32_t *__restrict__ blk_counts,
+                   const int32_t *__restrict__ blk_off, const uint32_t *__restrict__ codes,
+                   float *__restrict__ verts, int32_t *__restrict__ vidx, int4 *__restrict__ cells,
+                   const DevStatus *st, MeshCaps caps) {
     __shared__ int red[12];
     __shared__ uint8_t s_ntri[256];
     if (!mesh_fits(st, caps)) return;
+    // the blocks in `list` (persistent blocks stride over it), or block
+    // blockIdx.x when list is null
+    const int nblk = list ? st->mc_active : (int)gridDim.x;
+    bool have_table = false;
+    for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
+    const unsigned blk = list ? (unsigned)list[it] : (unsigned)it;
     // a block without vertices and active cells has nothing to write (and
     // mc_count stored no codes for it)
-    if (blk_counts[3 * blockIdx.x] == 0 && blk_counts[3 * blockIdx.x + 2] == 0) return;
+    if (blk_counts[3 * blk] == 0 && blk_counts[3 * blk + 2] == 0) continue;
     // the block's global offsets, loaded before anything waits on the codes
-    int vbase = blk_off[3 * blockIdx.x + 0], tbase = blk_off[3 * blockIdx.x + 1],
-        abase = blk_off[3 * blockIdx.x + 2];
-    mc_count_table(s_ntri);
+    int vbase = blk_off[3 * blk + 0], tbase = blk_off[3 * blk + 1], abase = blk_off[3 * blk + 2];
+    if (!have_table) {
+        mc_count_table(s_ntri);
+        have_table = true;
+    }
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
-    const unsigned l0u = blockIdx.x * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
+    const unsigned l0u = blk * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
     const size_t l0 = l0u;
     int eb[kMcPpt], cs[kMcPpt];
     int cnt[3] = {0, 0, 0};
@@ -583,6 +603,7 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
         }
     }
 }
+}
 
 __global__ void __launch_bounds__(256)
 mc_triangles_kernel(const int4 *__restrict__ cells, const int32_t *__restrict__ vidx, Grid g,
@@ -612,20 +633,36 @@ mc_triangles_kernel(const int4 *__restrict__ cells, const int32_t *__restrict__ 
     }
 }
 
-hipError_t launch_mc_count(const float *A, const float *level_f32, const float2 *rowmm, const Grid &g,
-                           int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,
-                           hipStream_t s) {
-    mc_count_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(A, level_f32, rowmm, g, blk_counts,
-                                                                    codes, cases_out, st);
+// Persistent grid of the list-driven marching-cubes kernels: the blocks
+// the surface passes are a few percent of all (a 256^3 grid has 16k).
+constexpr int kMcPersist = 2048;
+
+hipError_t launch_mc_classify(const float *level_f32, const float2 *rowmm, const Grid &g,
+                              int32_t *blk_counts, int32_t *list, DevStatus *st, hipStream_t s) {
+    const int nb = mc_blocks(g);
+    mc_classify_kernel<<<dim3((nb + 255) / 256), dim3(256), 0, s>>>(level_f32, rowmm, g, nb, blk_counts,
+                                                                    list, st);
     return hipGetLastError();
 }
 
-hipError_t launch_mc_generate(const float *A, const float *level_f32, const Grid &g,
+static int mc_grid(const Grid &g, const int32_t *list) {
+    return list ? std::min(mc_blocks(g), kMcPersist) : mc_blocks(g);
+}
+
+hipError_t launch_mc_count(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
+                           int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,
+                           hipStream_t s) {
+    mc_count_kernel<<<dim3(mc_grid(g, list)), dim3(kMcThreads), 0, s>>>(A, level_f32, list, g, blk_counts,
+                                                                        codes, cases_out, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_generate(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                               const int32_t *blk_counts, const int32_t *blk_offsets,
                               const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
                               const DevStatus *st, MeshCaps caps, hipStream_t s) {
-    mc_generate_kernel<<<dim3(mc_blocks(g)), dim3(kMcThreads), 0, s>>>(
-        A, level_f32, g, blk_counts, blk_offsets, codes, verts, vidx, cells, st, caps);
+    mc_generate_kernel<<<dim3(mc_grid(g, list)), dim3(kMcThreads), 0, s>>>(
+        A, level_f32, g, list, blk_counts, blk_offsets, codes, verts, vidx, cells, st, caps);
     return hipGetLastError();
 }
 

@@ -183,12 +183,27 @@ level_final_kernel(const double *__restrict__ psum, const int32_t *__restrict__ 
     __shared__ int scnt[kLevelThreads];
     double sum = 0.0, comp = 0.0;
     int cnt = 0;
-    for (int i = threadIdx.x; i < nb; i += kLevelThreads) {
-        const double v = psum[i];
-        const double s = sum + v;
-        comp += fabs(sum) >= fabs(v) ? (sum - s) + v : (v - s) + sum;
-        sum = s;
-        cnt += pcnt[i];
+    // partials kB at a time: loads from clamped indices go out together, the
+    // ones past the end count as zero; the summation order is fixed
+    constexpr int kB = 4;
+    for (int b0 = 0; b0 < nb; b0 += kB * kLevelThreads) {
+        double pv[kB];
+        int pc[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int i = min(b0 + u * kLevelThreads + (int)threadIdx.x, nb - 1);
+            pv[u] = psum[i];
+            pc[u] = pcnt[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            if (b0 + u * kLevelThreads + (int)threadIdx.x >= nb) break;
+            const double v = pv[u];
+            const double s = sum + v;
+            comp += fabs(sum) >= fabs(v) ? (sum - s) + v : (v - s) + sum;
+            sum = s;
+            cnt += pc[u];
+        }
     }
     ssum[threadIdx.x] = sum + comp;
     scnt[threadIdx.x] = cnt;

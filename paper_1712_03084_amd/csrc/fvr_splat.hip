@@ -598,12 +598,20 @@ tile_order_kernel(const int32_t *__restrict__ bin_count, int32_t *__restrict__ b
     }
     __shared__ int hist[kTileClasses], cursor[kTileClasses];
     __shared__ unsigned wmax[kScanBlock / 64], wnmax[kScanBlock / 64];
-    // the frame's largest W and W |N_c| (fixed-point units of the splat)
+    // the frame's largest W and W |N_c| (fixed-point units of the splat).
+    // Loads go out kBatch at a time with clamped indices (a duplicate does not
+    // change a maximum), so each batch costs one memory round trip.
+    constexpr int kBatch = 8;
     unsigned mw = 0, mn = 0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-        const uint2 v = blk_max[i];
-        mw = max(mw, v.x);
-        mn = max(mn, v.y);
+    for (int b0 = 0; b0 < nblk; b0 += kBatch * kScanBlock) {
+        uint2 v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) v[u] = blk_max[min(b0 + u * kScanBlock + (int)threadIdx.x, nblk - 1)];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            mw = max(mw, v[u].x);
+            mn = max(mn, v[u].y);
+        }
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
@@ -617,7 +625,14 @@ tile_order_kernel(const int32_t *__restrict__ bin_count, int32_t *__restrict__ b
     const int n = st->n_busy;
     if (threadIdx.x < kTileClasses) hist[threadIdx.x] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&hist[tile_class(pend[i].y)], 1);
+    for (int b0 = 0; b0 < n; b0 += kBatch * kScanBlock) {
+        int2 e[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) e[u] = pend[min(b0 + u * kScanBlock + (int)threadIdx.x, n - 1)];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (b0 + u * kScanBlock + (int)threadIdx.x < n) atomicAdd(&hist[tile_class(e[u].y)], 1);
+    }
     __syncthreads();
     if (threadIdx.x < kTileClasses) {
         // classes in decreasing order: the start of class c is the count of classes above it
@@ -627,9 +642,13 @@ tile_order_kernel(const int32_t *__restrict__ bin_count, int32_t *__restrict__ b
         cursor[c] = above;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int2 e = pend[i];
-        list[atomicAdd(&cursor[tile_class(e.y)], 1)] = e.x;
+    for (int b0 = 0; b0 < n; b0 += kBatch * kScanBlock) {
+        int2 e[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) e[u] = pend[min(b0 + u * kScanBlock + (int)threadIdx.x, n - 1)];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (b0 + u * kScanBlock + (int)threadIdx.x < n) list[atomicAdd(&cursor[tile_class(e[u].y)], 1)] = e[u].x;
     }
     if (threadIdx.x == 0) {
         unsigned a = 0, b = 0;

@@ -136,17 +136,18 @@ def _torch():
     return torch
 
 
-def _dev_f32(t, name, device, shape_tail):
+def _dev_f32(t, name, device, ncols):
+    """t as a contiguous float32 (n, ncols) tensor on cuda:device (checked)."""
     torch = _torch()
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if t.device.type != "cuda" or t.device.index != device:
+    if not t.is_cuda or t.get_device() != device:
         raise ValueError(f"{name} must live on cuda:{device}")
     if t.dtype != torch.float32:
         raise TypeError(f"{name} must be float32")
-    if tuple(t.shape[1:]) != shape_tail:
+    if t.dim() != 2 or t.shape[1] != ncols:
         raise ValueError(f"{name} has shape {tuple(t.shape)}")
-    return t.contiguous()
+    return t if t.is_contiguous() else t.contiguous()
 
 
 class Context:
@@ -159,6 +160,7 @@ class Context:
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.fvr_create(self.device, None, ctypes.byref(h)))
         self.handle = h
+        self._cur_stream = None  # the stream last passed to fvr_set_stream (None: the null stream)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -173,17 +175,21 @@ class Context:
 
     # -- helpers ------------------------------------------------------------
     def _stream(self):
+        """Enqueue on torch's current stream of the device (the library call
+        only when that stream changed)."""
         torch = _torch()
         s = torch.cuda.current_stream(self.device).cuda_stream
-        _check(self.lib, self.lib.fvr_set_stream(self.handle, ctypes.c_void_p(s)), self.handle)
+        if s != self._cur_stream:
+            _check(self.lib, self.lib.fvr_set_stream(self.handle, ctypes.c_void_p(s)), self.handle)
+            self._cur_stream = s
 
     def _frame(self, points, normals, weights, grid_dim, bbox):
-        points = _dev_f32(points, "points", self.device, (3,))
-        normals = _dev_f32(normals, "normals", self.device, (3,))
+        points = _dev_f32(points, "points", self.device, 3)
+        normals = _dev_f32(normals, "normals", self.device, 3)
         if normals.shape[0] != points.shape[0]:
             raise ValueError("points and normals differ in length")
         if weights is not None:
-            weights = _dev_f32(weights.reshape(-1, 1), "weights", self.device, (1,))
+            weights = _dev_f32(weights.reshape(-1, 1), "weights", self.device, 1)
             if weights.shape[0] != points.shape[0]:
                 raise ValueError("weights length differs from points")
         f = _Frame()

@@ -239,6 +239,29 @@ def test_row_range_skip_on_an_open_surface_256(ctx):
     assert torch.equal(full.vertices, mesh.vertices) and torch.equal(full.triangles, mesh.triangles)
 
 
+def test_fused_inverse_on_a_256x256x96_grid(ctx):
+    """N_x = N_y = 256 takes the fused inverse y/x pass and the marching-cubes
+    block list whatever N_z is: indicator against the oracle, mesh against the
+    full classification of the same field."""
+    f = _random_frame(21, 60_000, (256, 256, 96), (-1.0, -1.0, -0.375, 1.0, 1.0, 0.375))
+    print("[fused] random frame 256x256x96", flush=True)
+    dev = _frame_dev(f)
+    A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
+    Vo, _, _, _ = oracle.splat(f.points, f.normals, f.weights, f.dims, f.bbox)
+    Ao = oracle.indicator(Vo, f.dims, f.bbox)
+    Lo, _ = oracle.level(Ao, f.points, f.dims, f.bbox)
+    rng_ = Ao.max() - Ao.min()
+    err = np.abs(A.cpu().numpy() - Ao).max()
+    print(f"  range={rng_:.4g} rel err={err / rng_:.3g} L={L:.8g} Lo={Lo:.8g}")
+    assert err <= 1e-4 * rng_
+    assert abs(L - Lo) <= 1e-4 * rng_
+    mesh = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox)
+    full = ctx.extract(A, f.bbox, L)
+    assert mesh.vertices.shape[0] > 0
+    assert torch.equal(full.vertices, mesh.vertices) and torch.equal(full.triangles, mesh.triangles)
+    assert full.open_surface == mesh.open_surface
+
+
 def test_empty_and_all_rejected(ctx):
     z = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
     mesh = ctx.reconstruct(z, z, None, grid_dim=(16, 16, 16), bbox=(-1, -1, -1, 1, 1, 1))

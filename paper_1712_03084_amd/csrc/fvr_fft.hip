@@ -436,11 +436,16 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
     const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
     const bool col = k0 + c < H;
     float2 *p = spec + ((size_t)ky * Hp + k0);
+    // the lane's plane flags first (one LDS round trip), then the loads
+    unsigned km = 0;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) km |= (unsigned)(keep[Pn::in_row(t, n1)] != 0) << n1;
+    if (!col) km = 0;
     float2 a[N1], b[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
         const int r = Pn::in_row(t, n1);
-        const bool ld = col && keep[r];
+        const bool ld = (km >> n1) & 1u;
         const unsigned o = (unsigned)r * zs + (unsigned)c;
         a[n1] = ld ? p[o] : make_float2(0.f, 0.f);
         b[n1] = ld ? p[plane2 + o] : make_float2(0.f, 0.f);

@@ -75,12 +75,20 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
             }
         }
     }
-    // Wave-aggregated histogram: points arrive in capture (scanline) order, so
-    // a wave holds few distinct bins.  The wave first splits into groups of
-    // equal bin (no memory traffic), then every group's first lane adds the
-    // group size with one atomic - all groups in the same instruction, a single
-    // round trip - and each lane's rank is the group's base plus its position
-    // within the group.
+    // Block-aggregated histogram: points arrive in capture (scanline) order, so
+    // a block holds few distinct bins.  Each wave first splits into groups of
+    // equal bin (no memory traffic); the groups' first lanes then merge the
+    // block's groups of each bin in an LDS hash table (each gets its offset
+    // within the block's group), one thread per distinct bin adds the block's
+    // count with a single global atomic - all in the same round trip - and each
+    // lane's rank is that base plus its offsets.
+    constexpr int kHash = 512;  // power of two, twice the block: probing always ends
+    __shared__ int hkey[kHash], hcnt[kHash], hbase[kHash];
+    for (int t = threadIdx.x; t < kHash; t += blockDim.x) {
+        hkey[t] = -1;
+        hcnt[t] = 0;
+    }
+    __syncthreads();
     unsigned long long todo = __ballot(k >= 0);
     int leader = lane, pos = 0, size = 0;
     while (todo) {
@@ -94,8 +102,25 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
         if (lane == l) size = __popcll(grp);
         todo &= ~grp;
     }
+    int slot = 0, woff = 0;
+    if (k >= 0 && leader == lane) {
+        unsigned h = ((unsigned)k * 2654435761u) >> 23;  // 9 bits
+        for (;;) {
+            const int prev = atomicCAS(&hkey[h], -1, k);
+            if (prev == -1 || prev == k) break;
+            h = (h + 1) & (kHash - 1);
+        }
+        slot = (int)h;
+        woff = atomicAdd(&hcnt[slot], size);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kHash; t += blockDim.x) {
+        const int kk = hkey[t];
+        if (kk >= 0) hbase[t] = atomicAdd(&bin_count[kk], hcnt[t]);
+    }
+    __syncthreads();
     int base = 0;
-    if (k >= 0 && leader == lane) base = atomicAdd(&bin_count[k], size);
+    if (k >= 0 && leader == lane) base = hbase[slot] + woff;
     base = __shfl(base, leader, 64);
     const int myrank = base + pos;
     if (i < m) {

@@ -44,7 +44,11 @@ __device__ __forceinline__ bool finite3(float a, float b, float c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-__global__ void __launch_bounds__(256)
+// 1024 points per block: the block's groups of equal bin share one atomic
+// (61k atomics for the 700k-point proxy frame, 126k with 256-point blocks)
+constexpr int kBinThreads = 1024;
+
+__global__ void __launch_bounds__(kBinThreads)
 bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
                  const float *__restrict__ w, int m, Grid g, int32_t *__restrict__ bin_count,
                  int32_t *__restrict__ key, int32_t *__restrict__ rank, uint2 *__restrict__ blk_max,
@@ -82,7 +86,7 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
     // within the block's group), one thread per distinct bin adds the block's
     // count with a single global atomic - all in the same round trip - and each
     // lane's rank is that base plus its offsets.
-    constexpr int kHash = 512;  // power of two, twice the block: probing always ends
+    constexpr int kHash = 2 * kBinThreads;  // power of two, twice the block: probing always ends
     __shared__ int hkey[kHash], hcnt[kHash], hbase[kHash];
     for (int t = threadIdx.x; t < kHash; t += blockDim.x) {
         hkey[t] = -1;
@@ -104,7 +108,8 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
     }
     int slot = 0, woff = 0;
     if (k >= 0 && leader == lane) {
-        unsigned h = ((unsigned)k * 2654435761u) >> 23;  // 9 bits
+        unsigned h = ((unsigned)k * 2654435761u) >> (32 - 11);  // log2(kHash) bits
+        static_assert(kHash == 1 << 11, "hash width");
         for (;;) {
             const int prev = atomicCAS(&hkey[h], -1, k);
             if (prev == -1 || prev == k) break;
@@ -133,7 +138,7 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
         wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
         wnmax = fmaxf(wnmax, __shfl_xor(wnmax, d, 64));
     }
-    __shared__ float red[2][4];
+    __shared__ float red[2][kBinThreads / 64];
     const int wid = threadIdx.x >> 6;
     if (lane == 0) {
         if (brej) atomicAdd(&st->rejected, (uint32_t)__popcll(brej));
@@ -146,8 +151,11 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
         // the block's maxima; tile_order reduces them (atomics of every block on
         // one status word would serialise in one L2 channel); non-negative
         // floats order like their bit patterns
-        const float bw = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-        const float bn = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+        float bw = 0.0f, bn = 0.0f;
+        for (int w = 0; w < kBinThreads / 64; ++w) {
+            bw = fmaxf(bw, red[0][w]);
+            bn = fmaxf(bn, red[1][w]);
+        }
         blk_max[blockIdx.x] = make_uint2(__float_as_uint(bw), __float_as_uint(bn));
     }
 }
@@ -538,13 +546,13 @@ size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
            g.n[0] * sizeof(float2);
 }
 
-int bin_count_blocks(int m) { return m > 0 ? (m + 255) / 256 : 0; }
+int bin_count_blocks(int m) { return m > 0 ? (m + kBinThreads - 1) / kBinThreads : 0; }
 
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
                             const Grid &g, int32_t *bin_count, int32_t *key, int32_t *rank,
                             uint2 *blk_max, DevStatus *st, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    bin_count_kernel<<<dim3(bin_count_blocks(m)), dim3(256), 0, s>>>(pts, nrm, w, m, g, bin_count, key,
+    bin_count_kernel<<<dim3(bin_count_blocks(m)), dim3(kBinThreads), 0, s>>>(pts, nrm, w, m, g, bin_count, key,
                                                                      rank, blk_max, st);
     return hipGetLastError();
 }

@@ -371,8 +371,13 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
       HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
                                  P<uint32_t>(c->mc_codes), cases_out, st, s), "mc_count"); }
     { Timed t(c, K_MC_SCAN);
-      HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3,
-                             P<int32_t>(c->scan_part), st->mc_total, s), "mc_scan"); }
+      if (list) {
+          HIP_TRY(c, launch_mc_list_scan(list, P<int32_t>(c->mc_cnt), nb, P<int32_t>(c->mc_off), st, s),
+                  "mc_scan");
+      } else {
+          HIP_TRY(c, launch_scan(P<int32_t>(c->mc_cnt), P<int32_t>(c->mc_off), nb, 3,
+                                 P<int32_t>(c->scan_part), st->mc_total, s), "mc_scan");
+      } }
     // Generation follows without a host round trip: the kernels check the
     // totals against the capacities themselves and write nothing on a shortfall.
     const long long ncell_max = (long long)(g.n[0] - 1) * (g.n[1] - 1) * (g.n[2] - 1);
@@ -436,6 +441,7 @@ fvr_status fvr_create(int device, void *hip_stream, fvr_ctx **out) {
     e = mc_upload_table(counts, edges);
     if (e == hipSuccess) e = splat_configure();
     if (e == hipSuccess) e = fft_configure();
+    if (e == hipSuccess) e = mc_configure();
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_status, sizeof(DevStatus));
     if (e != hipSuccess) {
         fvr_status s = hip_fail(nullptr, e, "context setup");

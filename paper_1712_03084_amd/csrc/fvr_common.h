@@ -167,6 +167,13 @@ int mc_blocks(const Grid &g);
 // reading A (zero totals); the others go to list (st->mc_active entries).
 hipError_t launch_mc_classify(const float *level_f32, const float2 *rowmm, const Grid &g,
                               int32_t *blk_counts, int32_t *list, DevStatus *st, hipStream_t s);
+// Exclusive scan of the totals of the nb marching-cubes blocks when only the
+// blocks in list (st->mc_active of them) can be nonzero: out[3 b + c] for the
+// listed blocks (the others are not written), out[3 nb + c] and
+// st->mc_total[c] the totals.  One launch.
+hipError_t launch_mc_list_scan(const int32_t *list, const int32_t *cnt, int nb, int32_t *out,
+                               DevStatus *st, hipStream_t s);
+hipError_t mc_configure();
 // list: the blocks mc_classify left (null: every block).
 hipError_t launch_mc_count(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                            int32_t *blk_counts, uint32_t *codes, uint8_t *cases_out, DevStatus *st,

@@ -101,6 +101,158 @@ scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int 
     scan_tile_down<C>(in, out, n, partial, blockIdx.x, gridDim.x, totals);
 }
 
+// Offsets of the blocks in the marching-cubes list, in one block: the other
+// blocks have zero totals, so the exclusive scan over all nb blocks reduces
+// to a scan of the listed blocks in block order.  A bitmap of the listed
+// blocks gives each its rank in that order (popcounts of the words before
+// it), the listed totals are scanned in rank order, and each listed block
+// gets its offsets; out[3 nb + c] and st->mc_total receive the totals.  More
+// than kListCap listed blocks (a surface through most of the grid): a plain
+// scan over all nb blocks in the same block.
+constexpr int kListThreads = 1024;
+constexpr int kListCap = 4096;
+
+__global__ void __launch_bounds__(kListThreads)
+mc_list_scan_kernel(const int32_t *__restrict__ list, const int32_t *__restrict__ cnt, int nb,
+                    int32_t *__restrict__ out, DevStatus *st) {
+    extern __shared__ __attribute__((aligned(16))) int lsm[];
+    const int nw = (nb + 31) >> 5;          // bitmap words
+    unsigned *bits = reinterpret_cast<unsigned *>(lsm);
+    int *wbase = lsm + nw;                  // listed blocks before each word
+    int4 *srt = reinterpret_cast<int4 *>(lsm + ((2 * nw + 3) & ~3));  // (block, counts) in block order
+    __shared__ int wsum[3][kListThreads / 64];
+    const int n = st->mc_active;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (n <= kListCap) {
+        for (int w = threadIdx.x; w < nw; w += kListThreads) bits[w] = 0u;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kListThreads) {
+            const int b = list[i];
+            atomicOr(&bits[b >> 5], 1u << (b & 31));
+        }
+        __syncthreads();
+        // exclusive scan of the words' popcounts: thread t owns words [t S, (t+1) S)
+        const int S = (nw + kListThreads - 1) / kListThreads;
+        const int w0 = min((int)threadIdx.x * S, nw), w1 = min(w0 + S, nw);
+        int sp = 0;
+        for (int w = w0; w < w1; ++w) sp += __popc(bits[w]);
+        int incl = wave_incl_scan(sp);
+        if (lane == 63) wsum[0][wid] = incl;
+        __syncthreads();
+        int run = incl - sp;
+        for (int v = 0; v < wid; ++v) run += wsum[0][v];
+        for (int w = w0; w < w1; ++w) {
+            wbase[w] = run;
+            run += __popc(bits[w]);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kListThreads) {
+            const int b = list[i];
+            const int r = wbase[b >> 5] + __popc(bits[b >> 5] & ((1u << (b & 31)) - 1u));
+            srt[r] = make_int4(b, cnt[3 * b], cnt[3 * b + 1], cnt[3 * b + 2]);
+        }
+        __syncthreads();
+        // exclusive scan of the listed totals in block order
+        const int T = (n + kListThreads - 1) / kListThreads;
+        const int r0 = min((int)threadIdx.x * T, n), r1 = min(r0 + T, n);
+        int s3[3] = {0, 0, 0};
+        for (int r = r0; r < r1; ++r) {
+            s3[0] += srt[r].y;
+            s3[1] += srt[r].z;
+            s3[2] += srt[r].w;
+        }
+        int inc3[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            inc3[c] = wave_incl_scan(s3[c]);
+            if (lane == 63) wsum[c][wid] = inc3[c];
+        }
+        __syncthreads();
+        int run3[3], tot[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            run3[c] = inc3[c] - s3[c];
+            tot[c] = 0;
+            for (int v = 0; v < kListThreads / 64; ++v) {
+                if (v < wid) run3[c] += wsum[c][v];
+                tot[c] += wsum[c][v];
+            }
+        }
+        for (int r = r0; r < r1; ++r) {
+            const int4 e = srt[r];
+            out[3 * e.x + 0] = run3[0];
+            out[3 * e.x + 1] = run3[1];
+            out[3 * e.x + 2] = run3[2];
+            run3[0] += e.y;
+            run3[1] += e.z;
+            run3[2] += e.w;
+        }
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                out[3 * nb + c] = tot[c];
+                st->mc_total[c] = tot[c];
+            }
+        }
+        return;
+    }
+    // many listed blocks: a scan over every block, thread t owning a contiguous range
+    const int S = (nb + kListThreads - 1) / kListThreads;
+    const int b0 = min((int)threadIdx.x * S, nb), b1 = min(b0 + S, nb);
+    int s3[3] = {0, 0, 0};
+    for (int b = b0; b < b1; ++b) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s3[c] += cnt[3 * b + c];
+    }
+    int inc3[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        inc3[c] = wave_incl_scan(s3[c]);
+        if (lane == 63) wsum[c][wid] = inc3[c];
+    }
+    __syncthreads();
+    int run3[3], tot[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        run3[c] = inc3[c] - s3[c];
+        tot[c] = 0;
+        for (int v = 0; v < kListThreads / 64; ++v) {
+            if (v < wid) run3[c] += wsum[c][v];
+            tot[c] += wsum[c][v];
+        }
+    }
+    for (int b = b0; b < b1; ++b) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int v = cnt[3 * b + c];
+            out[3 * b + c] = run3[c];
+            run3[c] += v;
+        }
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            out[3 * nb + c] = tot[c];
+            st->mc_total[c] = tot[c];
+        }
+    }
+}
+
+static size_t mc_list_scan_lds(int nb) {
+    const int nw = (nb + 31) >> 5;
+    return (size_t)((2 * nw + 3) & ~3) * sizeof(int) + (size_t)kListCap * sizeof(int4);
+}
+
+hipError_t launch_mc_list_scan(const int32_t *list, const int32_t *cnt, int nb, int32_t *out,
+                               DevStatus *st, hipStream_t s) {
+    const size_t lds = mc_list_scan_lds(nb);
+    if (lds > (size_t)kLdsPerWorkgroup - 2048) return hipErrorInvalidValue;
+    mc_list_scan_kernel<<<dim3(1), dim3(kListThreads), lds, s>>>(list, cnt, nb, out, st);
+    return hipGetLastError();
+}
+
+hipError_t mc_configure() { return raise_dynamic_lds((const void *)mc_list_scan_kernel); }
+
 int scan_partials(int n) { return scan_tiles(n); }
 
 hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *partial,

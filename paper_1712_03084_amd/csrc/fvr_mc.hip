@@ -275,7 +275,9 @@ __device__ __forceinline__ float sample_trilinear(const float *__restrict__ A, c
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float u = __fsub_rn(__fdiv_rn(__fsub_rn(X[a], g.bmin[a]), g.h[a]), 0.5f);
-        int bb = (int)floorf(u);
+        // points inside the box have u in [-1/2, N - 1/2]; the clamp keeps the
+        // conversion defined for any input (NaN goes to -1)
+        int bb = (int)floorf(fminf(fmaxf(u, -1.0f), (float)g.n[a]));
         bb = min(max(bb, 0), g.n[a] - 2);
         b[a] = bb;
         t[a] = fminf(fmaxf(u - (float)bb, 0.0f), 1.0f);

@@ -285,6 +285,27 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
 // The output rows of thread t have the input form t + N2 m again
 // (m = q + Q k2), so an inverse transform starts from the registers after a
 // register permutation.
+// Raw buffer access to the spectrum allocation (three planes, below 2 GiB at
+// 512^3): 32-bit byte offsets from one 128-bit resource instead of a 64-bit
+// address per element, and the hardware's range check does the masking - a
+// load past the range returns zero and a store past it is dropped - so rows
+// known to be zero and idle lanes need neither a branch nor a memory access.
+// (Word 3 of the resource: the raw 32-bit-element format of gfx9-family GPUs.)
+constexpr unsigned kOob = 0xFFFFFFF0u;  // an offset past any spectrum allocation
+
+struct SpecBuf {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ SpecBuf(const float2 *base, unsigned bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base), (short)0, (int)bytes, 0x00020000)) {}
+    __device__ __forceinline__ float2 load(unsigned off) const {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    __device__ __forceinline__ void store(unsigned off, float2 v) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    }
+};
+
 template <int N1, int N2>
 struct Pencil {
     static constexpr int N = N1 * N2, Q = N1 / N2, THREADS = 16 * N2;
@@ -382,33 +403,40 @@ pen_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
     if (chunk == 0 && threadIdx.x == 0) zocc[z] = any ? 1 : 0;
     if (!any) return;  // an all-zero plane stays zero through the y transform
     const bool col = k0 + c < H;
-    float2 *p = spec + (size_t)z * N * Hp + k0 + c;
-    float2 a[N1], b[N1];
+    // byte offsets: rows of tiles that no point reaches (and idle lanes) get
+    // an offset past the range and read as zero
+    // one resource per plane, so the same offsets serve all three
+    const unsigned plb = (unsigned)(plane * sizeof(float2));
+    const SpecBuf s0(spec, plb), s1(spec + plane, plb), s2(spec + 2 * plane, plb);
+    const unsigned o0 = (unsigned)(((size_t)z * N * Hp + k0 + c) * sizeof(float2));
+    const unsigned rowb = (unsigned)Hp * sizeof(float2);
+    unsigned ro[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
         const int r = Pn::in_row(t, n1);
-        const bool ld = col && keep[r];
-        a[n1] = ld ? p[(size_t)r * Hp] : make_float2(0.f, 0.f);
-        b[n1] = ld ? p[plane + (size_t)r * Hp] : make_float2(0.f, 0.f);
+        ro[n1] = (col && keep[r]) ? o0 + (unsigned)r * rowb : kOob;
+    }
+    float2 a[N1], b[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+        a[n1] = s0.load(ro[n1]);
+        b[n1] = s1.load(ro[n1]);
     }
     Pn::template run<-1>(a, ex, tw, c, t);
     Pn::template run<-1>(b, ex, tw, c, t);
     // P0 <- F_y P0 + j w_y F_y P1
+    const unsigned so = col ? o0 : kOob;
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
         const int r = Pn::out_row(t, i);
         const float w = deriv_w(r, N, g.wstep[1]);
-        if (col) p[(size_t)r * Hp] = make_float2(a[i].x - w * b[i].y, a[i].y + w * b[i].x);
+        s0.store(col ? so + (unsigned)r * rowb : kOob, make_float2(a[i].x - w * b[i].y, a[i].y + w * b[i].x));
     }
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-        const int r = Pn::in_row(t, n1);
-        b[n1] = (col && keep[r]) ? p[2 * plane + (size_t)r * Hp] : make_float2(0.f, 0.f);
-    }
+    for (int n1 = 0; n1 < N1; ++n1) b[n1] = s2.load(ro[n1]);
     Pn::template run<-1>(b, ex, tw, c, t);
 #pragma unroll
-    for (int i = 0; i < N1; ++i)
-        if (col) p[2 * plane + (size_t)Pn::out_row(t, i) * Hp] = b[i];
+    for (int i = 0; i < N1; ++i) s2.store(col ? so + (unsigned)Pn::out_row(t, i) * rowb : kOob, b[i]);
 }
 
 template <int N1, int N2>
@@ -426,29 +454,25 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
         tw[i] = twg[i];
     }
     __syncthreads();
-    // element offsets from the block's base fit 32 bits (3 planes of at most
-    // 512 * 512 * 272 bins): a uniform 64-bit base plus 32-bit lane offsets
-    const unsigned zs = (unsigned)Ny * Hp;
-    const unsigned plane2 = 2u * (unsigned)N * zs;
+    // planes 0 and 2 through raw buffer resources: 32-bit byte offsets, and
+    // z planes that stay zero (and idle lanes) read as zero without a load
+    const size_t plane = (size_t)N * Ny * Hp;
+    const unsigned plb = (unsigned)(plane * sizeof(float2));
+    const SpecBuf s0(spec, plb), s2(spec + 2 * plane, plb);
+    const unsigned zsb = (unsigned)Ny * Hp * sizeof(float2);
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
     const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
     const bool col = k0 + c < H;
-    float2 *p = spec + ((size_t)ky * Hp + k0);
-    // the lane's plane flags first (one LDS round trip), then the loads
-    unsigned km = 0;
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) km |= (unsigned)(keep[Pn::in_row(t, n1)] != 0) << n1;
-    if (!col) km = 0;
+    const unsigned o0 = (unsigned)(((size_t)ky * Hp + k0 + c) * sizeof(float2));
     float2 a[N1], b[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
         const int r = Pn::in_row(t, n1);
-        const bool ld = (km >> n1) & 1u;
-        const unsigned o = (unsigned)r * zs + (unsigned)c;
-        a[n1] = ld ? p[o] : make_float2(0.f, 0.f);
-        b[n1] = ld ? p[plane2 + o] : make_float2(0.f, 0.f);
+        const unsigned o = (col && keep[r]) ? o0 + (unsigned)r * zsb : kOob;
+        a[n1] = s0.load(o);
+        b[n1] = s2.load(o);
     }
     Pn::template run<-1>(a, ex, tw, c, t);
     Pn::template run<-1>(b, ex, tw, c, t);
@@ -469,8 +493,7 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
     Pn::to_input(a);
     Pn::template run<+1>(a, ex, tw, c, t);
 #pragma unroll
-    for (int i = 0; i < N1; ++i)
-        if (col) p[(unsigned)Pn::out_row(t, i) * zs + (unsigned)c] = a[i];
+    for (int i = 0; i < N1; ++i) s0.store(col ? o0 + (unsigned)Pn::out_row(t, i) * zsb : kOob, a[i]);
 }
 
 template <int N1, int N2>

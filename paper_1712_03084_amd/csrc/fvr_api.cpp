@@ -4,9 +4,11 @@
 // schedule and float32 twiddle tables rounded from double), grow-only device
 // scratch, a pinned status block, and optional per-kernel HIP-event timing.
 // fvr_reconstruct enqueues the stages of Sec. III-B on the context's stream:
-//   reset -> bin_count -> scan -> bin_scatter -> splat+fft_x -> fft_y ->
-//   fft_z+solve -> fft_y_inv -> fft_x_c2r -> level -> mc_count -> scan
-//   -> [one device->host read of the counts] -> mc_generate -> mc_triangles.
+//   reset -> bin_count -> tile_list/tile_order (+ bin scan) -> bin_scatter ->
+//   splat+fft_x -> fft_y -> fft_z+solve -> fft_y_inv + fft_x_c2r (or the
+//   fused fft_yx_inv) -> level -> [mc_classify] -> mc_count -> scan ->
+//   mc_generate -> mc_triangles -> one device->host read of the status
+//   (mesh counts, flags, level) at the end.
 #include <algorithm>
 #include <array>
 #include <cmath>

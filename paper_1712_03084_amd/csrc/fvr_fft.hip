@@ -10,6 +10,8 @@
 //   fft_z_solve P0 <- F_z^-1 [ (F_z P0 + j w_z F_z P2) / |w|^2 ],  DC -> 0
 //   fft_y_inv   P0 <- F_y^-1 P0
 //   fft_x_c2r   A  <- F_x^-1 P0 / (Nx Ny Nz)          (real output)
+//   fft_yx_inv  both of the above in one kernel, one block per z plane
+//               (Nx = Ny = 256), with each row's range of A as a by-product
 //
 // By linearity this equals the paper's per-component transform, filter and
 // inverse followed by the sum of the X, Y and Z components.

@@ -8,16 +8,21 @@
 // precision arithmetic on the GPU.
 //
 // Marching cubes (end of Sec. III-B) without a dense per-cell output:
+//   mc_classify (when the row ranges of A are known) settles the blocks of
+//               1024 grid points whose cells lie on one side of the level and
+//               lists the others; the kernels below then run persistent
+//               blocks over that list
 //   mc_count    each thread owns 4 consecutive grid points q (linear order):
 //               the 3 grid edges leaving q that cross the level (vertices),
 //               the case of the cell with lower corner q, its triangle count
 //               and whether it is active; block totals -> blk_counts
 //               and, for blocks the surface passes, one code byte per point
 //               (the case, or the edge bits on the upper borders)
-//   scan        exclusive scan of the block totals (two launches; folding it
-//               into the neighbouring kernels with group totals kept by
-//               atomics measured slower: 117 us against 79 us for the four
-//               marching-cubes stages at 256^3)
+//   scan        exclusive scan of the block totals: over the listed blocks
+//               in one block when there is a list, else over all blocks in
+//               two launches (folding it into the neighbouring kernels with
+//               group totals kept by atomics measured slower: 117 us against
+//               79 us for the four marching-cubes stages at 256^3)
 //   mc_generate from the codes (blocks without vertices or active cells exit
 //               at once), block-scan, write each vertex at its global rank
 //               (vertex order = (linear index, axis)), record the vertex id of

@@ -336,7 +336,9 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     return FVR_OK;
 }
 
-fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float *field) {
+// final = false leaves the block partials for the classification of the
+// marching-cubes blocks to reduce (run_mc with rowmm).
+fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float *field, bool final = true) {
     const int m = (int)f->n_points;
     const int nb = level_blocks(m);
     HIP_TRY(c, ensure(c->lvl_sum, sizeof(double) * (size_t)nb), "alloc level partials");
@@ -344,14 +346,17 @@ fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float 
     HIP_TRY(c, ensure(c->level_f32, sizeof(float)), "alloc level");
     { Timed t(c, K_LEVEL);
       HIP_TRY(c, launch_level(f->points, m, field, g, P<double>(c->lvl_sum), P<int32_t>(c->lvl_cnt),
-                              P<DevStatus>(c->status), P<float>(c->level_f32), c->stream), "level"); }
+                              P<DevStatus>(c->status), P<float>(c->level_f32), final, c->stream),
+              "level"); }
     return FVR_OK;
 }
 
 // Marching cubes on `field` at the level in c->level_f32; status block must
 // already be reset.  Fills mesh counts; writes arrays only if they fit.
+// With rowmm, level_nb > 0 says the level's level_nb block partials are still to
+// be reduced (run_level with final = false); the classification does it.
 fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *rowmm, fvr_mesh *mesh,
-                  uint8_t *cases_out, bool check_invalid) {
+                  uint8_t *cases_out, bool check_invalid, int level_nb = 0) {
     const int nb = mc_blocks(g);
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
     HIP_TRY(c, ensure(c->mc_cnt, sizeof(int32_t) * 3 * (size_t)nb), "alloc mc counts");
@@ -366,8 +371,9 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
         HIP_TRY(c, ensure(c->mc_list, sizeof(int32_t) * (size_t)nb), "alloc mc block list");
         list = P<int32_t>(c->mc_list);
         Timed t(c, K_MC_CLASSIFY);
-        HIP_TRY(c, launch_mc_classify(P<float>(c->level_f32), rowmm, g, P<int32_t>(c->mc_cnt), list, st, s),
-                "mc_classify");
+        HIP_TRY(c, launch_mc_classify(P<float>(c->level_f32), level_nb > 0 ? P<double>(c->lvl_sum) : nullptr,
+                                      P<int32_t>(c->lvl_cnt), level_nb, rowmm, g, P<int32_t>(c->mc_cnt),
+                                      list, st, s), "mc_classify");
     }
     { Timed t(c, K_MC_COUNT);
       HIP_TRY(c, launch_mc_count(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
@@ -488,11 +494,14 @@ fvr_status fvr_reconstruct(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mesh) {
     const Grid g = make_grid(f->dims, f->bbox);
     HIP_TRY(c, ensure(c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2]), "alloc field");
     if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
-    if ((r = run_level(c, f, g, P<float>(c->field))) != FVR_OK) return r;
     // the fused inverse pass left each row's range of A: blocks of cells
-    // entirely on one side of the level skip the field
-    r = run_mc(c, g, P<float>(c->field), fft_yx_fused(g) ? P<float2>(c->rowmm) : nullptr, mesh, nullptr,
-               true);
+    // entirely on one side of the level skip the field, and their
+    // classification also finishes the level
+    const bool fused = fft_yx_fused(g);
+    const int level_nb = level_blocks((int)f->n_points);
+    if ((r = run_level(c, f, g, P<float>(c->field), !fused || level_nb == 0)) != FVR_OK) return r;
+    r = run_mc(c, g, P<float>(c->field), fused ? P<float2>(c->rowmm) : nullptr, mesh, nullptr, true,
+               fused ? level_nb : 0);
     mesh->level = c->host_status->level;
     return r;
 }

@@ -152,11 +152,13 @@ hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const F
                             hipStream_t s);
 
 // Iso-level: per-block double partial sums of trilinear A at accepted points,
-// then one block reduces them in a fixed order into st->level, st->n_used and
-// *level_f32 (the level rounded to float for the marching-cubes comparisons).
+// then (final) one block reduces them in a fixed order into st->level,
+// st->n_used and *level_f32 (the level rounded to float for the
+// marching-cubes comparisons).  Without final the partials are left for
+// launch_mc_classify to reduce.
 hipError_t launch_level(const float *pts, int m, const float *A, const Grid &g,
                         double *partial_sum, int32_t *partial_cnt, DevStatus *st,
-                        float *level_f32, hipStream_t s);
+                        float *level_f32, bool final, hipStream_t s);
 int level_blocks(int m);
 
 // Marching cubes.
@@ -165,8 +167,12 @@ int mc_blocks(const Grid &g);
 // From rowmm, the (min, max) of A per row (z Ny + y): blocks whose cells'
 // corner rows lie all above or all at/below the level are settled without
 // reading A (zero totals); the others go to list (st->mc_active entries).
-hipError_t launch_mc_classify(const float *level_f32, const float2 *rowmm, const Grid &g,
-                              int32_t *blk_counts, int32_t *list, DevStatus *st, hipStream_t s);
+// With partial_sum not null it also finishes the level from the lnb
+// partials launch_level left (same result as its final step); else it reads
+// *level_f32.
+hipError_t launch_mc_classify(float *level_f32, const double *partial_sum, const int32_t *partial_cnt,
+                              int lnb, const float2 *rowmm, const Grid &g, int32_t *blk_counts,
+                              int32_t *list, DevStatus *st, hipStream_t s);
 // Exclusive scan of the totals of the nb marching-cubes blocks when only the
 // blocks in list (st->mc_active of them) can be nonzero: out[3 b + c] for the
 // listed blocks (the others are not written), out[3 nb + c] and

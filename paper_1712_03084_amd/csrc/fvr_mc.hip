@@ -335,9 +335,11 @@ level_partial_kernel(const float *__restrict__ pts, int m, const float *__restri
     }
 }
 
-__global__ void __launch_bounds__(kLevelThreads)
-level_final_kernel(const double *__restrict__ psum, const int32_t *__restrict__ pcnt, int nb,
-                   DevStatus *st, float *level_f32) {
+// Sum and count over the nb block partials (compensated, in a fixed order,
+// so every caller gets the same bits).  Called by all kLevelThreads threads
+// of a block; each gets the totals.
+__device__ __forceinline__ void level_reduce(const double *__restrict__ psum, const int32_t *__restrict__ pcnt,
+                                             int nb, double &total, int &count) {
     __shared__ double ssum[kLevelThreads];
     __shared__ int scnt[kLevelThreads];
     double sum = 0.0, comp = 0.0;
@@ -374,25 +376,42 @@ level_final_kernel(const double *__restrict__ psum, const int32_t *__restrict__ 
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double L = scnt[0] > 0 ? ssum[0] / (double)scnt[0] : 0.0;
-        st->n_used = scnt[0];
+    total = ssum[0];
+    count = scnt[0];
+}
+
+// L = sum / count (0 when no sample was accepted), kept in fp64 in the
+// status block and as the float the classification compares against.
+__device__ __forceinline__ float level_publish(double total, int count, DevStatus *st, float *level_f32) {
+    const double L = count > 0 ? total / (double)count : 0.0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->n_used = count;
         st->level = L;
         *level_f32 = (float)L;
     }
+    return (float)L;
+}
+
+__global__ void __launch_bounds__(kLevelThreads)
+level_final_kernel(const double *__restrict__ psum, const int32_t *__restrict__ pcnt, int nb,
+                   DevStatus *st, float *level_f32) {
+    double total;
+    int count;
+    level_reduce(psum, pcnt, nb, total, count);
+    level_publish(total, count, st, level_f32);
 }
 
 int level_blocks(int m) { return (m + kLevelThreads * kLevelPpt - 1) / (kLevelThreads * kLevelPpt); }
 
 hipError_t launch_level(const float *pts, int m, const float *A, const Grid &g, double *psum,
-                        int32_t *pcnt, DevStatus *st, float *level_f32, hipStream_t s) {
+                        int32_t *pcnt, DevStatus *st, float *level_f32, bool final, hipStream_t s) {
     const int nb = level_blocks(m);
     if (nb > 0) {
         level_partial_kernel<<<dim3(nb), dim3(kLevelThreads), 0, s>>>(pts, m, A, g, psum, pcnt);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    level_final_kernel<<<1, kLevelThreads, 0, s>>>(psum, pcnt, nb, st, level_f32);
+    if (final) level_final_kernel<<<1, kLevelThreads, 0, s>>>(psum, pcnt, nb, st, level_f32);
     return hipGetLastError();
 }
 
@@ -499,12 +518,24 @@ __device__ __forceinline__ int block_sum(int v, int *red) {
 // and appends the others to `list` (st->mc_active entries, in no particular
 // order).  The rows r0 .. r1 of a block's points and their cells' corners
 // lie in rows r0 .. r1 + 1 and the same rows of the next plane (r + Ny).
-__global__ void __launch_bounds__(256)
-mc_classify_kernel(const float *__restrict__ level_f32, const float2 *__restrict__ rowmm, Grid g,
+// With the level's block partials given (psum not null), every block
+// reduces them itself and block 0 publishes the level (the work of
+// level_final_kernel, with the same bits); else the level is *level_f32.
+__global__ void __launch_bounds__(kLevelThreads)
+mc_classify_kernel(float *__restrict__ level_f32, const double *__restrict__ psum,
+                   const int32_t *__restrict__ pcnt, int lnb, const float2 *__restrict__ rowmm, Grid g,
                    int nb, int32_t *__restrict__ blk_counts, int32_t *__restrict__ list, DevStatus *st) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const float L = *level_f32;
+    float L;
+    if (psum) {
+        double total;
+        int count;
+        level_reduce(psum, pcnt, lnb, total, count);
+        L = level_publish(total, count, st, level_f32);
+    } else {
+        L = *level_f32;
+    }
     bool active = false, inside = false;
     if (b < nb) {
         const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -811,11 +842,12 @@ mc_triangles_kernel(const int4 *__restrict__ cells, const int32_t *__restrict__ 
 // the surface passes are a few percent of all (a 256^3 grid has 16k).
 constexpr int kMcPersist = 2048;
 
-hipError_t launch_mc_classify(const float *level_f32, const float2 *rowmm, const Grid &g,
-                              int32_t *blk_counts, int32_t *list, DevStatus *st, hipStream_t s) {
+hipError_t launch_mc_classify(float *level_f32, const double *psum, const int32_t *pcnt, int lnb,
+                              const float2 *rowmm, const Grid &g, int32_t *blk_counts, int32_t *list,
+                              DevStatus *st, hipStream_t s) {
     const int nb = mc_blocks(g);
-    mc_classify_kernel<<<dim3((nb + 255) / 256), dim3(256), 0, s>>>(level_f32, rowmm, g, nb, blk_counts,
-                                                                    list, st);
+    mc_classify_kernel<<<dim3((nb + kLevelThreads - 1) / kLevelThreads), dim3(kLevelThreads), 0, s>>>(
+        level_f32, psum, pcnt, lnb, rowmm, g, nb, blk_counts, list, st);
     return hipGetLastError();
 }
 

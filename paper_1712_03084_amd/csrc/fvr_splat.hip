@@ -53,10 +53,21 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
                  const float *__restrict__ w, int m, Grid g, int32_t *__restrict__ bin_count,
                  int32_t *__restrict__ key, int32_t *__restrict__ rank, uint2 *__restrict__ blk_max,
                  DevStatus *st) {
+    constexpr int kHash = 2 * kBinThreads;  // power of two, twice the block: probing always ends
+    static_assert(kHash == 1 << 11, "hash width");
+    __shared__ int hkey[kHash], hcnt[kHash], hbase[kHash];             // bins
+    __shared__ int gkey[kHash], gcnt[kHash], goff[kHash], gbin[kHash];  // (bin, i0_x) pairs
+    // cleared first: the stores overlap the loads of the points
+    for (int t = threadIdx.x; t < kHash; t += blockDim.x) {
+        hkey[t] = -1;
+        hcnt[t] = 0;
+        gkey[t] = -1;
+        gcnt[t] = 0;
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     bool bad = false, rej = false;
-    int k = -1;
+    int k = -1, kx = 0;  // bin, and the footprint x origin i0_x + 1
     float wmax = 0.0f, wnmax = 0.0f;
     if (i < m) {
         const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
@@ -69,54 +80,57 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
             if (acc) {
                 wmax = wi;
                 wnmax = wi * fmaxf(fabsf(nx), fmaxf(fabsf(ny), fabsf(nz)));
+                int ix = (int)floorf(voxel_coord(x, g.bmin[0], g.h[0]));
                 int iy = (int)floorf(voxel_coord(y, g.bmin[1], g.h[1]));
                 int iz = (int)floorf(voxel_coord(z, g.bmin[2], g.h[2]));
+                ix = min(max(ix, -1), g.n[0] - 1);
                 iy = min(max(iy, -1), g.n[1] - 1);
                 iz = min(max(iz, -1), g.n[2] - 1);
                 k = (iz + 1) * (g.n[1] + 1) + (iy + 1);
+                kx = ix + 1;
             } else {
                 rej = true;
             }
         }
     }
-    // Block-aggregated histogram: points arrive in capture (scanline) order, so
-    // a block holds few distinct bins.  Each wave first splits into groups of
-    // equal bin (no memory traffic); the groups' first lanes then merge the
-    // block's groups of each bin in an LDS hash table (each gets its offset
-    // within the block's group), one thread per distinct bin adds the block's
-    // count with a single global atomic - all in the same round trip - and each
-    // lane's rank is that base plus its offsets.
-    constexpr int kHash = 2 * kBinThreads;  // power of two, twice the block: probing always ends
-    __shared__ int hkey[kHash], hcnt[kHash], hbase[kHash];
-    for (int t = threadIdx.x; t < kHash; t += blockDim.x) {
-        hkey[t] = -1;
-        hcnt[t] = 0;
-    }
+    // Block-aggregated histogram whose ranks group a bin's points by i0_x.
+    // Points arrive in capture (scanline) order, so a block holds few
+    // distinct bins, and the points of one bin and i0_x reach the same 4^3
+    // voxels: placed next to each other, the splat sums them in registers
+    // before one LDS atomic per voxel (a proxy frame's runs grow from 1.4 to
+    // 2.3 points).  Each point claims its (bin, i0_x) pair in one LDS hash
+    // table (its offset within the block's points of the pair); a thread per
+    // distinct pair places the pair within the block's share of its bin in a
+    // second table (offset within the bin); a thread per distinct bin adds
+    // the block's count with a single global atomic - the global traffic of
+    // a plain per-bin histogram - and a point's rank is the sum of the three
+    // offsets.
     __syncthreads();
-    unsigned long long todo = __ballot(k >= 0);
-    int leader = lane, pos = 0, size = 0;
-    while (todo) {
-        const int l = __ffsll((unsigned long long)todo) - 1;
-        const int lk = __shfl(k, l, 64);
-        const unsigned long long grp = __ballot(k == lk);
-        if (k == lk) {
-            leader = l;
-            pos = __popcll(grp & ((1ull << lane) - 1ull));
-        }
-        if (lane == l) size = __popcll(grp);
-        todo &= ~grp;
-    }
-    int slot = 0, woff = 0;
-    if (k >= 0 && leader == lane) {
-        unsigned h = ((unsigned)k * 2654435761u) >> (32 - 11);  // log2(kHash) bits
-        static_assert(kHash == 1 << 11, "hash width");
+    const int nxk = g.n[0] + 1;
+    const int k2 = k >= 0 ? k * nxk + kx : -1;  // < 513^3 < 2^31
+    auto probe = [](int *keys, int key) {
+        unsigned h = ((unsigned)key * 2654435761u) >> (32 - 11);  // log2(kHash) bits
         for (;;) {
-            const int prev = atomicCAS(&hkey[h], -1, k);
-            if (prev == -1 || prev == k) break;
+            const int prev = atomicCAS(&keys[h], -1, key);
+            if (prev == -1 || prev == key) return (int)h;
             h = (h + 1) & (kHash - 1);
         }
-        slot = (int)h;
-        woff = atomicAdd(&hcnt[slot], size);
+    };
+    // the lanes of a wave mostly hold distinct pairs, so their table
+    // atomics rarely meet on one address
+    int gslot = 0, myoff = 0;
+    if (k2 >= 0) {
+        gslot = probe(gkey, k2);
+        myoff = atomicAdd(&gcnt[gslot], 1);
+        gbin[gslot] = k;  // every point of the pair stores the same bin
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kHash; t += blockDim.x) {
+        if (gkey[t] >= 0) {
+            const int slot = probe(hkey, gbin[t]);
+            gbin[t] = slot;
+            goff[t] = atomicAdd(&hcnt[slot], gcnt[t]);
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < kHash; t += blockDim.x) {
@@ -124,10 +138,7 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
         if (kk >= 0) hbase[t] = atomicAdd(&bin_count[kk], hcnt[t]);
     }
     __syncthreads();
-    int base = 0;
-    if (k >= 0 && leader == lane) base = hbase[slot] + woff;
-    base = __shfl(base, leader, 64);
-    const int myrank = base + pos;
+    const int myrank = k2 >= 0 ? hbase[gbin[gslot]] + goff[gslot] + myoff : 0;
     if (i < m) {
         key[i] = k;
         if (k >= 0) rank[i] = myrank;

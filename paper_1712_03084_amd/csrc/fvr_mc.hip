@@ -306,16 +306,28 @@ level_partial_kernel(const float *__restrict__ pts, int m, const float *__restri
     double sum = 0.0, comp = 0.0;
     int cnt = 0;
     const int base = blockIdx.x * kLevelThreads * kLevelPpt;
+    // all of a thread's samples are gathered before any is summed, so their
+    // loads overlap: positions from clamped indices, then the 8 corners of
+    // every position (the sampler keeps any input inside the grid); points
+    // past the end or outside the box are then skipped in order
+    float v[kLevelPpt];
+    bool acc[kLevelPpt];
+#pragma unroll
     for (int j = 0; j < kLevelPpt; ++j) {
         const int i = base + j * kLevelThreads + threadIdx.x;
-        if (i >= m) break;
-        const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
-        const bool acc = x >= g.bmin[0] && x <= g.bmax[0] && y >= g.bmin[1] && y <= g.bmax[1] &&
-                         z >= g.bmin[2] && z <= g.bmax[2];
-        if (!acc) continue;  // NaN coordinates fail the comparisons too
-        const double v = (double)sample_trilinear(A, g, x, y, z);
-        const double s = sum + v;
-        comp += fabs(sum) >= fabs(v) ? (sum - s) + v : (v - s) + sum;
+        const int ic = min(i, m - 1);
+        const float x = pts[3 * ic], y = pts[3 * ic + 1], z = pts[3 * ic + 2];
+        // NaN coordinates fail the comparisons too
+        acc[j] = i < m && x >= g.bmin[0] && x <= g.bmax[0] && y >= g.bmin[1] && y <= g.bmax[1] &&
+                 z >= g.bmin[2] && z <= g.bmax[2];
+        v[j] = sample_trilinear(A, g, x, y, z);
+    }
+#pragma unroll
+    for (int j = 0; j < kLevelPpt; ++j) {
+        if (!acc[j]) continue;
+        const double vj = (double)v[j];
+        const double s = sum + vj;
+        comp += fabs(sum) >= fabs(vj) ? (sum - s) + vj : (vj - s) + sum;
         sum = s;
         ++cnt;
     }

@@ -21,7 +21,7 @@ import os
 from collections import namedtuple
 
 __all__ = [
-    "FvrError", "FvrUnavailable", "Context", "Mesh", "reconstruct", "indicator",
+    "FvrError", "FvrUnavailable", "Context", "PreparedFrame", "Mesh", "reconstruct", "indicator",
     "extract", "debug_splat", "mc_table", "check_grid", "library_path", "load_library",
     "STATUS",
 ]
@@ -150,6 +150,43 @@ def _dev_f32(t, name, device, ncols):
     return t if t.is_contiguous() else t.contiguous()
 
 
+class PreparedFrame:
+    """One frame's marshalled fvr_reconstruct call (``Context.prepare``)."""
+
+    def __init__(self, ctx, frame, keep, out, stream):
+        self._ctx, self._f, self._keep, self._stream = ctx, frame, keep, stream
+        self.vertices_buf, self.triangles_buf = out
+        m = _Mesh()
+        m.vertices = self.vertices_buf.data_ptr()
+        m.triangles = self.triangles_buf.data_ptr()
+        m.vertex_capacity = self.vertices_buf.shape[0]
+        m.triangle_capacity = self.triangles_buf.shape[0]
+        self._m = m
+        self._args = (ctx.handle, ctypes.byref(frame), ctypes.byref(m))
+        self._fn = ctx.lib.fvr_reconstruct
+
+    def run(self):
+        """Sec. III-B end to end on the frame's current contents; returns
+        (n_vertices, n_triangles), the leading rows of the output buffers."""
+        ctx = self._ctx
+        if ctx._cur_stream != self._stream:
+            _check(ctx.lib, ctx.lib.fvr_set_stream(ctx.handle, ctypes.c_void_p(self._stream)), ctx.handle)
+            ctx._cur_stream = self._stream
+        m = self._m
+        m.vertex_capacity = self.vertices_buf.shape[0]
+        m.triangle_capacity = self.triangles_buf.shape[0]
+        st = self._fn(*self._args)
+        if st:
+            _check(ctx.lib, st, ctx.handle)
+        return m.n_vertices, m.n_triangles
+
+    def mesh(self) -> Mesh:
+        """The last run's result as views of the output buffers."""
+        m = self._m
+        return Mesh(self.vertices_buf[:m.n_vertices], self.triangles_buf[:m.n_triangles], m.level,
+                    int(m.n_rejected), bool(m.flags & FVR_FLAG_OPEN_SURFACE))
+
+
 class Context:
     """An fvr_ctx on one device: resident FFT plans, twiddles and scratch."""
 
@@ -246,6 +283,26 @@ class Context:
         return self._run_mesh(lambda m: self.lib.fvr_reconstruct(self.handle, ctypes.byref(f),
                                                                  ctypes.byref(m)),
                               dims, out, vertex_capacity, triangle_capacity)
+
+    def prepare(self, points, normals, weights=None, grid_dim=(128, 128, 128),
+                bbox=((-1, -1, -1), (1, 1, 1)), out=None, vertex_capacity=None,
+                triangle_capacity=None) -> "PreparedFrame":
+        """A frame for repeated reconstruction: the tensors are checked and
+        the call's arguments marshalled once.  ``run()`` then enqueues the
+        same work as ``reconstruct`` on the stream that was current here,
+        reading the tensors' contents at each call (a serving loop refills
+        the same input and output buffers between runs).  The output
+        buffers are ``out`` or allocated once; a capacity shortfall raises."""
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        self._stream()
+        torch = _torch()
+        if out is None:
+            nx, ny, nz = tuple(f.dims)
+            vcap = vertex_capacity or max(4096, 6 * (nx * ny + ny * nz + nx * nz))
+            tcap = triangle_capacity or 2 * vcap
+            out = (torch.empty((vcap, 3), dtype=torch.float32, device=f"cuda:{self.device}"),
+                   torch.empty((tcap, 3), dtype=torch.int32, device=f"cuda:{self.device}"))
+        return PreparedFrame(self, f, keep, out, self._cur_stream)
 
     def indicator(self, points, normals, weights=None, grid_dim=(128, 128, 128),
                   bbox=((-1, -1, -1), (1, 1, 1))):

@@ -169,3 +169,46 @@ def test_one_dense_bin(ctx):
     rng_ = Ao.max() - Ao.min()
     assert np.abs(A - Ao).max() <= 1e-4 * rng_
     assert abs(L - Lo) <= 1e-4 * rng_
+
+
+def test_prepared_frame_matches_reconstruct_and_reads_refilled_inputs(ctx):
+    """Context.prepare marshals the call once; each run() must equal
+    reconstruct() on the buffers' current contents, bit for bit."""
+    fa = synth.config_frame("sphere64")
+    fb = synth.config_frame("sphere64", seed=5)
+    assert fb.n_points == fa.n_points and fb.dims == fa.dims and fb.bbox == fa.bbox
+    print(f"[prepared] sphere64 {fa.n_points} points, seeds 0 and 5 through one staging buffer",
+          flush=True)
+    pa, pb = _frame_dev(fa), _frame_dev(fb)
+    ref_a = _mesh_np(ctx.reconstruct(*pa, grid_dim=fa.dims, bbox=fa.bbox))
+    ref_b = _mesh_np(ctx.reconstruct(*pb, grid_dim=fb.dims, bbox=fb.bbox))
+    assert not np.array_equal(ref_a[0], ref_b[0])
+    staging = tuple(t.clone() for t in pa)
+    nv_max = max(len(ref_a[0]), len(ref_b[0]))
+    nt_max = max(len(ref_a[1]), len(ref_b[1]))
+    out = (torch.empty((nv_max, 3), dtype=torch.float32, device="cuda"),
+           torch.empty((nt_max, 3), dtype=torch.int32, device="cuda"))
+    prep = ctx.prepare(*staging, grid_dim=fa.dims, bbox=fa.bbox, out=out)
+    for want, src in ((ref_a, pa), (ref_b, pb), (ref_a, pa)):
+        for dst, s in zip(staging, src):
+            dst.copy_(s)
+        nv, nt = prep.run()
+        got = _mesh_np(prep.mesh())
+        assert (nv, nt) == (len(want[0]), len(want[1]))
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+def test_prepared_frame_reports_a_capacity_shortfall(ctx):
+    f = synth.config_frame("sphere64")
+    print("[prepared] capacity shortfall", flush=True)
+    dev = _frame_dev(f)
+    full = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox)
+    out = (torch.empty((16, 3), dtype=torch.float32, device="cuda"),
+           torch.empty((16, 3), dtype=torch.int32, device="cuda"))
+    prep = ctx.prepare(*dev, grid_dim=f.dims, bbox=f.bbox, out=out)
+    with pytest.raises(fvr.FvrError) as e:
+        prep.run()
+    assert "CAPACITY" in str(e.value)
+    # the required counts are reported in the prepared call's mesh struct
+    assert prep._m.n_vertices == full.vertices.shape[0]
+    assert prep._m.n_triangles == full.triangles.shape[0]

@@ -65,3 +65,15 @@ def test_entry_points_fail_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(fvr, "_lib", None)
     with pytest.raises(fvr.FvrUnavailable):
         fvr.load_library()
+
+
+def test_bench_covers_every_timed_kernel():
+    """bench.py prices and fingerprints each launch the library can time."""
+    import bench
+    lib = fvr.load_library()
+    names = {lib.fvr_timing_name(i).decode() for i in range(lib.fvr_timing_count())}
+    assert names >= {"splat_fft_x", "fft_yx_inv", "mc_classify"}
+    assert names <= set(bench.KERNEL_SOURCES), names - set(bench.KERNEL_SOURCES)
+    priced = set(bench.kernel_alg_bytes((256, 256, 256), 700_000, 40_000, 80_000))
+    assert priced <= names, priced - names
+    assert names - priced <= {"prep", "mc_scan"}, names - priced

@@ -404,8 +404,7 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
     { Timed t(c, K_MC_TRIANGLES);
       HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), P<int32_t>(c->vidx), g, mesh->triangles, st,
                                      caps, s), "mc_triangles"); }
-    HIP_TRY(c, hipMemcpyAsync(c->host_status, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s),
-            "status readback");
+    HIP_TRY(c, launch_status_publish(st, c->host_status, s), "status readback");
     fvr_status r = sync(c);
     if (r != FVR_OK) return r;
     const DevStatus hs = *c->host_status;
@@ -519,8 +518,8 @@ fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, doubl
     HIP_TRY(c, ensure(c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2]), "alloc field");
     if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
     if ((r = run_level(c, f, g, P<float>(c->field))) != FVR_OK) return r;
-    HIP_TRY(c, hipMemcpyAsync(c->host_status, c->status.p, sizeof(DevStatus), hipMemcpyDeviceToHost,
-                              c->stream), "status readback");
+    HIP_TRY(c, launch_status_publish(P<DevStatus>(c->status), c->host_status, c->stream),
+            "status readback");
     if ((r = sync(c)) != FVR_OK) return r;
     if (c->host_status->flags & kFlagInvalid)
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
@@ -563,8 +562,8 @@ fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
     HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(v_out), 3 * (int64_t)g.n[0] * g.n[1] * g.n[2], 0,
                                c->stream), "clear v_out");
     if ((r = run_field(c, f, p, g, nullptr, v_out, true)) != FVR_OK) return r;
-    HIP_TRY(c, hipMemcpyAsync(c->host_status, c->status.p, sizeof(DevStatus), hipMemcpyDeviceToHost,
-                              c->stream), "status readback");
+    HIP_TRY(c, launch_status_publish(P<DevStatus>(c->status), c->host_status, c->stream),
+            "status readback");
     if ((r = sync(c)) != FVR_OK) return r;
     if (c->host_status->flags & kFlagInvalid)
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");

@@ -83,6 +83,8 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
 // Reset the status block and zero `nbins` bin counters in one launch.
 hipError_t launch_prep(DevStatus *st, int32_t *bins, int nbins, hipStream_t s);
+// Copy of the status block into pinned host memory (hipHostMalloc) by a kernel.
+hipError_t launch_status_publish(const DevStatus *st, DevStatus *host, hipStream_t s);
 
 // Exclusive scan of `n` items of `C` interleaved int32 components (C = 3):
 // out[i*C + c] = sum_{j<i} in[j*C + c]; out[n*C + c] = total; totals[c] = total.

@@ -77,6 +77,21 @@ __global__ void prep_kernel(DevStatus *st, int32_t *bins, int nbins) {
     if (bins && i < nbins) bins[i] = 0;
 }
 
+// The status block copied by one small kernel into the context's pinned,
+// device-accessible host copy: the stores go straight to host memory and are
+// visible once the stream has been synchronized.  Cheaper at the end of a
+// frame than a device-to-host copy (about 4 us per frame on the proxy frame).
+__global__ void status_publish_kernel(const DevStatus *__restrict__ st, uint32_t *__restrict__ dst) {
+    static_assert(sizeof(DevStatus) % 4 == 0, "status words");
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(st);
+    for (int i = threadIdx.x; i < (int)(sizeof(DevStatus) / 4); i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_status_publish(const DevStatus *st, DevStatus *host, hipStream_t s) {
+    status_publish_kernel<<<1, 64, 0, s>>>(st, reinterpret_cast<uint32_t *>(host));
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(DevStatus *st, int32_t *bins, int nbins, hipStream_t s) {
     const int blocks = nbins > 0 ? (nbins + 255) / 256 : 1;
     prep_kernel<<<dim3(blocks), dim3(256), 0, s>>>(st, bins, nbins);

@@ -399,12 +399,12 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
     { Timed t(c, K_MC_GENERATE);
       HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
                                     P<int32_t>(c->mc_off), P<uint32_t>(c->mc_codes), mesh->vertices,
-                                    P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, s),
+                                    P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, c->host_status, s),
               "mc_generate"); }
     { Timed t(c, K_MC_TRIANGLES);
       HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), P<int32_t>(c->vidx), g, mesh->triangles, st,
                                      caps, s), "mc_triangles"); }
-    HIP_TRY(c, launch_status_publish(st, c->host_status, s), "status readback");
+    // mc_generate copied the final status block to c->host_status
     fvr_status r = sync(c);
     if (r != FVR_OK) return r;
     const DevStatus hs = *c->host_status;

@@ -196,7 +196,9 @@ struct MeshCaps {
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                               const int32_t *blk_counts, const int32_t *blk_offsets,
                               const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
-                              const DevStatus *st, MeshCaps caps, hipStream_t s);
+                              const DevStatus *st, MeshCaps caps, DevStatus *host_status, hipStream_t s);
+// (host_status, if not null: pinned host memory that receives a copy of the
+// final status block, as launch_status_publish would write it)
 hipError_t launch_mc_triangles(const int4 *cells, const int32_t *vidx, const Grid &g, int32_t *tris,
                                const DevStatus *st, MeshCaps caps, hipStream_t s);
 

@@ -722,9 +722,16 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
                    const int32_t *__restrict__ list, const int32_t *__restrict__ blk_counts,
                    const int32_t *__restrict__ blk_off, const uint32_t *__restrict__ codes,
                    float *__restrict__ verts, int32_t *__restrict__ vidx, int4 *__restrict__ cells,
-                   const DevStatus *st, MeshCaps caps) {
+                   const DevStatus *st, MeshCaps caps, uint32_t *__restrict__ host_status) {
     __shared__ int red[12];
     __shared__ uint8_t s_ntri[256];
+    // The status block is final here (the mesh kernels only read it): block 0
+    // copies it to the host (as status_publish_kernel does), and the stores'
+    // latency hides behind the mesh work instead of costing a launch.
+    if (host_status && blockIdx.x == 0) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(st);
+        for (int i = threadIdx.x; i < (int)(sizeof(DevStatus) / 4); i += blockDim.x) host_status[i] = src[i];
+    }
     if (!mesh_fits(st, caps)) return;
     // the blocks in `list` (persistent blocks stride over it), or block
     // blockIdx.x when list is null
@@ -893,9 +900,10 @@ hipError_t launch_mc_count(const float *A, const float *level_f32, const int32_t
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                               const int32_t *blk_counts, const int32_t *blk_offsets,
                               const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
-                              const DevStatus *st, MeshCaps caps, hipStream_t s) {
+                              const DevStatus *st, MeshCaps caps, DevStatus *host_status, hipStream_t s) {
     mc_generate_kernel<<<dim3(mc_grid(g, list)), dim3(kMcThreads), 0, s>>>(
-        A, level_f32, g, list, blk_counts, blk_offsets, codes, verts, vidx, cells, st, caps);
+        A, level_f32, g, list, blk_counts, blk_offsets, codes, verts, vidx, cells, st, caps,
+        reinterpret_cast<uint32_t *>(host_status));
     return hipGetLastError();
 }
 

@@ -40,6 +40,17 @@ __device__ __forceinline__ float voxel_coord(float x, float bmin, float h) {
     return __fsub_rn(__fdiv_rn(__fsub_rn(x, bmin), h), 0.5f);
 }
 
+// Nearest integer of a fixed-point term (|x| < 2^30), ties upward, in one
+// instruction (v_cvt_rpi_i32_f32 = floor(x + 1/2)); a correctly rounded
+// conversion takes a separate round-to-even first, and the accumulation loop
+// is bound by its vector instruction count.  The error stays within half a
+// unit per term (one unit if the hardware rounded the sum x + 1/2).
+__device__ __forceinline__ int round_units(float x) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ bool finite3(float a, float b, float c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
@@ -422,10 +433,10 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
             float h2 = __builtin_amdgcn_exp2f(sc.e2[0] * (1.0f - 2.0f * d0));
 #pragma unroll
             for (int ox = 0; ox < 4; ++ox) {
-                run[ox][0] += __float2int_rn(g1 * sx);
-                run[ox][1] += __float2int_rn(g1 * sy);
-                run[ox][2] += __float2int_rn(g1 * sz);
-                run[ox][3] += __float2int_rn(g2 * a2);
+                run[ox][0] += round_units(g1 * sx);
+                run[ox][1] += round_units(g1 * sy);
+                run[ox][2] += round_units(g1 * sz);
+                run[ox][3] += round_units(g2 * a2);
                 if (ox < 3) {
                     g1 *= h1;
                     g2 *= h2;

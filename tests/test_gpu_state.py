@@ -212,3 +212,21 @@ def test_prepared_frame_reports_a_capacity_shortfall(ctx):
     # the required counts are reported in the prepared call's mesh struct
     assert prep._m.n_vertices == full.vertices.shape[0]
     assert prep._m.n_triangles == full.triangles.shape[0]
+
+
+def test_level_finished_by_the_block_classification_has_the_same_bits():
+    """At N_x = N_y = 256 the marching-cubes block classification reduces the
+    level's block partials itself; the result must equal the separate final
+    reduction that fvr_indicator runs, bit for bit."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fvr.Context(0)
+    f = synth.config_frame("sphere64")
+    dims = (256, 256, 96)
+    print(f"[level fold] sphere {f.n_points} points on {dims}", flush=True)
+    dev = _frame_dev(f)
+    _, L = c.indicator(*dev, grid_dim=dims, bbox=f.bbox)
+    m = c.reconstruct(*dev, grid_dim=dims, bbox=f.bbox)
+    assert m.level == L
+    assert m.vertices.shape[0] > 0
+    c.close()

@@ -36,6 +36,8 @@ __all__ = [
     "human_proxy_frame",
     "config_frame",
     "CONFIGS",
+    "isolated_weights_frame",
+    "spread_weights",
 ]
 
 
@@ -370,3 +372,45 @@ def config_frame(name: str, seed: int | None = None) -> Frame:
     if kind == "sphere":
         return sphere_frame(**c)
     return human_proxy_frame(**c)
+
+
+# ---------------------------------------------------------------------------
+# Wide weight ranges (confidence weights that reach zero at silhouettes)
+# ---------------------------------------------------------------------------
+def isolated_weights_frame(weights=(0.01, 100.0), grid: int = 32, seed: int = 0,
+                           spacing_voxels: float = 9.0, pairs: int = 1) -> Frame:
+    """Groups of single points with very different weights on a small grid.
+
+    Each group places one point per entry of ``weights`` on a line along x,
+    ``spacing_voxels`` voxels apart (far enough that their 4^3 footprints do
+    not overlap when the spacing exceeds 4), at seeded sub-voxel offsets, with
+    seeded unit normals.  Groups are stacked along y and z.  The bbox is
+    [-1, 1]^3 and the grid ``grid``^3.
+    """
+    rng = np.random.default_rng(seed)
+    h = 2.0 / grid
+    P, N, W = [], [], []
+    for g in range(pairs):
+        base = np.array([-0.5, -0.5 + 0.45 * (g % 3), -0.5 + 0.45 * (g // 3)])
+        for j, w in enumerate(weights):
+            off = rng.uniform(0.0, 1.0, 3) * h
+            P.append(base + np.array([j * spacing_voxels * h, 0.0, 0.0]) + off)
+            n = rng.standard_normal(3)
+            N.append(n / np.linalg.norm(n))
+            W.append(w)
+    m = len(P)
+    return Frame(_f32(np.array(P)), _f32(np.array(N)), _f32(np.array(W)),
+                 (grid, grid, grid), (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0),
+                 name=f"isolated_weights_{m}", info={"seed": seed, "weights": tuple(weights)})
+
+
+def spread_weights(frame: Frame, decades: float = 4.0, seed: int = 0) -> Frame:
+    """The same frame with every weight multiplied by 10^U(-decades/2, decades/2)
+    (seeded), so the weights span about ``decades`` more powers of ten."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-0.5 * decades, 0.5 * decades, frame.n_points)
+    w = frame.weights.astype(np.float64) * 10.0 ** f
+    info = dict(frame.info or {})
+    info["weight_decades"] = decades
+    return Frame(frame.points, frame.normals, _f32(w), frame.dims, frame.bbox,
+                 name=frame.name + f"_w{decades:g}dec", info=info)

@@ -64,6 +64,10 @@ typedef enum {
     FVR_E_DEVICE = -5       /* a HIP runtime error */
 } fvr_status;
 
+/* Largest point count of one frame: (2^31 - 1) / 3, so that every
+ * coordinate index 3 i fits a 32-bit integer in the kernels. */
+#define FVR_MAX_POINTS 715827882LL
+
 /* fvr_mesh.flags bits */
 #define FVR_FLAG_OPEN_SURFACE 1u /* a voxel on the grid's outer layer is inside:
                                     the bbox was not padded enough */
@@ -76,7 +80,7 @@ typedef struct {
     const float *points;  /* M x 3, world units */
     const float *normals; /* M x 3 (used as given; not renormalised) */
     const float *weights; /* M, >= 0; NULL means every weight is 1 */
-    int64_t n_points;     /* M >= 0 */
+    int64_t n_points;     /* 0 <= M <= FVR_MAX_POINTS, else FVR_E_INVALID */
     int32_t dims[3];      /* Nx, Ny, Nz: each even, 8..512, 2^a 3^b 5^c */
     float bbox[6];        /* xmin, ymin, zmin, xmax, ymax, zmax (max > min) */
 } fvr_frame;
@@ -129,6 +133,11 @@ fvr_status fvr_debug_splat(fvr_ctx *ctx, const fvr_frame *frame, float *v_out);
 /* Host-only helpers (no device work; callable without a GPU). */
 /* Check dims and bbox as fvr_reconstruct would. */
 fvr_status fvr_check_grid(const int32_t dims[3], const float bbox[6]);
+/* Check a frame's host-side fields as fvr_reconstruct does before any
+ * launch: point count (0..FVR_MAX_POINTS), the required pointers, grid and
+ * bbox.  The device arrays are not read (their values are checked on the
+ * device during a reconstruction). */
+fvr_status fvr_check_frame(const fvr_frame *frame);
 /* Copy the library's generated marching-cubes table: counts[256] triangles
  * per case and edges[256 * 15] cube-edge ids (-1 padded), cube edge
  * id = 4 axis + b_lo + 2 b_hi. */

@@ -22,7 +22,7 @@ from collections import namedtuple
 
 __all__ = [
     "FvrError", "FvrUnavailable", "Context", "PreparedFrame", "Mesh", "reconstruct", "indicator",
-    "extract", "debug_splat", "mc_table", "check_grid", "library_path", "load_library",
+    "extract", "debug_splat", "mc_table", "check_grid", "check_frame", "library_path", "load_library",
     "STATUS",
 ]
 
@@ -86,6 +86,7 @@ def load_library():
                                 ctypes.c_float, ctypes.POINTER(_Mesh), P]
     lib.fvr_debug_splat.argtypes = [P, ctypes.POINTER(_Frame), P]
     lib.fvr_check_grid.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+    lib.fvr_check_frame.argtypes = [ctypes.POINTER(_Frame)]
     lib.fvr_mc_table.argtypes = [P, P]
     lib.fvr_timing_enable.argtypes = [P, I]
     lib.fvr_timing_select.argtypes = [P, ctypes.c_uint32]
@@ -99,7 +100,7 @@ def load_library():
     lib.fvr_last_error.argtypes = [P]
     lib.fvr_last_error.restype = ctypes.c_char_p
     for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_indicator", "fvr_extract",
-               "fvr_debug_splat", "fvr_check_grid", "fvr_mc_table", "fvr_timing_enable",
+               "fvr_debug_splat", "fvr_check_grid", "fvr_check_frame", "fvr_mc_table", "fvr_timing_enable",
                "fvr_timing_select", "fvr_timing_reset", "fvr_timing_get"):
         getattr(lib, fn).restype = I
     _lib = lib
@@ -118,6 +119,19 @@ def check_grid(dims, bbox) -> int:
     d = (ctypes.c_int32 * 3)(*[int(x) for x in dims])
     b = (ctypes.c_float * 6)(*[float(x) for x in bbox])
     return int(lib.fvr_check_grid(d, b))
+
+
+def check_frame(n_points, grid_dim, bbox, points_ptr=1, normals_ptr=1, weights_ptr=0) -> int:
+    """Host-only validation of a frame's host-side fields (point count,
+    required pointers, grid, bbox) as ``fvr_reconstruct`` does before any
+    launch; the pointers are not dereferenced.  Returns the fvr_status code."""
+    lib = load_library()
+    f = _Frame()
+    f.points, f.normals, f.weights = points_ptr or None, normals_ptr or None, weights_ptr or None
+    f.n_points = int(n_points)
+    f.dims = (ctypes.c_int32 * 3)(*[int(x) for x in grid_dim])
+    f.bbox = (ctypes.c_float * 6)(*[float(x) for x in bbox])
+    return int(lib.fvr_check_frame(ctypes.byref(f)))
 
 
 def mc_table():

@@ -263,14 +263,20 @@ fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan
     return FVR_OK;
 }
 
-fvr_status check_frame(fvr_ctx *c, const fvr_frame *f) {
-    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+// The frame's host-side fields: point count, required pointers, grid, bbox.
+fvr_status check_frame_fields(fvr_ctx *c, const fvr_frame *f) {
     if (!f) return fail(c, FVR_E_INVALID, "frame is NULL");
     if (f->n_points < 0) return fail(c, FVR_E_INVALID, "n_points < 0");
-    if (f->n_points > 0x7fffffff) return fail(c, FVR_E_INVALID, "n_points above 2^31 - 1");
+    // the kernels index coordinates as 3 i in 32-bit integers
+    if (f->n_points > FVR_MAX_POINTS) return fail(c, FVR_E_INVALID, "n_points above FVR_MAX_POINTS");
     if (f->n_points > 0 && (!f->points || !f->normals))
         return fail(c, FVR_E_INVALID, "points or normals is NULL");
     return check_grid(c, f->dims, f->bbox);
+}
+
+fvr_status check_frame(fvr_ctx *c, const fvr_frame *f) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    return check_frame_fields(c, f);
 }
 
 // Stages 1-4 (and optionally 5): status reset, binning, splat + x FFT and,
@@ -314,7 +320,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
               "tile_list"); }
     { Timed t(c, K_BIN_SCATTER);
       HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, g, P<int32_t>(c->key),
-                                    P<int32_t>(c->rank), P<int32_t>(c->bin_off), P<float4>(c->rec), s),
+                                    P<int32_t>(c->rank), P<int32_t>(c->bin_off), st, P<float4>(c->rec), s),
               "bin_scatter"); }
     { Timed t(c, K_SPLAT_FFT_X);
       HIP_TRY(c, launch_splat_fft_x(P<float4>(c->rec), P<int32_t>(c->bin_off), g, p->sc, p->ax[0],
@@ -568,6 +574,10 @@ fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
     if (c->host_status->flags & kFlagInvalid)
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
     return FVR_OK;
+}
+
+fvr_status fvr_check_frame(const fvr_frame *frame) {
+    return check_frame_fields(nullptr, frame);
 }
 
 fvr_status fvr_check_grid(const int32_t dims[3], const float bbox[6]) {

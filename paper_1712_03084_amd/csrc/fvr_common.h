@@ -105,7 +105,8 @@ hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, 
 // x footprint origin) into bin order.
 hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
                               const Grid &g, const int32_t *key, const int32_t *rank,
-                              const int32_t *bin_off, float4 *rec, hipStream_t s);
+                              const int32_t *bin_off, const DevStatus *st, float4 *rec,
+                              hipStream_t s);
 // Splat, stage 3 fused with the forward real FFT along x: each block owns
 // ty x tz full x-rows, accumulates S_x, S_y, S_z and D in LDS (64-bit fixed
 // point, scaled per frame from st->wmax_bits / wnmax_bits), forms

@@ -32,6 +32,7 @@ constexpr int kSplatThreads = 512;
 constexpr int kSplatMaxPlane = 2048;  // voxels per channel plane of a tile, at most
 constexpr int kMaxBins = 128;   // (ty+3)(tz+3) footprint-origin bins per tile, at most
 constexpr int kChunkPts = 8;    // consecutive points of a bin per splat work item
+constexpr int kUnitBits = 48;   // a term is below 2^48 units; a run of kChunkPts below 2^51
 
 // Footprint origin floor((x - bmin)/h - 1/2) in float32, each operation
 // correctly rounded (no contraction), so every implementation that follows
@@ -40,15 +41,43 @@ __device__ __forceinline__ float voxel_coord(float x, float bmin, float h) {
     return __fsub_rn(__fdiv_rn(__fsub_rn(x, bmin), h), 0.5f);
 }
 
-// Nearest integer of a fixed-point term (|x| < 2^30), ties upward, in one
-// instruction (v_cvt_rpi_i32_f32 = floor(x + 1/2)); a correctly rounded
-// conversion takes a separate round-to-even first, and the accumulation loop
-// is bound by its vector instruction count.  The error stays within half a
-// unit per term (one unit if the hardware rounded the sum x + 1/2).
-__device__ __forceinline__ int round_units(float x) {
-    int r;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
+// Exact, order-independent fixed-point accumulation in f64 registers.
+// A run accumulator holds kBias + x, where x is an integer count of the
+// tile's unit.  A run adds at most kChunkPts = 8 terms t with |t| < 2^48
+// units, so before each addition |x| <= 7 * 2^48 and |x + t| < 2^51: the
+// exact value kBias + x + t lies in [2^52, 2^53], where the representable
+// doubles are exactly the integers.  A term t = g s is added with one fused
+// multiply-add, which rounds kBias + x + t once to the nearest integer.  The
+// factor s is given an odd 53-bit significand (lowest bit set: a relative
+// change of 2^-53): g = a 2^i, s = b 2^j with a, b odd and b >= 2^52, so if
+// t = ab 2^(i+j) were an odd multiple of 1/2, i + j = -1 and |t| >= 2^51.
+// For |t| < 2^48 the sum is therefore never halfway between two integers:
+// the result is kBias + x + nearest(t) whatever x is.  Every
+// term is therefore rounded on its own, and the sums are exact integers,
+// independent of the order of the points (bit-reproducible).
+constexpr double kBias = 6755399441055744.0;  // 1.5 * 2^52
+constexpr int kBiasHi = 0x43380000;           // high word of kBias; its low word is 0
+
+__device__ __forceinline__ double odd_significand(double x) {
+    return __hiloint2double(__double2hiint(x), __double2loint(x) | 1);
+}
+
+// The integer x of a run accumulator kBias + x as a two's-complement int64:
+// the low words agree, and the high word differs by kBias's alone.
+__device__ __forceinline__ unsigned long long run_value(double a) {
+    const unsigned lo = (unsigned)__double2loint(a);
+    const unsigned hi = (unsigned)(__double2hiint(a) - kBiasHi);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Exponent e of the frame's fixed-point scale for a maximum mx >= 0:
+// mx < (1 - 2^-10) 2^e.  A term's Gaussian factors are products of rounded
+// exponentials (a few float32 ulps above 1 at most), so the headroom keeps
+// every term below 2^E_t units.
+__device__ __forceinline__ int unit_exp(float mx) {
+    int e;
+    const float fr = frexpf(mx, &e);
+    return fr >= 1.0f - 0x1p-10f ? e + 1 : e;
 }
 
 __device__ __forceinline__ bool finite3(float a, float b, float c) {
@@ -183,41 +212,57 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
 }
 
 // Record of a binned point: (f_x, f_y, f_z, W), (W N_x, W N_y, W N_z, i0_x),
-// with v = (X - bmin)/h - 1/2 the voxel-centre coordinate (float32 formula
-// above), i0 = floor(v) the footprint origin and f = v - i0 in [0, 1).  The
-// (i0_y, i0_z) pair is the record's bin; i0_x travels as integer bits.
+// W and W N_c in the frame's fixed-point scale (below 2^kUnitBits),
+// with i0 = floor(v) the footprint origin chosen by the float32 formula for
+// v = (X - bmin)/h - 1/2 above, and f = v - i0 the point's offset from that
+// origin's centre in voxels, evaluated in f64 (h = (bmax - bmin)/N in f64)
+// and rounded once to float32.  A float32 v carries an absolute error of up
+// to 2^-16 voxels at N = 512, which the Gaussians would turn into relative
+// errors of order 1e-5 in V; the f64 offset keeps only float32's own relative
+// rounding of f.  The (i0_y, i0_z) pair is the record's bin; i0_x travels as
+// integer bits.
 __global__ void __launch_bounds__(256)
 bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
                    const float *__restrict__ w, int m, Grid g, const int32_t *__restrict__ key,
                    const int32_t *__restrict__ rank, const int32_t *__restrict__ bin_off,
-                   float4 *__restrict__ rec) {
+                   const DevStatus *__restrict__ st, float4 *__restrict__ rec) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const int k = key[i];
     if (k < 0) return;
     const int pos = bin_off[k] + rank[i];
+    // W and W N_c in the frame's fixed-point scale: the largest becomes
+    // < 2^kUnitBits (ldexp scales exactly, whatever the exponent)
+    const int sw = kUnitBits - unit_exp(__uint_as_float(st->wmax_bits));
+    const int sn = kUnitBits - unit_exp(__uint_as_float(st->wnmax_bits));
     const float wi = w ? w[i] : 1.0f;
     float f[3];
     int ix = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float v = voxel_coord(pts[3 * i + a], g.bmin[a], g.h[a]);
-        const float fl = floorf(v);
-        f[a] = v - fl;
+        const float x = pts[3 * i + a];
+        const float fl = floorf(voxel_coord(x, g.bmin[a], g.h[a]));
+        const double h64 = ((double)g.bmax[a] - (double)g.bmin[a]) / (double)g.n[a];
+        f[a] = (float)(((double)x - (double)g.bmin[a]) / h64 - 0.5 - (double)fl);
         if (a == 0) ix = (int)fl;
     }
-    rec[2 * pos] = make_float4(f[0], f[1], f[2], wi);
-    rec[2 * pos + 1] = make_float4(wi * nrm[3 * i], wi * nrm[3 * i + 1], wi * nrm[3 * i + 2],
-                                   __int_as_float(ix));
+    rec[2 * pos] = make_float4(f[0], f[1], f[2], ldexpf(wi, sw));
+    rec[2 * pos + 1] = make_float4(ldexpf(wi * nrm[3 * i], sn), ldexpf(wi * nrm[3 * i + 1], sn),
+                                   ldexpf(wi * nrm[3 * i + 2], sn), __int_as_float(ix));
 }
 
 // Accumulation is in 64-bit fixed point with integer LDS atomics (gfx950's
-// LDS float atomics run ~30x slower than its integer ones).  Every term
-// g W N_c (or g W for D) is rounded to an int32 count of a power-of-two unit
-// chosen per frame from the largest |W N_c| (or W), so |term| < 2^30 units
-// and an int64 voxel sum cannot overflow for fewer than 2^31 points.  The sums
-// are exact, hence independent of the order of the additions: the splat is
-// bit-reproducible.  V = (sigma2/sigma1) (S unit_S) / (D unit_D).
+// LDS float atomics run ~30x slower than its integer ones, and integer sums
+// do not depend on the order of the additions).  The unit of a tile is
+// 2^(e - E_t), where (1 - 2^-10) 2^e bounds the frame's largest |W N_c| (or
+// W) and
+// E_t = min(48, 62 - ceil(log2 N_t)) for the N_t points of the tile's bins:
+// every term is below 2^E_t units, a run of at most kChunkPts terms below
+// 2^51, and no voxel sum can exceed 2^62.  Each term is rounded to the unit
+// on its own (f64 run sums above), so a term's error is at most half a unit,
+// 2^-49 of the frame's largest term while N_t <= 2^14.  The sums are exact, hence independent
+// of the order of the additions: the splat is bit-reproducible.
+// V = (sigma2/sigma1) (S unit_S) / (D unit_D); the tile's 2^E_t cancels.
 // Work decomposition: the candidate points of a tile come in bins of equal
 // footprint origin (i0_y, i0_z), and all points of one bin reach the same
 // in-tile rows.  The block enumerates (bin, chunk of up to kChunkPts
@@ -225,7 +270,7 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
 // point an item spends 6 exponentials on its 4 x-voxels of the row: the
 // (y, z) factor of each Gaussian and, per Gaussian, the x factor at the first
 // centre and its ratio to the next (the later x factors follow by products).
-__global__ void __launch_bounds__(kSplatThreads)
+__global__ void __launch_bounds__(kSplatThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
                    SplatConsts sc, FftAxis ax, DevStatus *__restrict__ st,
                    const int32_t *__restrict__ list, float2 *__restrict__ spec,
@@ -236,7 +281,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     __shared__ int b_qy[kMaxBins], b_qz[kMaxBins], b_iy[kMaxBins], b_iz[kMaxBins];
     __shared__ unsigned b_mrows[kMaxBins], b_mny[kMaxBins];
 
-    __shared__ int s_tile;
+    __shared__ int s_tile, s_npts;
     const int Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
     const int TY = sc.ty, TZ = sc.tz, R = TY * TZ;
     const int nbusy = st->n_busy;
@@ -252,11 +297,10 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     const size_t pl = (size_t)Nz * Ny * Hp;
     float2 *twl = reinterpret_cast<float2 *>(acc + 4 * aplane);
     load_twiddles(twl, ax);
-    // fixed-point units: 2^(e-30) with max < 2^e, so every rounded term fits int32
-    int eS, eD;
-    (void)frexpf(__uint_as_float(st->wnmax_bits), &eS);
-    (void)frexpf(__uint_as_float(st->wmax_bits), &eD);
-    const float qS = ldexpf(1.0f, 30 - eS), qD = ldexpf(1.0f, 30 - eD);
+    // the records carry W and W N_c scaled by 2^(kUnitBits - e) (e from the
+    // frame maxima); a tile scales its terms by a further 2^(E_t - kUnitBits)
+    const int eS = unit_exp(__uint_as_float(st->wnmax_bits));
+    const int eD = unit_exp(__uint_as_float(st->wmax_bits));
     const float k1 = exp2f(2.0f * sc.e1[0]), k2 = exp2f(2.0f * sc.e2[0]);
 
     // Persistent blocks (one per CU) claim the busy tiles from a ticket counter.
@@ -296,23 +340,32 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     }
     __syncthreads();
     if (threadIdx.x < 64) {
-        // inclusive prefix of the bins' item counts (nbins <= 128: two per lane)
+        // inclusive prefix of the bins' item counts (nbins <= 128: two per
+        // lane), and the tile's point count N_t
         const int l = threadIdx.x;
         const int v0 = 2 * l < nbins ? b_pre[2 * l + 1] : 0;
         const int v1 = 2 * l + 1 < nbins ? b_pre[2 * l + 2] : 0;
+        int npts = (2 * l < nbins ? b_cnt[2 * l] : 0) + (2 * l + 1 < nbins ? b_cnt[2 * l + 1] : 0);
         int incl = v0 + v1;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int u = __shfl_up(incl, d, 64);
             if (l >= d) incl += u;
+            npts += __shfl_xor(npts, d, 64);
         }
         const int excl = incl - v0 - v1;
         if (2 * l < nbins) b_pre[2 * l + 1] = excl + v0;
         if (2 * l + 1 < nbins) b_pre[2 * l + 2] = excl + v0 + v1;
-        if (l == 0) b_pre[0] = 0;
+        if (l == 0) {
+            b_pre[0] = 0;
+            s_npts = npts;
+        }
     }
     __syncthreads();
     const int total = b_pre[nbins];
+    // the tile's exponent E_t: N_t terms of at most 2^E_t units stay below 2^62
+    const int e_t = min(kUnitBits, 62 - (32 - __clz(max(s_npts - 1, 0))));
+    const float qt = ldexpf(1.0f, e_t - kUnitBits);
     if (total == 0) {  // not in the busy list; kept for safety
         __syncthreads();
         continue;
@@ -380,10 +433,10 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     };
 
     // Points of one chunk that share a footprint cell (consecutive equal i0_x;
-    // capture order keeps neighbouring samples together) are summed in int64
-    // registers - exact, so the order of summation cannot matter - and reach
-    // LDS as one atomic per voxel and channel when the cell changes.
-    long long run[4][4];
+    // capture order keeps neighbouring samples together) are summed in f64
+    // run accumulators (exact integers, see odd_significand) and reach LDS as
+    // one atomic per voxel and channel when the cell changes.
+    double run[4][4];
     int run_ix = 0, run_row = 0;
     auto flush = [&]() {
         const int l = run_row * P + run_ix + 1;  // voxel x = run_ix - 1 in the padded row
@@ -391,14 +444,14 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int ox = 0; ox < 4; ++ox) {
-                atomicAdd(&acc[c * aplane + l + ox], (unsigned long long)run[ox][c]);
-                run[ox][c] = 0;
+                atomicAdd(&acc[c * aplane + l + ox], run_value(run[ox][c]));
+                run[ox][c] = kBias;
             }
     };
 #pragma unroll
     for (int ox = 0; ox < 4; ++ox)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) run[ox][c] = 0;
+        for (int c = 0; c < 4; ++c) run[ox][c] = kBias;
 
     while (j >= 0) {
         int p, len, qy, qz, iy, iz;
@@ -421,9 +474,12 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
             // offsets of this row's centre from the point, in voxels
             const float dy = r0.y + (float)(iy - qy);
             const float dz = r0.z + (float)(iz - qz);
-            const float a1 = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy + sc.e1[2] * dz * dz);
-            const float a2 = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy + sc.e2[2] * dz * dz) * (r0.w * qD);
-            const float sx = a1 * r1.x * qS, sy = a1 * r1.y * qS, sz = a1 * r1.z * qS;
+            const float a1 = __builtin_amdgcn_exp2f(sc.e1[1] * dy * dy + sc.e1[2] * dz * dz) * qt;
+            const float a2 = __builtin_amdgcn_exp2f(sc.e2[1] * dy * dy + sc.e2[2] * dz * dz) * qt;
+            const double sx = odd_significand((double)(a1 * r1.x));
+            const double sy = odd_significand((double)(a1 * r1.y));
+            const double sz = odd_significand((double)(a1 * r1.z));
+            const double sd = odd_significand((double)(a2 * r0.w));
             // x factors at the 4 centres ox - 1, offsets d = fx + 1 - ox:
             // 2^(e (d-1)^2) = 2^(e d^2) 2^(e (1 - 2d)), and that ratio gains 2^(2e) per step
             const float d0 = r0.x + 1.0f;
@@ -433,10 +489,11 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
             float h2 = __builtin_amdgcn_exp2f(sc.e2[0] * (1.0f - 2.0f * d0));
 #pragma unroll
             for (int ox = 0; ox < 4; ++ox) {
-                run[ox][0] += round_units(g1 * sx);
-                run[ox][1] += round_units(g1 * sy);
-                run[ox][2] += round_units(g1 * sz);
-                run[ox][3] += round_units(g2 * a2);
+                const double G1 = (double)g1, G2 = (double)g2;
+                run[ox][0] = fma(G1, sx, run[ox][0]);
+                run[ox][1] = fma(G1, sy, run[ox][1]);
+                run[ox][2] = fma(G1, sz, run[ox][2]);
+                run[ox][3] = fma(G2, sd, run[ox][3]);
                 if (ox < 3) {
                     g1 *= h1;
                     g2 *= h2;
@@ -452,13 +509,13 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     }
     __syncthreads();
 
-    // V = (sigma2/sigma1) (S / qS) / (D / qD), 0 where D = 0; converted in
+    // V = (sigma2/sigma1) 2^(eS - eD) S / D, 0 where D = 0; converted in
     // registers first, then written as float planes over the front of the
     // accumulator buffer (the float rows overlap int64 slots still unread by
     // other threads, hence the barrier in between)
     constexpr int kVpt = kSplatMaxPlane / kSplatThreads;
     float vv[kVpt][3];
-    const float ratio = sc.vscale * (qD / qS);
+    const float ratio = sc.vscale * ldexpf(1.0f, eS - eD);
 #pragma unroll
     for (int t = 0; t < kVpt; ++t) {
         const int l = threadIdx.x + t * blockDim.x;
@@ -567,10 +624,11 @@ hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, 
 
 hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
                               const Grid &g, const int32_t *key, const int32_t *rank,
-                              const int32_t *bin_off, float4 *rec, hipStream_t s) {
+                              const int32_t *bin_off, const DevStatus *st, float4 *rec,
+                              hipStream_t s) {
     if (m <= 0) return hipSuccess;
     bin_scatter_kernel<<<dim3((m + 255) / 256), dim3(256), 0, s>>>(pts, nrm, w, m, g, key, rank,
-                                                                   bin_off, rec);
+                                                                   bin_off, st, rec);
     return hipGetLastError();
 }
 

@@ -45,6 +45,22 @@ def test_check_grid_statuses():
     assert fvr.check_grid((64, 64, 64), (0, 0, 0, 1, float("nan"), 1)) == -1
 
 
+def test_check_frame_point_count_cap_and_pointers():
+    """A frame is refused on the host, before any launch, when its point
+    count exceeds what 32-bit coordinate indices (3 i) can address."""
+    ok = (-1, -1, -1, 1, 1, 1)
+    cap = 715827882
+    assert cap == (2 ** 31 - 1) // 3
+    assert fvr.check_frame(cap, (64, 64, 64), ok) == 0
+    assert fvr.check_frame(cap + 1, (64, 64, 64), ok) == -1
+    assert fvr.check_frame(2 ** 31, (64, 64, 64), ok) == -1
+    assert fvr.check_frame(-1, (64, 64, 64), ok) == -1
+    assert fvr.check_frame(0, (64, 64, 64), ok, points_ptr=0, normals_ptr=0) == 0
+    assert fvr.check_frame(10, (64, 64, 64), ok, points_ptr=0) == -1
+    assert fvr.check_frame(10, (64, 64, 64), ok, normals_ptr=0) == -1
+    assert fvr.check_frame(10, (14, 64, 64), ok) == -2
+
+
 def test_mc_table_identical_to_oracle_generator():
     c_gpu, e_gpu = fvr.mc_table()
     c_orc, e_orc = oracle.mc_table()

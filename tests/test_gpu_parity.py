@@ -1,13 +1,13 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 Tolerances (float32 path vs double oracle):
-  splat V        max |V_gpu - V_orc| <= 1e-4 * max |V_orc|
+  splat V        max |V_gpu - V_orc| <= 1e-5 * max |V_orc|
   indicator A    max |A_gpu - A_orc| <= 1e-4 * (max A_orc - min A_orc)   (stated target)
   level L        |L_gpu - L_orc|     <= 1e-4 * range(A_orc)
   marching cubes on the oracle's field rounded to float32 with L rounded to
                  float32: case bytes, vertex/triangle counts and triangle index
                  arrays bit-exact; vertex positions within 1e-4 h
-  end to end     symmetric vertex Hausdorff distance to the oracle mesh <= 0.05 h
+  end to end     symmetric vertex Hausdorff distance to the oracle mesh <= 0.01 h
 """
 import collections
 import math
@@ -95,7 +95,7 @@ def test_splat_parity(ctx, name, spec):
     scale = np.abs(Vo).max()
     err = np.abs(V - Vo).max()
     print(f"  max|V|={scale:.4g} max err={err:.3g} rel={err / scale:.3g}")
-    assert err <= 1e-4 * scale
+    assert err <= 1e-5 * scale
     # identical support: the footprint decision is the same float32 formula
     assert np.array_equal(np.abs(V).sum(0) > 0, np.abs(Vo).sum(0) > 0)
 
@@ -136,6 +136,50 @@ def _mc_compare(ctx, Ao, Lo, dims, bbox):
     print(f"  V={len(vo)} T={len(to)} max vertex err / h = {dv / h}")
     assert np.all(dv <= 1e-4 * h)
     return mesh
+
+
+def _splat_and_indicator_errors(ctx, f):
+    dev = _frame_dev(f)
+    V = ctx.debug_splat(*dev, grid_dim=f.dims, bbox=f.bbox).cpu().numpy()
+    A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
+    Vo, _, _, _ = oracle.splat(f.points, f.normals, f.weights, f.dims, f.bbox)
+    Ao = oracle.indicator(Vo, f.dims, f.bbox)
+    Lo, _ = oracle.level(Ao, f.points, f.dims, f.bbox)
+    ev = np.abs(V - Vo).max() / np.abs(Vo).max()
+    rng_ = Ao.max() - Ao.min()
+    ea = np.abs(A.cpu().numpy() - Ao).max() / rng_
+    el = abs(L - Lo) / rng_
+    support = np.array_equal(np.abs(V).sum(0) > 0, np.abs(Vo).sum(0) > 0)
+    return ev, ea, el, support
+
+
+@pytest.mark.parametrize("weights,bar", [((0.01, 100.0), 1e-5), ((1e-4, 1.0, 100.0), 1e-4)])
+def test_splat_isolated_points_with_a_wide_weight_range(ctx, weights, bar):
+    """Light points far from heavy ones (W = W1 W2 reaches 0 at silhouettes,
+    Sec. III-A): a voxel that only a light point reaches keeps a relative
+    accuracy set by the weight ratio R, not lost to the frame's largest
+    weight.  The splat's fixed-point bound is 2^-47 R e^(32/3) of max |V|
+    (2.9e-5 at R = 1e4, 3e-4 at R = 1e6, where the far footprint corner of a
+    light point is all a voxel holds); the bar is 1e-5 at R = 1e4 and 1e-4
+    at R = 1e6."""
+    f = synth.isolated_weights_frame(weights, grid=32, seed=3, pairs=9)
+    ev, ea, el, support = _splat_and_indicator_errors(ctx, f)
+    print(f"[wide W {weights}] V rel={ev:.3g} A rel={ea:.3g} L rel={el:.3g}", flush=True)
+    assert ev <= bar
+    assert ea <= 1e-5 and el <= 1e-5
+    assert support
+
+
+def test_splat_proxy128_with_weights_over_four_decades(ctx):
+    """The 4-view human proxy at 128^3 with every weight multiplied by a
+    seeded 10^U(-2, 2): overlapping footprints mix terms 10^4 apart."""
+    f = synth.spread_weights(synth.config_frame("proxy128"), decades=4.0, seed=7)
+    assert f.weights.max() / f.weights[f.weights > 0].min() > 1e4
+    ev, ea, el, support = _splat_and_indicator_errors(ctx, f)
+    print(f"[proxy128 W x 10^U(-2,2)] V rel={ev:.3g} A rel={ea:.3g} L rel={el:.3g}", flush=True)
+    assert ev <= 1e-5
+    assert ea <= 1e-5 and el <= 1e-5
+    assert support
 
 
 def test_marching_cubes_bit_exact_on_oracle_field_sphere(ctx):
@@ -186,7 +230,7 @@ def test_reconstruct_sphere_end_to_end(ctx):
     hd = _hausdorff(v, r["verts"])
     print(f"  V={len(v)} (oracle {len(r['verts'])}) T={len(t)} Hausdorff/h={hd / h:.3g} "
           f"L={mesh.level:.8g} Lo={r['level']:.8g}")
-    assert hd <= 0.05 * h
+    assert hd <= 0.01 * h
     assert np.max(np.abs(np.linalg.norm(v, axis=1) - 0.8)) <= h
     ok, ne = _closed(t)
     assert ok and len(v) - ne + len(t) == 2
@@ -213,7 +257,7 @@ def test_full_size_human_proxy_256(ctx):
     assert err <= 1e-4 * rng_
     assert abs(L - r["level"]) <= 1e-4 * rng_
     assert abs(mesh.level - r["level"]) <= 1e-4 * rng_
-    assert hd <= 0.05 * h
+    assert hd <= 0.01 * h
     assert abs(mesh.vertices.shape[0] - len(r["verts"])) <= 0.001 * len(r["verts"])
     ok, _ = _closed(mesh.triangles.cpu().numpy())
     assert ok

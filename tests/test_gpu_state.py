@@ -99,7 +99,7 @@ def test_proxy128_end_to_end(ctx):
           f"Hausdorff/h={hd / h:.3g}", flush=True)
     assert err <= 1e-4 * rng_
     assert abs(L - r["level"]) <= 1e-4 * rng_
-    assert hd <= 0.05 * h
+    assert hd <= 0.01 * h
     assert abs(mesh.vertices.shape[0] - len(r["verts"])) <= 0.001 * len(r["verts"])
 
 

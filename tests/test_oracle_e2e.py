@@ -65,3 +65,31 @@ def test_human_proxy_vertices_near_analytic_surface():
     ok, _ = _closed_manifold(r["tris"])
     assert ok
     assert not r["open_surface"]
+
+
+def test_open_surface_flag_definition():
+    """oracle.open_surface against its definition (Sec. III-B: the bbox must
+    be extended enough that the surface closes inside it): True iff some
+    voxel of the grid's outer layer has A > L, checked on each face, an
+    edge, a corner, an interior voxel and a tie."""
+    shape = (5, 6, 7)  # (Nz, Ny, Nx)
+    L = 0.5
+    A = np.zeros(shape)
+    assert oracle.open_surface(A, L) is False
+    interior = A.copy()
+    interior[2, 3, 3] = 1.0
+    assert oracle.open_surface(interior, L) is False
+    on_border = [(0, 2, 3), (4, 2, 3), (2, 0, 3), (2, 5, 3), (2, 2, 0), (2, 2, 6),
+                 (0, 0, 3), (4, 5, 6)]
+    for idx in on_border:
+        B = A.copy()
+        B[idx] = 1.0
+        assert oracle.open_surface(B, L) is True, idx
+    tie = A.copy()
+    tie[0, 0, 0] = L  # inside means A > L strictly
+    assert oracle.open_surface(tie, L) is False
+    # a ball field: closed when it fits the box, open when the box cuts it
+    z, y, x = np.meshgrid(*[np.linspace(-1, 1, 9)] * 3, indexing="ij")
+    r = np.sqrt(x * x + y * y + z * z)
+    assert oracle.open_surface(0.6 - r, 0.0) is False
+    assert oracle.open_surface(1.1 - r, 0.0) is True

@@ -111,6 +111,27 @@ fvr_status fvr_set_stream(fvr_ctx *ctx, void *hip_stream);
  * required n_vertices / n_triangles and writes nothing else. */
 fvr_status fvr_reconstruct(fvr_ctx *ctx, const fvr_frame *frame, fvr_mesh *mesh);
 
+/* Size of the static device scratch of fvr_reconstruct_noalloc: one array
+ * per GPU the library runs on, held until the process ends.  It holds a
+ * 128^3 frame of up to about a million points (with the triangle capacity
+ * of its mesh); 96^3 and smaller grids hold several million. */
+#define FVR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* fvr_reconstruct for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with every scratch buffer
+ * carved from the device's static array of FVR_NOALLOC_SCRATCH_BYTES
+ * instead of the context's own memory, and no hipMalloc, hipFree or other
+ * allocation in the call (the context, made beforehand by fvr_create, owns
+ * the stream and the pinned status block).  The caller passes the inputs
+ * and the mesh outputs as for fvr_reconstruct.  A frame whose scratch does
+ * not fit is refused with FVR_E_NOMEM before anything is enqueued.  Per-kernel
+ * timing is not recorded in this call.  All calls on one GPU, from every
+ * context, share that GPU's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other threads, other streams) race and
+ * must be serialised by the caller. */
+fvr_status fvr_reconstruct_noalloc(fvr_ctx *ctx, const fvr_frame *frame, fvr_mesh *mesh);
+
 /* Steps 1-5 only: the indicator A (Nz x Ny x Nx floats, device) and L.
  * Same kernels as fvr_reconstruct. */
 fvr_status fvr_indicator(fvr_ctx *ctx, const fvr_frame *frame, float *field_out,

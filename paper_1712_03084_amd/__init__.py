@@ -81,6 +81,7 @@ def load_library():
     lib.fvr_destroy.restype = None
     lib.fvr_set_stream.argtypes = [P, P]
     lib.fvr_reconstruct.argtypes = [P, ctypes.POINTER(_Frame), ctypes.POINTER(_Mesh)]
+    lib.fvr_reconstruct_noalloc.argtypes = [P, ctypes.POINTER(_Frame), ctypes.POINTER(_Mesh)]
     lib.fvr_indicator.argtypes = [P, ctypes.POINTER(_Frame), P, ctypes.POINTER(ctypes.c_double)]
     lib.fvr_extract.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
                                 ctypes.c_float, ctypes.POINTER(_Mesh), P]
@@ -99,7 +100,8 @@ def load_library():
     lib.fvr_status_string.restype = ctypes.c_char_p
     lib.fvr_last_error.argtypes = [P]
     lib.fvr_last_error.restype = ctypes.c_char_p
-    for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_indicator", "fvr_extract",
+    for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_reconstruct_noalloc",
+               "fvr_indicator", "fvr_extract",
                "fvr_debug_splat", "fvr_check_grid", "fvr_check_frame", "fvr_mc_table", "fvr_timing_enable",
                "fvr_timing_select", "fvr_timing_reset", "fvr_timing_get"):
         getattr(lib, fn).restype = I
@@ -297,6 +299,28 @@ class Context:
         return self._run_mesh(lambda m: self.lib.fvr_reconstruct(self.handle, ctypes.byref(f),
                                                                  ctypes.byref(m)),
                               dims, out, vertex_capacity, triangle_capacity)
+
+    def reconstruct_noalloc(self, points, normals, weights=None, grid_dim=(128, 128, 128),
+                            bbox=((-1, -1, -1), (1, 1, 1)), out=None) -> Mesh:
+        """``reconstruct`` through ``fvr_reconstruct_noalloc``: the library
+        allocates no device memory in the call (its scratch is the device's
+        static array of FVR_NOALLOC_SCRATCH_BYTES).  ``out`` = (verts, tris)
+        is required; a capacity shortfall or a frame beyond the static
+        scratch raises FvrError."""
+        if out is None:
+            raise ValueError("reconstruct_noalloc needs preallocated out=(vertices, triangles)")
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        self._stream()
+        verts, tris = out
+        m = _Mesh()
+        m.vertices = verts.data_ptr()
+        m.triangles = tris.data_ptr()
+        m.vertex_capacity = verts.shape[0]
+        m.triangle_capacity = tris.shape[0]
+        _check(self.lib, self.lib.fvr_reconstruct_noalloc(self.handle, ctypes.byref(f), ctypes.byref(m)),
+               self.handle)
+        return Mesh(verts[:m.n_vertices], tris[:m.n_triangles], m.level, int(m.n_rejected),
+                    bool(m.flags & FVR_FLAG_OPEN_SURFACE))
 
     def prepare(self, points, normals, weights=None, grid_dim=(128, 128, 128),
                 bbox=((-1, -1, -1), (1, 1, 1)), out=None, vertex_capacity=None,

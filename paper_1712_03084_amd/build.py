@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfvr.so")
 
-SOURCES = ["fvr_api.cpp", "fvr_mc_table.cpp", "fvr_splat.hip", "fvr_fft.hip", "fvr_mc.hip"]
+SOURCES = ["fvr_api.cpp", "fvr_mc_table.cpp", "fvr_splat.hip", "fvr_fft.hip", "fvr_mc.hip",
+           "fvr_static.hip"]
 ARCH = "gfx950"
 
 

@@ -38,29 +38,40 @@ const char *kKernelNames[K_COUNT] = {
 
 thread_local std::string g_error;
 
+// A scratch buffer of the context: memory it owns (p, cap, grown on demand),
+// or, during an allocation-free call, a slice of the device's static scratch
+// array; `view` is the memory the current call uses.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    void *view = nullptr;
+    uint64_t epoch = 0;  // allocation-free call that carved `view` (0: owned memory)
+    size_t bytes = 0;    // size of that slice
 };
 
 struct Plan {
     int dims[3];
     FftAxis ax[3];
-    float2 *tw = nullptr;
     SplatConsts sc;
 };
 
-// Radix schedule: as many 8s as possible, then a 4 or 2, then 3s and 5s.
-bool factor(int n, std::vector<int> &rad) {
-    rad.clear();
+// Radix schedule: as many 8s as possible, then a 4 or 2, then 3s and 5s
+// (at most kMaxStages; false if n has another factor or needs more stages).
+bool factor(int n, int rad[kMaxStages], int &ns) {
+    ns = 0;
     int a = 0;
     while (n % 2 == 0) { n /= 2; ++a; }
-    while (a >= 3) { rad.push_back(8); a -= 3; }
-    if (a == 2) rad.push_back(4);
-    if (a == 1) rad.push_back(2);
-    while (n % 3 == 0) { n /= 3; rad.push_back(3); }
-    while (n % 5 == 0) { n /= 5; rad.push_back(5); }
-    return n == 1 && (int)rad.size() <= kMaxStages;
+    auto push = [&](int r) {
+        if (ns == kMaxStages) return false;
+        rad[ns++] = r;
+        return true;
+    };
+    while (a >= 3) { if (!push(8)) return false; a -= 3; }
+    if (a == 2 && !push(4)) return false;
+    if (a == 1 && !push(2)) return false;
+    while (n % 3 == 0) { n /= 3; if (!push(3)) return false; }
+    while (n % 5 == 0) { n /= 5; if (!push(5)) return false; }
+    return n == 1;
 }
 
 }  // namespace
@@ -70,6 +81,10 @@ struct fvr_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     std::map<std::array<int, 3>, Plan> plans;
+    // allocation-free calls carve their buffers from the static scratch
+    unsigned char *arena = nullptr;  // non-null during such a call
+    size_t arena_off = 0;
+    uint64_t arena_epoch = 0;
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
         lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm, mc_list;
     DevStatus *host_status = nullptr;
@@ -111,7 +126,30 @@ hipError_t ensure(DevBuf &b, size_t bytes) {
     return e;
 }
 
-template <class T> T *P(DevBuf &b) { return static_cast<T *>(b.p); }
+// Makes `bytes` of buffer b available to the current call: the context's
+// own memory (grown with hipMalloc), or, in an allocation-free call, a
+// 256-byte aligned slice of the static scratch (the same slice when the
+// buffer is asked for again within the call).  Overflowing the static
+// scratch reports hipErrorOutOfMemory without allocating.
+hipError_t get(fvr_ctx *c, DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (!c->arena) {
+        hipError_t e = ensure(b, bytes);
+        if (e == hipSuccess) b.view = b.p;
+        b.epoch = 0;
+        return e;
+    }
+    if (b.epoch == c->arena_epoch && b.bytes >= bytes) return hipSuccess;
+    const size_t off = (c->arena_off + 255) & ~(size_t)255;
+    if (off > FVR_NOALLOC_SCRATCH_BYTES || bytes > FVR_NOALLOC_SCRATCH_BYTES - off) return hipErrorOutOfMemory;
+    b.view = c->arena + off;
+    b.epoch = c->arena_epoch;
+    b.bytes = bytes;
+    c->arena_off = off + bytes;
+    return hipSuccess;
+}
+
+template <class T> T *P(DevBuf &b) { return static_cast<T *>(b.view); }
 
 // RAII launch timer: records a HIP event before and after the launch when
 // timing is on; the pairs are read after the next synchronisation.
@@ -165,8 +203,8 @@ fvr_status check_grid(fvr_ctx *c, const int32_t dims[3], const float bbox[6]) {
         const int n = dims[a];
         if (n < 8 || (n & 1)) return fail(c, FVR_E_INVALID, "grid dims must be even and >= 8");
         if (n > kMaxDim) return fail(c, FVR_E_UNSUPPORTED, "grid dim above 512");
-        std::vector<int> r;
-        if (!factor(n, r)) return fail(c, FVR_E_UNSUPPORTED, "grid dim must be 2^a 3^b 5^c");
+        int r[kMaxStages], ns;
+        if (!factor(n, r, ns)) return fail(c, FVR_E_UNSUPPORTED, "grid dim must be 2^a 3^b 5^c");
         if (!std::isfinite(bbox[a]) || !std::isfinite(bbox[a + 3]) || !(bbox[a + 3] > bbox[a]))
             return fail(c, FVR_E_INVALID, "bbox must be finite with max > min");
         const float h = (bbox[a + 3] - bbox[a]) / (float)n;
@@ -208,45 +246,33 @@ Grid make_grid(const int32_t dims[3], const float bbox[6]) {
     return g;
 }
 
-fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan **out) {
-    const std::array<int, 3> key = {dims[0], dims[1], dims[2]};
-    auto it = c->plans.find(key);
-    Plan *p;
-    if (it == c->plans.end()) {
-        Plan np;
-        std::memcpy(np.dims, dims, sizeof(np.dims));
-        std::vector<float2> tab;
-        std::vector<size_t> offs;
-        for (int a = 0; a < 3; ++a) {
-            std::vector<int> r;
-            factor(dims[a], r);
-            np.ax[a].n = dims[a];
-            np.ax[a].nstages = (int)r.size();
-            np.ax[a].radices = 0;
-            for (int s = 0; s < (int)r.size(); ++s) np.ax[a].radices |= (unsigned)r[s] << (4 * s);
-            offs.push_back(tab.size());
-            for (int t = 0; t < dims[a]; ++t) {
-                const double ang = 2.0 * M_PI * (double)t / (double)dims[a];
-                tab.push_back(make_float2((float)std::cos(ang), (float)-std::sin(ang)));
-            }
-        }
-        HIP_TRY(c, hipMalloc(&np.tw, tab.size() * sizeof(float2)), "hipMalloc(twiddles)");
-        HIP_TRY(c, hipMemcpy(np.tw, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice),
-                "hipMemcpy(twiddles)");
-        for (int a = 0; a < 3; ++a) np.ax[a].tw = np.tw + offs[a];
-        // splat tile: ty x tz full x-rows, R = ty tz rows with R Nx within the
-        // kernel's plane bound (4 <= R <= 64; Nx <= 512 keeps 4 rows in bound)
-        const int nx = dims[0];
-        int R = 64;
-        while (R > 4 && R * nx > splat_max_plane()) R /= 2;
-        np.sc.tz = R >= 64 ? 8 : R >= 32 ? 8 : R >= 16 ? 4 : R >= 8 ? 4 : 2;
-        np.sc.ty = R / np.sc.tz;
-        np.sc.tiles_y = (dims[1] + np.sc.ty - 1) / np.sc.ty;
-        p = &(c->plans[key] = np);
-    } else {
-        p = &it->second;
+// Radix schedules, twiddles (the device's static table: nothing to allocate)
+// and splat tiling of a grid shape.
+fvr_status build_plan(fvr_ctx *c, const int32_t dims[3], Plan &np) {
+    std::memcpy(np.dims, dims, sizeof(np.dims));
+    for (int a = 0; a < 3; ++a) {
+        int r[kMaxStages], ns;
+        if (!factor(dims[a], r, ns)) return fail(c, FVR_E_UNSUPPORTED, "grid dim must be 2^a 3^b 5^c");
+        np.ax[a].n = dims[a];
+        np.ax[a].nstages = ns;
+        np.ax[a].radices = 0;
+        for (int k = 0; k < ns; ++k) np.ax[a].radices |= (unsigned)r[k] << (4 * k);
+        np.ax[a].tw = statics_twiddles(c->device, dims[a]);
+        if (!np.ax[a].tw) return fail(c, FVR_E_DEVICE, "twiddle table missing for this length");
     }
-    // geometry-dependent splat constants (bbox may change between calls)
+    // splat tile: ty x tz full x-rows, R = ty tz rows with R Nx within the
+    // kernel's plane bound (4 <= R <= 64; Nx <= 512 keeps 4 rows in bound)
+    const int nx = dims[0];
+    int R = 64;
+    while (R > 4 && R * nx > splat_max_plane()) R /= 2;
+    np.sc.tz = R >= 64 ? 8 : R >= 32 ? 8 : R >= 16 ? 4 : R >= 8 ? 4 : 2;
+    np.sc.ty = R / np.sc.tz;
+    np.sc.tiles_y = (dims[1] + np.sc.ty - 1) / np.sc.ty;
+    return FVR_OK;
+}
+
+// Geometry-dependent splat constants (the bbox may change between calls).
+void plan_geometry(Plan *p, const int32_t dims[3], const float bbox[6]) {
     double h[3], s1sq = 0.0;
     for (int a = 0; a < 3; ++a) {
         h[a] = ((double)bbox[a + 3] - (double)bbox[a]) / (double)dims[a];
@@ -259,6 +285,21 @@ fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan
         p->sc.e2[a] = (float)(-h[a] * h[a] / s2sq * log2e);
     }
     p->sc.vscale = (float)std::sqrt(1.5);
+}
+
+fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan **out) {
+    const std::array<int, 3> key = {dims[0], dims[1], dims[2]};
+    auto it = c->plans.find(key);
+    Plan *p;
+    if (it == c->plans.end()) {
+        Plan np;
+        fvr_status r = build_plan(c, dims, np);
+        if (r != FVR_OK) return r;
+        p = &(c->plans[key] = np);
+    } else {
+        p = &it->second;
+    }
+    plan_geometry(p, dims, bbox);
     *out = p;
     return FVR_OK;
 }
@@ -279,6 +320,77 @@ fvr_status check_frame(fvr_ctx *c, const fvr_frame *f) {
     return check_frame_fields(c, f);
 }
 
+// A scratch request of the current call; in an allocation-free call a
+// request beyond the static scratch is refused with FVR_E_NOMEM.
+#define GET(c, buf, bytes, what)                                                              \
+    do {                                                                                      \
+        hipError_t e_ = get((c), (buf), (bytes));                                             \
+        if (e_ == hipErrorOutOfMemory && (c)->arena)                                          \
+            return fail((c), FVR_E_NOMEM,                                                     \
+                        std::string("the frame needs more than the FVR_NOALLOC_SCRATCH_BYTES " \
+                                    "of static scratch (at ") + (what) + ")");                \
+        if (e_ != hipSuccess) return hip_fail((c), e_, (what));                               \
+    } while (0)
+
+// Scratch of stages 1-5 (status, binning, splat, transforms) for m points.
+fvr_status field_bufs(fvr_ctx *c, const Grid &g, const Plan *p, int m) {
+    const int ntiles = p->sc.tiles_y * ((g.n[2] + p->sc.tz - 1) / p->sc.tz);
+    const int nbins = (g.n[2] + 1) * (g.n[1] + 1);
+    const size_t nspec = (size_t)g.n[2] * g.n[1] * g.Hp;
+    GET(c, c->status, sizeof(DevStatus), "status");
+    GET(c, c->bin_count, sizeof(int32_t) * nbins, "bins");
+    GET(c, c->bin_off, sizeof(int32_t) * (nbins + 1), "bin offsets");
+    GET(c, c->key, sizeof(int32_t) * (size_t)m, "keys");
+    GET(c, c->rank, sizeof(int32_t) * (size_t)m, "ranks");
+    GET(c, c->rec, sizeof(float4) * 2 * (size_t)m, "records");
+    GET(c, c->spec, sizeof(float2) * 3 * nspec, "spectra");
+    GET(c, c->occ, (size_t)ntiles, "tile occupancy");
+    GET(c, c->tiles, sizeof(int32_t) * (size_t)ntiles, "tile list");
+    GET(c, c->tile_pend, sizeof(int2) * (size_t)ntiles, "tile costs");
+    GET(c, c->blk_max, sizeof(uint2) * (size_t)std::max(1, bin_count_blocks(m)), "block maxima");
+    GET(c, c->zocc, (size_t)g.n[2], "plane occupancy");
+    // sized for both scans of the frame before anything is enqueued
+    const int scan_items = std::max(bin_scan_tiles(nbins), 3 * scan_partials(mc_blocks(g)));
+    GET(c, c->scan_part, sizeof(int32_t) * (size_t)scan_items, "scan scratch");
+    if (fft_yx_fused(g)) GET(c, c->rowmm, sizeof(float2) * (size_t)g.n[1] * g.n[2], "row ranges");
+    return FVR_OK;
+}
+
+// Scratch of the iso-level (stage 6) for m points.
+fvr_status level_bufs(fvr_ctx *c, int m) {
+    const int nb = level_blocks(m);
+    GET(c, c->lvl_sum, sizeof(double) * (size_t)nb, "level partials");
+    GET(c, c->lvl_cnt, sizeof(int32_t) * (size_t)nb, "level counts");
+    GET(c, c->level_f32, sizeof(float), "level");
+    return FVR_OK;
+}
+
+// Marching cubes never writes more active cells than triangles (every active
+// cell emits at least one) or than the grid has cells.
+MeshCaps mesh_caps(const Grid &g, const fvr_mesh *mesh, bool check_invalid) {
+    const long long ncell_max = (long long)(g.n[0] - 1) * (g.n[1] - 1) * (g.n[2] - 1);
+    MeshCaps caps;
+    caps.vertices = mesh->vertices ? mesh->vertex_capacity : 0;
+    caps.triangles = mesh->triangles ? mesh->triangle_capacity : 0;
+    caps.cells = std::max(0LL, std::min((long long)caps.triangles, ncell_max));
+    caps.check_invalid = check_invalid ? 1 : 0;
+    return caps;
+}
+
+// Scratch of stages 7-9 (marching cubes), with the block list of the fused path.
+fvr_status mc_bufs(fvr_ctx *c, const Grid &g, const MeshCaps &caps, bool with_list) {
+    const int nb = mc_blocks(g);
+    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
+    GET(c, c->mc_cnt, sizeof(int32_t) * 3 * (size_t)nb, "mc counts");
+    GET(c, c->mc_off, sizeof(int32_t) * 3 * ((size_t)nb + 1), "mc offsets");
+    GET(c, c->vidx, sizeof(int32_t) * 3 * n, "vertex ids");
+    GET(c, c->mc_codes, (size_t)nb * 1024, "point codes");
+    GET(c, c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_partials(nb), "scan scratch");
+    if (with_list) GET(c, c->mc_list, sizeof(int32_t) * (size_t)nb, "mc block list");
+    GET(c, c->cells, sizeof(int4) * (size_t)std::max(1LL, caps.cells), "active cells");
+    return FVR_OK;
+}
+
 // Stages 1-4 (and optionally 5): status reset, binning, splat + x FFT and,
 // unless splat_only, the remaining transform passes into `field`.
 fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, float *field,
@@ -287,25 +399,10 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     g.ty = p->sc.ty;
     g.tz = p->sc.tz;
     g.tiles_y = p->sc.tiles_y;
-    const int ntiles = p->sc.tiles_y * ((g.n[2] + p->sc.tz - 1) / p->sc.tz);
     const int m = (int)f->n_points;
     const int nbins = (g.n[2] + 1) * (g.n[1] + 1);
-    const size_t nspec = (size_t)g.n[2] * g.n[1] * g.Hp;
-    HIP_TRY(c, ensure(c->bin_count, sizeof(int32_t) * nbins), "alloc bins");
-    HIP_TRY(c, ensure(c->bin_off, sizeof(int32_t) * (nbins + 1)), "alloc bin offsets");
-    HIP_TRY(c, ensure(c->key, sizeof(int32_t) * (size_t)m), "alloc keys");
-    HIP_TRY(c, ensure(c->rank, sizeof(int32_t) * (size_t)m), "alloc ranks");
-    HIP_TRY(c, ensure(c->rec, sizeof(float4) * 2 * (size_t)m), "alloc records");
-    HIP_TRY(c, ensure(c->spec, sizeof(float2) * 3 * nspec), "alloc spectra");
-    HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
-    HIP_TRY(c, ensure(c->occ, (size_t)ntiles), "alloc tile occupancy");
-    HIP_TRY(c, ensure(c->tiles, sizeof(int32_t) * (size_t)ntiles), "alloc tile list");
-    HIP_TRY(c, ensure(c->tile_pend, sizeof(int2) * (size_t)ntiles), "alloc tile costs");
-    HIP_TRY(c, ensure(c->blk_max, sizeof(uint2) * (size_t)std::max(1, bin_count_blocks(m))), "alloc block maxima");
-    HIP_TRY(c, ensure(c->zocc, (size_t)g.n[2]), "alloc plane occupancy");
-    // sized for both scans of the frame before anything is enqueued
-    const int scan_items = std::max(bin_scan_tiles(nbins), 3 * scan_partials(mc_blocks(g)));
-    HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * (size_t)scan_items), "alloc scan scratch");
+    fvr_status r = field_bufs(c, g, p, m);
+    if (r != FVR_OK) return r;
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(st, P<int32_t>(c->bin_count), nbins, s), "prep"); }
@@ -332,7 +429,6 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     { Timed t(c, K_FFT_Z_SOLVE);
       HIP_TRY(c, launch_fft_z_solve(sp, P<uint8_t>(c->zocc), g, p->ax[2], s), "fft_z_solve"); }
     if (fft_yx_fused(g)) {
-        HIP_TRY(c, ensure(c->rowmm, sizeof(float2) * (size_t)g.n[1] * g.n[2]), "alloc row ranges");
         Timed t(c, K_FFT_YX_INV);
         HIP_TRY(c, launch_fft_yx_inv(sp, field, P<float2>(c->rowmm), g, p->ax[1], s), "fft_yx_inv");
     } else {
@@ -346,10 +442,8 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
 // marching-cubes blocks to reduce (run_mc with rowmm).
 fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float *field, bool final = true) {
     const int m = (int)f->n_points;
-    const int nb = level_blocks(m);
-    HIP_TRY(c, ensure(c->lvl_sum, sizeof(double) * (size_t)nb), "alloc level partials");
-    HIP_TRY(c, ensure(c->lvl_cnt, sizeof(int32_t) * (size_t)nb), "alloc level counts");
-    HIP_TRY(c, ensure(c->level_f32, sizeof(float)), "alloc level");
+    fvr_status r = level_bufs(c, m);
+    if (r != FVR_OK) return r;
     { Timed t(c, K_LEVEL);
       HIP_TRY(c, launch_level(f->points, m, field, g, P<double>(c->lvl_sum), P<int32_t>(c->lvl_cnt),
                               P<DevStatus>(c->status), P<float>(c->level_f32), final, c->stream),
@@ -364,17 +458,13 @@ fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float 
 fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *rowmm, fvr_mesh *mesh,
                   uint8_t *cases_out, bool check_invalid, int level_nb = 0) {
     const int nb = mc_blocks(g);
-    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
-    HIP_TRY(c, ensure(c->mc_cnt, sizeof(int32_t) * 3 * (size_t)nb), "alloc mc counts");
-    HIP_TRY(c, ensure(c->mc_off, sizeof(int32_t) * 3 * ((size_t)nb + 1)), "alloc mc offsets");
-    HIP_TRY(c, ensure(c->vidx, sizeof(int32_t) * 3 * n), "alloc vertex ids");
-    HIP_TRY(c, ensure(c->mc_codes, (size_t)nb * 1024), "alloc point codes");
-    HIP_TRY(c, ensure(c->scan_part, sizeof(int32_t) * 3 * (size_t)scan_partials(nb)), "alloc scan scratch");
+    const MeshCaps caps = mesh_caps(g, mesh, check_invalid);
+    fvr_status r0 = mc_bufs(c, g, caps, rowmm != nullptr);
+    if (r0 != FVR_OK) return r0;
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     int32_t *list = nullptr;
     if (rowmm) {
-        HIP_TRY(c, ensure(c->mc_list, sizeof(int32_t) * (size_t)nb), "alloc mc block list");
         list = P<int32_t>(c->mc_list);
         Timed t(c, K_MC_CLASSIFY);
         HIP_TRY(c, launch_mc_classify(P<float>(c->level_f32), level_nb > 0 ? P<double>(c->lvl_sum) : nullptr,
@@ -394,14 +484,6 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
       } }
     // Generation follows without a host round trip: the kernels check the
     // totals against the capacities themselves and write nothing on a shortfall.
-    const long long ncell_max = (long long)(g.n[0] - 1) * (g.n[1] - 1) * (g.n[2] - 1);
-    MeshCaps caps;
-    caps.vertices = mesh->vertices ? mesh->vertex_capacity : 0;
-    caps.triangles = mesh->triangles ? mesh->triangle_capacity : 0;
-    // every active cell emits at least one triangle
-    caps.cells = std::max(0LL, std::min((long long)caps.triangles, ncell_max));
-    caps.check_invalid = check_invalid ? 1 : 0;
-    HIP_TRY(c, ensure(c->cells, sizeof(int4) * (size_t)std::max(1LL, caps.cells)), "alloc active cells");
     { Timed t(c, K_MC_GENERATE);
       HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
                                     P<int32_t>(c->mc_off), P<uint32_t>(c->mc_codes), mesh->vertices,
@@ -440,6 +522,9 @@ fvr_status fvr_create(int device, void *hip_stream, fvr_ctx **out) {
     if (device < 0 || device >= ndev) return fail(nullptr, FVR_E_INVALID, "device index out of range");
     e = hipSetDevice(device);
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    // twiddle tables and static scratch of this device (looked up once)
+    e = statics_init(device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "device statics");
     fvr_ctx *c = new fvr_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -469,7 +554,6 @@ void fvr_destroy(fvr_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (auto &kv : c->plans) (void)hipFree(kv.second.tw);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
                       &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max, &c->rowmm, &c->mc_list};
@@ -497,13 +581,60 @@ fvr_status fvr_reconstruct(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mesh) {
     Plan *p;
     if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
     const Grid g = make_grid(f->dims, f->bbox);
-    HIP_TRY(c, ensure(c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2]), "alloc field");
+    GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
     if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
     // the fused inverse pass left each row's range of A: blocks of cells
     // entirely on one side of the level skip the field, and their
     // classification also finishes the level
     const bool fused = fft_yx_fused(g);
     const int level_nb = level_blocks((int)f->n_points);
+    if ((r = run_level(c, f, g, P<float>(c->field), !fused || level_nb == 0)) != FVR_OK) return r;
+    r = run_mc(c, g, P<float>(c->field), fused ? P<float2>(c->rowmm) : nullptr, mesh, nullptr, true,
+               fused ? level_nb : 0);
+    mesh->level = c->host_status->level;
+    return r;
+}
+
+fvr_status fvr_reconstruct_noalloc(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mesh) {
+    fvr_status r = check_frame(c, f);
+    if (r != FVR_OK) return r;
+    if (!mesh) return fail(c, FVR_E_INVALID, "mesh is NULL");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    unsigned char *arena = statics_scratch(c->device);
+    if (!arena) return fail(c, FVR_E_DEVICE, "static scratch not set up on this device");
+    // the plan lives on the stack (no plan-cache insertion), its twiddles in
+    // the device's static table
+    Plan plan;
+    if ((r = build_plan(c, f->dims, plan)) != FVR_OK) return r;
+    plan_geometry(&plan, f->dims, f->bbox);
+    const Grid g = make_grid(f->dims, f->bbox);
+    // arena mode for this call: every scratch buffer is a slice of the static
+    // array; timing events (created on first use) are off
+    struct ArenaCall {
+        fvr_ctx *c;
+        uint32_t mask;
+        ArenaCall(fvr_ctx *ctx, unsigned char *a) : c(ctx), mask(ctx->timing_mask) {
+            c->arena = a;
+            c->arena_off = 0;
+            ++c->arena_epoch;
+            c->timing_mask = 0;
+        }
+        ~ArenaCall() {
+            c->arena = nullptr;
+            c->timing_mask = mask;
+        }
+    } call(c, arena);
+    // carve every buffer of the path before anything is enqueued, so a frame
+    // beyond the static scratch is refused without side effects
+    const int m = (int)f->n_points;
+    GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
+    if ((r = field_bufs(c, g, &plan, m)) != FVR_OK) return r;
+    if ((r = level_bufs(c, m)) != FVR_OK) return r;
+    const bool fused = fft_yx_fused(g);
+    if ((r = mc_bufs(c, g, mesh_caps(g, mesh, true), fused)) != FVR_OK) return r;
+    // the same stages as fvr_reconstruct on the carved buffers
+    if ((r = run_field(c, f, &plan, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
+    const int level_nb = level_blocks(m);
     if ((r = run_level(c, f, g, P<float>(c->field), !fused || level_nb == 0)) != FVR_OK) return r;
     r = run_mc(c, g, P<float>(c->field), fused ? P<float2>(c->rowmm) : nullptr, mesh, nullptr, true,
                fused ? level_nb : 0);
@@ -521,7 +652,7 @@ fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, doubl
     const Grid g = make_grid(f->dims, f->bbox);
     // the transform writes into the context's field first: on invalid input
     // the caller's buffer stays untouched
-    HIP_TRY(c, ensure(c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2]), "alloc field");
+    GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
     if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
     if ((r = run_level(c, f, g, P<float>(c->field))) != FVR_OK) return r;
     HIP_TRY(c, launch_status_publish(P<DevStatus>(c->status), c->host_status, c->stream),
@@ -529,7 +660,7 @@ fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, doubl
     if ((r = sync(c)) != FVR_OK) return r;
     if (c->host_status->flags & kFlagInvalid)
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
-    HIP_TRY(c, hipMemcpyAsync(field_out, c->field.p, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2],
+    HIP_TRY(c, hipMemcpyAsync(field_out, P<float>(c->field), sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2],
                               hipMemcpyDeviceToDevice, c->stream), "field copy");
     if ((r = sync(c)) != FVR_OK) return r;
     if (level_out) *level_out = c->host_status->level;
@@ -545,10 +676,10 @@ fvr_status fvr_extract(fvr_ctx *c, const float *field, const int32_t dims[3], co
     if (!std::isfinite(level)) return fail(c, FVR_E_INVALID, "level is not finite");
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     const Grid g = make_grid(dims, bbox);
-    HIP_TRY(c, ensure(c->status, sizeof(DevStatus)), "alloc status");
-    HIP_TRY(c, ensure(c->level_f32, sizeof(float)), "alloc level");
+    GET(c, c->status, sizeof(DevStatus), "status");
+    GET(c, c->level_f32, sizeof(float), "level");
     { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(P<DevStatus>(c->status), nullptr, 0, c->stream), "prep"); }
-    HIP_TRY(c, hipMemcpyAsync(c->level_f32.p, &level, sizeof(float), hipMemcpyHostToDevice, c->stream),
+    HIP_TRY(c, hipMemcpyAsync(P<float>(c->level_f32), &level, sizeof(float), hipMemcpyHostToDevice, c->stream),
             "level upload");
     r = run_mc(c, g, field, nullptr, mesh, cases_out, false);
     mesh->level = level;

@@ -83,6 +83,14 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
 // Reset the status block and zero `nbins` bin counters in one launch.
 hipError_t launch_prep(DevStatus *st, int32_t *bins, int nbins, hipStream_t s);
+// Device statics (fvr_static.hip): twiddle tables of every supported length
+// and the scratch array of the allocation-free entry point, one copy per GPU.
+// statics_init looks their addresses up once per device (device current).
+hipError_t statics_init(int device);
+int twiddle_offset(int n);                               // -1 if n is unsupported
+const float2 *statics_twiddles(int device, int n);       // nullptr before statics_init
+unsigned char *statics_scratch(int device);              // FVR_NOALLOC_SCRATCH_BYTES
+
 // Copy of the status block into pinned host memory (hipHostMalloc) by a kernel.
 hipError_t launch_status_publish(const DevStatus *st, DevStatus *host, hipStream_t s);
 

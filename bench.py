@@ -6,7 +6,14 @@ resident in HBM.  Default workload: the 6-view human proxy (700k points)
 on a 256^3 grid over a 2.0 m box.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--config proxy256] [--pool P]
-                  [--no-cpu-baseline]
+                  [--poses Q] [--latency-frames L] [--no-cpu-baseline]
+
+The pool holds P distinct frames resident in HBM (64 by default: 1.25 GB at
+256^3, well beyond the 256 MB last-level cache): Q of them ray-cast, the
+others those captures with the rig turned by a seeded yaw and shifted
+(synth.repose), since ray-casting a frame takes seconds on the host.
+Throughput is the K timed steps; p50/p99 come from a separate sample of
+max(L, K) frames, each a synchronous call timed on the host clock.
 
 Per-kernel durations come from HIP events the library records on its stream
 around every launch, in an untimed pass after the warmup; that pass names the
@@ -45,6 +52,7 @@ def kernel_alg_bytes(dims, m, nv, nt):
     F = 4 * n
     S = 8 * nz * ny * (nx // 2 + 1)
     return {
+        "prep": 0,
         "bin_count": 28 * m + 8 * m,
         "tile_list": 0,
         "bin_scatter": 36 * m + 32 * m,
@@ -105,6 +113,22 @@ def stored_traffic(name, config):
     return None
 
 
+def kernel_touched_bytes(dims, m, stats):
+    """Bytes the sparse passes actually move on this frame (the dense figures
+    of kernel_alg_bytes priced on the parts of the grid they touch): the
+    splat writes the spectrum rows of busy tiles only, the y pass reads those
+    rows and writes the non-zero z planes, the z pass reads those planes."""
+    nx, ny, nz = dims
+    S = 8 * nz * ny * (nx // 2 + 1)
+    tf = stats["busy_tiles"] / max(1, stats["tiles"])
+    pf = stats["nonzero_planes"] / max(1, stats["planes"])
+    return {
+        "splat_fft_x": round(28 * m + 3 * S * tf),
+        "fft_y_fwd": round(3 * S * tf + 2 * S * pf),
+        "fft_z_solve": round(2 * S * pf + S),
+    }
+
+
 def frame_alg_bytes(dims, m, nv, nt):
     """Whole-frame algorithmic bytes: each stage of the method reads its
     defined input once and writes its output once (8F + 8S + 40m + mesh)."""
@@ -136,7 +160,16 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="proxy256", choices=sorted(WORKLOADS))
-    ap.add_argument("--pool", type=int, default=2, help="distinct seeded frames cycled through")
+    ap.add_argument("--pool", type=int, default=64, help="distinct frames resident in HBM, cycled through")
+    ap.add_argument("--poses", type=int, default=2,
+                    help="ray-cast captures in the pool; the rest are reposed copies of them")
+    ap.add_argument("--latency-frames", type=int, default=200,
+                    help="frames in the separate latency sample (at least --steps)")
+    ap.add_argument("--secondary", default="proxy128",
+                    help="comma-separated workloads measured after the headline one and reported "
+                         "under 'secondary' (empty: none)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-cores CPU baseline (0: the host's CPUs, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--breakdown", type=int, default=20,
@@ -158,9 +191,13 @@ def main():
     import paper_1712_03084_amd as fvr
     import synth
 
-    print(f"[bench] generating {args.pool} frame(s) of {args.config}", file=sys.stderr, flush=True)
+    npose = max(1, min(args.poses, args.pool))
+    print(f"[bench] generating {npose} capture(s) of {args.config}, pool of {args.pool}",
+          file=sys.stderr, flush=True)
     base_seed = synth.CONFIGS[args.config]["seed"]
-    frames = [_load_frame(synth, args.config, base_seed + i, args.cache) for i in range(args.pool)]
+    caps = [_load_frame(synth, args.config, base_seed + i, args.cache) for i in range(npose)]
+    frames = list(caps) + [synth.repose(caps[i % npose], seed=base_seed + 100 + i)
+                           for i in range(args.pool - npose)]
     dev = torch.device("cuda:0")
     pool = [tuple(torch.from_numpy(a).to(dev) for a in (f.points, f.normals, f.weights))
             for f in frames]
@@ -224,6 +261,17 @@ def main():
     elapsed = t1 - t0
     fps = args.steps / elapsed
 
+    stats = ctx.last_stats()
+
+    # latency sample: each frame a synchronous call, timed on the host clock
+    nlat = max(args.latency_frames, args.steps)
+    print(f"[bench] latency sample of {nlat} frames", file=sys.stderr, flush=True)
+    lat = []
+    for k in range(nlat):
+        ts = time.perf_counter()
+        prepared[k % len(pool)].run()
+        lat.append(time.perf_counter() - ts)
+
     # the same frames through Context.reconstruct, which checks and marshals
     # its tensors on every call (reported beside the headline figure)
     torch.cuda.synchronize()
@@ -263,36 +311,93 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "grid": list(dims), "points": m,
-                   "frames_in_pool": args.pool, "binding": "Context.prepare(...).run()"},
+                   "frames_in_pool": args.pool, "captures_in_pool": npose,
+                   "binding": "Context.prepare(...).run()"},
         "value_reconstruct_call": round(fps_call, 2),
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
         "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+        "latency_frames": nlat,
         "mesh": {"vertices": round(nv_avg), "triangles": round(nt_avg)},
         "frame_roofline": {"alg_bytes": fb, "achieved_GBs": round(fb * fps / 1e9, 1),
                            "frac": round(fb * fps / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roof,
         "kernels": kernels,
+        "work": stats,
     }
+    touched = kernel_touched_bytes(dims, m, stats)
+    algb = kernel_alg_bytes(dims, m, nv_avg, nt_avg)
+    for name, kv in kernels.items():
+        kv["alg_bytes"] = algb.get(name)
+        if name in touched:
+            kv["touched_bytes"] = touched[name]
+
+    # secondary workloads: throughput and latency of the same call on other
+    # grids (their own pools of one capture and reposed copies)
+    sec = {}
+    for name in [x for x in args.secondary.split(",") if x and x != args.config]:
+        print(f"[bench] secondary workload {name}", file=sys.stderr, flush=True)
+        cap = _load_frame(synth, name, synth.CONFIGS[name]["seed"], args.cache)
+        sframes = [cap] + [synth.repose(cap, seed=7000 + i) for i in range(15)]
+        sdims, sbbox = cap.dims, cap.bbox
+        sprep = [ctx.prepare(*(torch.from_numpy(a).to(dev) for a in (f.points, f.normals, f.weights)),
+                             grid_dim=sdims, bbox=sbbox, out=out) for f in sframes]
+        for k in range(args.warmup):
+            sprep[k % len(sprep)].run()
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        for k in range(args.steps):
+            sprep[k % len(sprep)].run()
+        torch.cuda.synchronize()
+        sfps = args.steps / (time.perf_counter() - q0)
+        slat = []
+        for k in range(max(args.latency_frames, args.steps)):
+            ts = time.perf_counter()
+            sprep[k % len(sprep)].run()
+            slat.append(time.perf_counter() - ts)
+        slat = np.asarray(slat) * 1e3
+        sfb = frame_alg_bytes(sdims, cap.n_points, 0, 0)
+        sec[name] = {"workload": WORKLOADS[name], "value": round(sfps, 2), "unit": "frames/s",
+                     "ms_per_step": round(1e3 / sfps, 4),
+                     "p50_ms": round(float(np.percentile(slat, 50)), 4),
+                     "p99_ms": round(float(np.percentile(slat, 99)), 4),
+                     "frames_in_pool": len(sframes),
+                     "frame_alg_bytes": sfb,
+                     "effective_GBs": round(sfb * sfps / 1e9, 1)}
+        del sprep
+    if sec:
+        result["secondary"] = sec
 
     if not args.no_cpu_baseline:
-        # the oracle as it stands, single-threaded FP64, on whole frames of the
-        # same workload until about 10 s of CPU time have passed
+        # the oracle as it stands (FP64), on whole frames of the same workload:
+        # single-threaded, then on the host's cores (OpenMP over voxel and
+        # marching-cubes planes, FFT lines over workers: the same sums)
         import oracle
-        print("[bench] cpu baseline: oracle on full frames", file=sys.stderr, flush=True)
-        tc = time.perf_counter()
-        nf = 0
-        while nf < len(frames) * 4 and (nf == 0 or time.perf_counter() - tc < 10.0):
-            f = frames[nf % len(frames)]
-            oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
-            nf += 1
-            print(f"[bench] cpu baseline: {nf} frame(s), {time.perf_counter() - tc:.1f} s",
-                  file=sys.stderr, flush=True)
-        tcpu = time.perf_counter() - tc
-        result["cpu_baseline"] = {"value": round(nf / tcpu, 5), "unit": "frames/s", "cores": 1,
-                                  "kind": "oracle",
-                                  "sample": f"{nf} full frame(s) of the same workload "
-                                            f"({m} points, {dims[0]}x{dims[1]}x{dims[2]}), "
-                                            f"{tcpu:.2f} s single-threaded FP64"}
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        nthr = args.cpu_threads or max(1, min(16, avail))
+        print(f"[bench] cpu baseline: host has {os.cpu_count()} CPUs ({avail} available); "
+              f"oracle at 1 and {nthr} threads", file=sys.stderr, flush=True)
+
+        def leg(threads, budget_s):
+            tc = time.perf_counter()
+            nf = 0
+            while nf < len(frames) and (nf == 0 or time.perf_counter() - tc < budget_s):
+                f = frames[nf % len(frames)]
+                oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox, threads=threads)
+                nf += 1
+                print(f"[bench] cpu baseline ({threads} thread(s)): {nf} frame(s), "
+                      f"{time.perf_counter() - tc:.1f} s", file=sys.stderr, flush=True)
+            return nf, time.perf_counter() - tc
+
+        nf1, t1c = leg(1, 10.0)
+        nfa, tac = leg(nthr, 10.0)
+        result["cpu_baseline"] = {
+            "value": round(nfa / tac, 5), "unit": "frames/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{nfa} full frame(s) of the same workload ({m} points, "
+                      f"{dims[0]}x{dims[1]}x{dims[2]}), {tac:.2f} s FP64 on {nthr} threads",
+            "host_cpus": os.cpu_count(), "host_cpus_available": avail,
+            "single_core": {"value": round(nf1 / t1c, 5), "unit": "frames/s", "cores": 1,
+                            "sample": f"{nf1} full frame(s), {t1c:.2f} s single-threaded FP64"},
+        }
     print(json.dumps(result))
 
 

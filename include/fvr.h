@@ -151,6 +151,19 @@ fvr_status fvr_extract(fvr_ctx *ctx, const float *field, const int32_t dims[3],
  * component-major) written by the same splat kernel the path uses. */
 fvr_status fvr_debug_splat(fvr_ctx *ctx, const fvr_frame *frame, float *v_out);
 
+/* Work counters of the context's last completed fvr_reconstruct,
+ * fvr_reconstruct_noalloc or fvr_indicator call, from the status block that
+ * call read back (no device work): how much of the grid the sparse passes
+ * touched. */
+typedef struct {
+    int64_t busy_tiles, tiles;            /* splat tiles some footprint reaches / all */
+    int64_t nonzero_planes, planes;       /* z planes the passes after the y transform read / all */
+    int64_t mc_blocks_listed, mc_blocks;  /* marching-cubes blocks classified from the field / all
+                                             (all are listed when the row ranges are not used) */
+    int64_t points_used, points_rejected; /* accepted points in the level, points outside the bbox */
+} fvr_stats;
+fvr_status fvr_last_stats(const fvr_ctx *ctx, fvr_stats *out);
+
 /* Host-only helpers (no device work; callable without a GPU). */
 /* Check dims and bbox as fvr_reconstruct would. */
 fvr_status fvr_check_grid(const int32_t dims[3], const float bbox[6]);

@@ -40,7 +40,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle's C part with gcc (no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                                "-ffp-contract=off", "-fno-fast-math",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
@@ -58,12 +58,12 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
-        lib.oracle_splat.argtypes = [P, P, P, i64, P, P, P, P, P]
+        lib.oracle_splat.argtypes = [P, P, P, i64, P, P, P, P, P, ctypes.c_int]
         lib.oracle_splat.restype = i64
         lib.oracle_level.argtypes = [P, P, P, P, i64, P]
         lib.oracle_level.restype = ctypes.c_double
         lib.oracle_marching_cubes.argtypes = [P, P, P, ctypes.c_double, P, P,
-                                              P, i64, P, i64, P, P, P]
+                                              P, i64, P, i64, P, P, P, ctypes.c_int]
         lib.oracle_marching_cubes.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -85,9 +85,11 @@ def geometry(dims, bbox):
     return h, s1, s1 * np.sqrt(1.5)
 
 
-def splat(points, normals, weights, dims, bbox):
+def splat(points, normals, weights, dims, bbox, threads: int = 1):
     """Eqs. (1)-(2).  Returns (V, S, D, n_rejected); V and S have shape
-    (3, Nz, Ny, Nx), D has shape (Nz, Ny, Nx).  weights None means all 1."""
+    (3, Nz, Ny, Nx), D has shape (Nz, Ny, Nx).  weights None means all 1.
+    threads > 1 splits the voxel planes over OpenMP threads; every voxel
+    still sums its terms in input order (the same bits)."""
     lib = _load()
     p = _f32c(points).reshape(-1, 3)
     nrm = _f32c(normals).reshape(-1, 3)
@@ -100,7 +102,7 @@ def splat(points, normals, weights, dims, bbox):
     D = np.empty((Nz, Ny, Nx))
     V = np.empty((3, Nz, Ny, Nx))
     rej = lib.oracle_splat(_ptr(p), _ptr(nrm), _ptr(w), m, _ptr(d), _ptr(b),
-                           _ptr(S), _ptr(D), _ptr(V))
+                           _ptr(S), _ptr(D), _ptr(V), int(threads))
     return V, S, D, int(rej)
 
 
@@ -136,19 +138,27 @@ def filter_factors(dims, bbox):
     return dx[None, None, :], dy[None, :, None], dz[:, None, None], inv
 
 
-def indicator(V, dims, bbox, return_imag: bool = False):
+def indicator(V, dims, bbox, return_imag: bool = False, threads: int = 1):
     """Spectral integration of Sec. III-B, taken literally.
 
     For each component c: V^_c = DFT3(V_c) (unnormalised, exp(-i...)),
     A^_c = j w_c V^_c / |w|^2, A_c = inverse DFT3 (with 1/n); then
     A = sum_c Re(A_c).  Returns A with shape (Nz, Ny, Nx) (and the largest
-    |Im| seen if requested)."""
+    |Im| seen if requested).  The transform primitive is numpy's FFT; with
+    threads > 1 it is scipy's FFT with that many workers over independent
+    lines (a timing configuration: its rounding may differ in the last bits)."""
     dx, dy, dz, inv = filter_factors(dims, bbox)
+    if threads > 1:
+        import scipy.fft as sfft
+        fftn = lambda x: sfft.fftn(x, workers=threads)  # noqa: E731
+        ifftn = lambda x: sfft.ifftn(x, workers=threads)  # noqa: E731
+    else:
+        fftn, ifftn = np.fft.fftn, np.fft.ifftn
     A = np.zeros(V.shape[1:])
     imag = 0.0
     for c, dfac in enumerate((dx, dy, dz)):
-        spec = np.fft.fftn(V[c])
-        a = np.fft.ifftn(1j * dfac * spec * inv)
+        spec = fftn(V[c])
+        a = ifftn(1j * dfac * spec * inv)
         imag = max(imag, float(np.max(np.abs(a.imag))))
         A += a.real
     return (A, imag) if return_imag else A
@@ -177,9 +187,10 @@ def mc_table():
     return _TABLE
 
 
-def extract(A, L, dims, bbox, with_cases: bool = True):
+def extract(A, L, dims, bbox, with_cases: bool = True, threads: int = 1):
     """Marching cubes at level L.  Returns (verts (V,3) f64, tris (T,3) i32,
-    cases uint8 (Nz-1, Ny-1, Nx-1) or None)."""
+    cases uint8 (Nz-1, Ny-1, Nx-1) or None).  threads > 1 spreads the z
+    planes over OpenMP threads (same output)."""
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     Nx, Ny, Nz = (int(x) for x in dims)
@@ -190,11 +201,11 @@ def extract(A, L, dims, bbox, with_cases: bool = True):
             float(L), _ptr(count), _ptr(edges))
     # first pass sizes the output, second pass fills it
     lib.oracle_marching_cubes(*args, None, 0, None, 0, _ptr(cases),
-                              ctypes.byref(nv), ctypes.byref(nt))
+                              ctypes.byref(nv), ctypes.byref(nt), int(threads))
     verts = np.empty((max(nv.value, 1), 3))
     tris = np.empty((max(nt.value, 1), 3), np.int32)
     rc = lib.oracle_marching_cubes(*args, _ptr(verts), nv.value, _ptr(tris), nt.value,
-                                   None, ctypes.byref(nv), ctypes.byref(nt))
+                                   None, ctypes.byref(nv), ctypes.byref(nt), int(threads))
     assert rc == 0
     return verts[:nv.value], tris[:nt.value], cases
 
@@ -208,13 +219,15 @@ def open_surface(A, L) -> bool:
     return bool(np.any(A[shell] > L))
 
 
-def reconstruct(points, normals, weights, dims, bbox, with_cases=False):
-    """The whole path: splat, spectral integration, level, marching cubes."""
-    V, _, _, rej = splat(points, normals, weights, dims, bbox)
-    A = indicator(V, dims, bbox)
+def reconstruct(points, normals, weights, dims, bbox, with_cases=False, threads: int = 1):
+    """The whole path: splat, spectral integration, level, marching cubes.
+    threads > 1 runs the splat, the transforms and marching cubes on that
+    many host threads (see each step)."""
+    V, _, _, rej = splat(points, normals, weights, dims, bbox, threads=threads)
+    A = indicator(V, dims, bbox, threads=threads)
     L, used = level(A, points, dims, bbox)
     if used == 0:
         L = 0.0
-    verts, tris, cases = extract(A, L, dims, bbox, with_cases=with_cases)
+    verts, tris, cases = extract(A, L, dims, bbox, with_cases=with_cases, threads=threads)
     return dict(V=V, A=A, level=L, n_used=used, n_rejected=rej, verts=verts,
                 tris=tris, cases=cases, open_surface=open_surface(A, L))

@@ -55,10 +55,12 @@ static int point_accepted(const float *x, const float *bbox)
  * weights == NULL means every W_i = 1.
  * Outputs are (Nz, Ny, Nx) arrays, x fastest; S and V hold 3 such arrays
  * (component-major).  Returns the number of rejected (outside-bbox) points.
+ * nthreads > 1 splits the voxel planes among OpenMP threads without
+ * changing any sum (see the loop).
  */
 int64_t oracle_splat(const float *points, const float *normals, const float *weights,
                      int64_t m, const int32_t *dims, const float *bbox,
-                     double *S, double *D, double *V)
+                     double *S, double *D, double *V, int nthreads)
 {
     const int Nx = dims[0], Ny = dims[1], Nz = dims[2];
     const int64_t n = (int64_t)Nx * Ny * Nz;
@@ -71,36 +73,49 @@ int64_t oracle_splat(const float *points, const float *normals, const float *wei
     memset(S, 0, sizeof(double) * 3 * n);
     memset(D, 0, sizeof(double) * n);
     int64_t rejected = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (!point_accepted(points + 3 * i, bbox)) ++rejected;
 
-    for (int64_t i = 0; i < m; ++i) {
-        const float *X = points + 3 * i;
-        if (!point_accepted(X, bbox)) { ++rejected; continue; }
-        const double W = weights ? (double)weights[i] : 1.0;
-        int i0[3];
-        for (int a = 0; a < 3; ++a)
-            i0[a] = footprint_origin_f32(X[a], bbox[a], bbox[a + 3], dims[a]);
-        for (int oz = -1; oz <= 2; ++oz) {
-            const int qz = i0[2] + oz;
-            if (qz < 0 || qz >= Nz) continue;
-            for (int oy = -1; oy <= 2; ++oy) {
-                const int qy = i0[1] + oy;
-                if (qy < 0 || qy >= Ny) continue;
-                for (int ox = -1; ox <= 2; ++ox) {
-                    const int qx = i0[0] + ox;
-                    if (qx < 0 || qx >= Nx) continue;
-                    const double px = (double)bbox[0] + (qx + 0.5) * h[0];
-                    const double py = (double)bbox[1] + (qy + 0.5) * h[1];
-                    const double pz = (double)bbox[2] + (qz + 0.5) * h[2];
-                    const double dx = (double)X[0] - px;
-                    const double dy = (double)X[1] - py;
-                    const double dz = (double)X[2] - pz;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    const double g1 = exp(-r2 / (sigma1 * sigma1)) / sigma1;
-                    const double g2 = exp(-r2 / (sigma2 * sigma2)) / sigma2;
-                    const int64_t l = qx + (int64_t)Nx * (qy + (int64_t)Ny * qz);
-                    for (int c = 0; c < 3; ++c)
-                        S[c * n + l] += g1 * W * (double)normals[3 * i + c];
-                    D[l] += g2 * W;
+    /* With several threads, thread t owns the voxel planes z in
+     * [z0(t), z1(t)) and visits every point in input order, adding only to
+     * its own planes: each voxel still receives its terms in input order, so
+     * the sums are those of the single-threaded loop, bit for bit. */
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > Nz) nthreads = Nz;
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1)
+    for (int t = 0; t < nthreads; ++t) {
+        const int z0 = (int)((int64_t)Nz * t / nthreads), z1 = (int)((int64_t)Nz * (t + 1) / nthreads);
+        for (int64_t i = 0; i < m; ++i) {
+            const float *X = points + 3 * i;
+            if (!point_accepted(X, bbox)) continue;
+            const double W = weights ? (double)weights[i] : 1.0;
+            int i0[3];
+            for (int a = 0; a < 3; ++a)
+                i0[a] = footprint_origin_f32(X[a], bbox[a], bbox[a + 3], dims[a]);
+            if (i0[2] + 2 < z0 || i0[2] - 1 >= z1) continue;
+            for (int oz = -1; oz <= 2; ++oz) {
+                const int qz = i0[2] + oz;
+                if (qz < 0 || qz >= Nz || qz < z0 || qz >= z1) continue;
+                for (int oy = -1; oy <= 2; ++oy) {
+                    const int qy = i0[1] + oy;
+                    if (qy < 0 || qy >= Ny) continue;
+                    for (int ox = -1; ox <= 2; ++ox) {
+                        const int qx = i0[0] + ox;
+                        if (qx < 0 || qx >= Nx) continue;
+                        const double px = (double)bbox[0] + (qx + 0.5) * h[0];
+                        const double py = (double)bbox[1] + (qy + 0.5) * h[1];
+                        const double pz = (double)bbox[2] + (qz + 0.5) * h[2];
+                        const double dx = (double)X[0] - px;
+                        const double dy = (double)X[1] - py;
+                        const double dz = (double)X[2] - pz;
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        const double g1 = exp(-r2 / (sigma1 * sigma1)) / sigma1;
+                        const double g2 = exp(-r2 / (sigma2 * sigma2)) / sigma2;
+                        const int64_t l = qx + (int64_t)Nx * (qy + (int64_t)Ny * qz);
+                        for (int c = 0; c < 3; ++c)
+                            S[c * n + l] += g1 * W * (double)normals[3 * i + c];
+                        D[l] += g2 * W;
+                    }
                 }
             }
         }
@@ -176,34 +191,28 @@ double oracle_level(const double *A, const int32_t *dims, const float *bbox,
  * tri_count[256] and tri_edges[256 * 15] come from the oracle's own table
  * generator (the rule is documented there).
  * Output sizes are checked against the capacities; the required counts are
- * always written.  Returns 0, or -1 if a capacity is too small.
+ * always written.  Returns 0, or -1 if a capacity is too small.  nthreads > 1
+ * spreads the z planes over OpenMP threads; the output is the same.
  */
-int oracle_marching_cubes(const double *A, const int32_t *dims, const float *bbox,
-                          double level, const uint8_t *tri_count, const int8_t *tri_edges,
-                          double *verts, int64_t vert_cap, int32_t *tris, int64_t tri_cap,
-                          uint8_t *cases, int64_t *n_verts, int64_t *n_tris)
+/* Vertices whose grid point lies in plane qz, in (l, axis) order; writes
+ * ids from `first` (and positions, if they fit) when vid is not NULL. */
+static int64_t mc_plane_vertices(const double *A, const int32_t *dims, const float *bbox,
+                                 const double *h, double level, int qz, int64_t first,
+                                 int32_t *vid, double *verts, int64_t vert_cap)
 {
-    const int Nx = dims[0], Ny = dims[1], Nz = dims[2];
-    const int64_t n = (int64_t)Nx * Ny * Nz;
-    double h[3];
-    for (int a = 0; a < 3; ++a)
-        h[a] = ((double)bbox[a + 3] - (double)bbox[a]) / (double)dims[a];
-    int32_t *vid = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)n);
-    if (!vid) return -2;
-
-    /* vertices on active grid edges, in (l, axis) order */
-    int64_t nv = 0;
-    for (int qz = 0; qz < Nz; ++qz)
-        for (int qy = 0; qy < Ny; ++qy)
-            for (int qx = 0; qx < Nx; ++qx) {
-                const int64_t l = qx + (int64_t)Nx * (qy + (int64_t)Ny * qz);
-                const int q[3] = {qx, qy, qz};
-                const int64_t stride[3] = {1, Nx, (int64_t)Nx * Ny};
-                for (int a = 0; a < 3; ++a) {
-                    vid[3 * l + a] = -1;
-                    if (q[a] + 1 >= dims[a]) continue;
-                    const double a0 = A[l], a1 = A[l + stride[a]];
-                    if ((a0 > level) == (a1 > level)) continue;
+    const int Nx = dims[0], Ny = dims[1];
+    int64_t nv = first;
+    for (int qy = 0; qy < Ny; ++qy)
+        for (int qx = 0; qx < Nx; ++qx) {
+            const int64_t l = qx + (int64_t)Nx * (qy + (int64_t)Ny * qz);
+            const int q[3] = {qx, qy, qz};
+            const int64_t stride[3] = {1, Nx, (int64_t)Nx * Ny};
+            for (int a = 0; a < 3; ++a) {
+                if (vid) vid[3 * l + a] = -1;
+                if (q[a] + 1 >= dims[a]) continue;
+                const double a0 = A[l], a1 = A[l + stride[a]];
+                if ((a0 > level) == (a1 > level)) continue;
+                if (vid) {
                     if (nv < vert_cap) {
                         const double t = (level - a0) / (a1 - a0);
                         for (int b = 0; b < 3; ++b) {
@@ -213,42 +222,108 @@ int oracle_marching_cubes(const double *A, const int32_t *dims, const float *bbo
                         }
                     }
                     vid[3 * l + a] = (int32_t)nv;
-                    ++nv;
                 }
+                ++nv;
             }
+        }
+    return nv - first;
+}
 
-    /* triangles, cell by cell */
-    int64_t nt = 0;
-    for (int cz = 0; cz < Nz - 1; ++cz)
-        for (int cy = 0; cy < Ny - 1; ++cy)
-            for (int cx = 0; cx < Nx - 1; ++cx) {
-                int cs = 0;
-                for (int k = 0; k < 8; ++k) {
-                    const int64_t l = (cx + (k & 1)) + (int64_t)Nx * ((cy + ((k >> 1) & 1)) +
-                                                                    (int64_t)Ny * (cz + ((k >> 2) & 1)));
-                    if (A[l] > level) cs |= 1 << k;
-                }
-                if (cases)
-                    cases[cx + (int64_t)(Nx - 1) * (cy + (int64_t)(Ny - 1) * cz)] = (uint8_t)cs;
-                for (int t = 0; t < tri_count[cs]; ++t) {
-                    for (int j = 0; j < 3; ++j) {
-                        const int e = tri_edges[cs * 15 + 3 * t + j];
-                        const int axis = e / 4, r = e % 4;
-                        int off[3] = {0, 0, 0};
-                        int o = 0;
-                        for (int b = 0; b < 3; ++b) {
-                            if (b == axis) continue;
-                            off[b] = o == 0 ? (r & 1) : ((r >> 1) & 1);
-                            ++o;
-                        }
-                        const int64_t l = (cx + off[0]) + (int64_t)Nx * ((cy + off[1]) +
-                                                                       (int64_t)Ny * (cz + off[2]));
-                        if (nt < tri_cap) tris[3 * nt + j] = vid[3 * l + axis];
-                    }
-                    ++nt;
-                }
+/* Triangles of the cells in plane cz, in (l(c), table) order.  With fill,
+ * writes the case bytes (if cases is not NULL) and the triangles from
+ * `first` (if they fit); otherwise only counts. */
+static int64_t mc_plane_triangles(const double *A, const int32_t *dims, double level, int cz,
+                                  const uint8_t *tri_count, const int8_t *tri_edges,
+                                  const int32_t *vid, int fill, int64_t first, int32_t *tris,
+                                  int64_t tri_cap, uint8_t *cases)
+{
+    const int Nx = dims[0], Ny = dims[1];
+    int64_t nt = first;
+    for (int cy = 0; cy < Ny - 1; ++cy)
+        for (int cx = 0; cx < Nx - 1; ++cx) {
+            int cs = 0;
+            for (int k = 0; k < 8; ++k) {
+                const int64_t l = (cx + (k & 1)) + (int64_t)Nx * ((cy + ((k >> 1) & 1)) +
+                                                                (int64_t)Ny * (cz + ((k >> 2) & 1)));
+                if (A[l] > level) cs |= 1 << k;
             }
+            if (!fill) {
+                nt += tri_count[cs];
+                continue;
+            }
+            if (cases)
+                cases[cx + (int64_t)(Nx - 1) * (cy + (int64_t)(Ny - 1) * cz)] = (uint8_t)cs;
+            for (int t = 0; t < tri_count[cs]; ++t) {
+                for (int j = 0; j < 3; ++j) {
+                    const int e = tri_edges[cs * 15 + 3 * t + j];
+                    const int axis = e / 4, r = e % 4;
+                    int off[3] = {0, 0, 0};
+                    int o = 0;
+                    for (int b = 0; b < 3; ++b) {
+                        if (b == axis) continue;
+                        off[b] = o == 0 ? (r & 1) : ((r >> 1) & 1);
+                        ++o;
+                    }
+                    const int64_t l = (cx + off[0]) + (int64_t)Nx * ((cy + off[1]) +
+                                                                   (int64_t)Ny * (cz + off[2]));
+                    if (tris && nt < tri_cap) tris[3 * nt + j] = vid[3 * l + axis];
+                }
+                ++nt;
+            }
+        }
+    return nt - first;
+}
+
+int oracle_marching_cubes(const double *A, const int32_t *dims, const float *bbox,
+                          double level, const uint8_t *tri_count, const int8_t *tri_edges,
+                          double *verts, int64_t vert_cap, int32_t *tris, int64_t tri_cap,
+                          uint8_t *cases, int64_t *n_verts, int64_t *n_tris, int nthreads)
+{
+    const int Nx = dims[0], Ny = dims[1], Nz = dims[2];
+    const int64_t n = (int64_t)Nx * Ny * Nz;
+    double h[3];
+    for (int a = 0; a < 3; ++a)
+        h[a] = ((double)bbox[a + 3] - (double)bbox[a]) / (double)dims[a];
+    int32_t *vid = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)n);
+    int64_t *vfirst = (int64_t *)malloc(sizeof(int64_t) * ((size_t)Nz + 1));
+    int64_t *tfirst = (int64_t *)malloc(sizeof(int64_t) * ((size_t)Nz + 1));
+    if (!vid || !vfirst || !tfirst) {
+        free(vid);
+        free(vfirst);
+        free(tfirst);
+        return -2;
+    }
+    if (nthreads < 1) nthreads = 1;
+
+    /* Vertices on active grid edges, in (l, axis) order: each z plane is
+     * counted, the counts are prefix-summed in plane order, and each plane
+     * numbers its vertices from its offset - the numbering of one loop over
+     * l, whatever the number of threads. */
+    vfirst[0] = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int qz = 0; qz < Nz; ++qz)
+        vfirst[qz + 1] = mc_plane_vertices(A, dims, bbox, h, level, qz, 0, NULL, NULL, 0);
+    for (int qz = 0; qz < Nz; ++qz) vfirst[qz + 1] += vfirst[qz];
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int qz = 0; qz < Nz; ++qz)
+        mc_plane_vertices(A, dims, bbox, h, level, qz, vfirst[qz], vid, verts, vert_cap);
+
+    /* Triangles, cell by cell in (l(c), table) order, the same way per plane
+     * of cells. */
+    tfirst[0] = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int cz = 0; cz < Nz - 1; ++cz)
+        tfirst[cz + 1] = mc_plane_triangles(A, dims, level, cz, tri_count, tri_edges, vid, 0, 0, NULL,
+                                            0, NULL);
+    for (int cz = 0; cz < Nz - 1; ++cz) tfirst[cz + 1] += tfirst[cz];
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int cz = 0; cz < Nz - 1; ++cz)
+        mc_plane_triangles(A, dims, level, cz, tri_count, tri_edges, vid, 1, tfirst[cz], tris, tri_cap,
+                           cases);
+    const int64_t nv = vfirst[Nz], nt = tfirst[Nz - 1];
     free(vid);
+    free(vfirst);
+    free(tfirst);
     *n_verts = nv;
     *n_tris = nt;
     return (nv > vert_cap || nt > tri_cap) ? -1 : 0;

@@ -50,6 +50,12 @@ class _Frame(ctypes.Structure):
                 ("dims", ctypes.c_int32 * 3), ("bbox", ctypes.c_float * 6)]
 
 
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "busy_tiles", "tiles", "nonzero_planes", "planes", "mc_blocks_listed", "mc_blocks",
+        "points_used", "points_rejected")]
+
+
 class _Mesh(ctypes.Structure):
     _fields_ = [("vertices", ctypes.c_void_p), ("triangles", ctypes.c_void_p),
                 ("vertex_capacity", ctypes.c_int64), ("triangle_capacity", ctypes.c_int64),
@@ -88,6 +94,7 @@ def load_library():
     lib.fvr_debug_splat.argtypes = [P, ctypes.POINTER(_Frame), P]
     lib.fvr_check_grid.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
     lib.fvr_check_frame.argtypes = [ctypes.POINTER(_Frame)]
+    lib.fvr_last_stats.argtypes = [P, ctypes.POINTER(_Stats)]
     lib.fvr_mc_table.argtypes = [P, P]
     lib.fvr_timing_enable.argtypes = [P, I]
     lib.fvr_timing_select.argtypes = [P, ctypes.c_uint32]
@@ -102,7 +109,8 @@ def load_library():
     lib.fvr_last_error.restype = ctypes.c_char_p
     for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_reconstruct_noalloc",
                "fvr_indicator", "fvr_extract",
-               "fvr_debug_splat", "fvr_check_grid", "fvr_check_frame", "fvr_mc_table", "fvr_timing_enable",
+               "fvr_debug_splat", "fvr_check_grid", "fvr_check_frame", "fvr_last_stats", "fvr_mc_table",
+               "fvr_timing_enable",
                "fvr_timing_select", "fvr_timing_reset", "fvr_timing_get"):
         getattr(lib, fn).restype = I
     _lib = lib
@@ -299,6 +307,14 @@ class Context:
         return self._run_mesh(lambda m: self.lib.fvr_reconstruct(self.handle, ctypes.byref(f),
                                                                  ctypes.byref(m)),
                               dims, out, vertex_capacity, triangle_capacity)
+
+    def last_stats(self) -> dict:
+        """Work counters of the last reconstruction or indicator call
+        (``fvr_last_stats``): busy splat tiles, non-zero z planes, listed
+        marching-cubes blocks, points used and rejected."""
+        st = _Stats()
+        _check(self.lib, self.lib.fvr_last_stats(self.handle, ctypes.byref(st)), self.handle)
+        return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
 
     def reconstruct_noalloc(self, points, normals, weights=None, grid_dim=(128, 128, 128),
                             bbox=((-1, -1, -1), (1, 1, 1)), out=None) -> Mesh:

@@ -88,6 +88,7 @@ struct fvr_ctx {
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
         lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm, mc_list;
     DevStatus *host_status = nullptr;
+    fvr_stats last{};  // sizes of the last call; the counters come from host_status
     uint32_t timing_mask = 0;  // bit k: time kernel k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<int> ev_kid;
@@ -403,6 +404,9 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     const int nbins = (g.n[2] + 1) * (g.n[1] + 1);
     fvr_status r = field_bufs(c, g, p, m);
     if (r != FVR_OK) return r;
+    c->last = fvr_stats{};
+    c->last.tiles = p->sc.tiles_y * ((g.n[2] + p->sc.tz - 1) / p->sc.tz);
+    c->last.planes = g.n[2];
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(st, P<int32_t>(c->bin_count), nbins, s), "prep"); }
@@ -425,7 +429,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     if (splat_only) return FVR_OK;
     float2 *sp = P<float2>(c->spec);
     { Timed t(c, K_FFT_Y_FWD);
-      HIP_TRY(c, launch_fft_y_fwd(sp, P<uint8_t>(c->occ), P<uint8_t>(c->zocc), g, p->ax[1], s), "fft_y_fwd"); }
+      HIP_TRY(c, launch_fft_y_fwd(sp, P<uint8_t>(c->occ), P<uint8_t>(c->zocc), st, g, p->ax[1], s), "fft_y_fwd"); }
     { Timed t(c, K_FFT_Z_SOLVE);
       HIP_TRY(c, launch_fft_z_solve(sp, P<uint8_t>(c->zocc), g, p->ax[2], s), "fft_z_solve"); }
     if (fft_yx_fused(g)) {
@@ -461,6 +465,8 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
     const MeshCaps caps = mesh_caps(g, mesh, check_invalid);
     fvr_status r0 = mc_bufs(c, g, caps, rowmm != nullptr);
     if (r0 != FVR_OK) return r0;
+    c->last.mc_blocks = nb;
+    c->last.mc_blocks_listed = rowmm ? -1 : nb;  // -1: read from the status block
     DevStatus *st = P<DevStatus>(c->status);
     hipStream_t s = c->stream;
     int32_t *list = nullptr;
@@ -704,6 +710,18 @@ fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
     if ((r = sync(c)) != FVR_OK) return r;
     if (c->host_status->flags & kFlagInvalid)
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
+    return FVR_OK;
+}
+
+fvr_status fvr_last_stats(const fvr_ctx *c, fvr_stats *out) {
+    if (!c || !out) return fail(nullptr, FVR_E_INVALID, "context or out is NULL");
+    *out = c->last;
+    const DevStatus &h = *c->host_status;
+    out->busy_tiles = h.n_busy;
+    out->nonzero_planes = h.n_zplanes;
+    if (out->mc_blocks_listed < 0) out->mc_blocks_listed = h.mc_active;
+    out->points_used = h.n_used;
+    out->points_rejected = h.rejected;
     return FVR_OK;
 }
 

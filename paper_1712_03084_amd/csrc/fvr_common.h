@@ -70,6 +70,7 @@ struct DevStatus {
     int32_t tile_ticket;  // next entry of the busy-tile list to claim (persistent splat blocks)
     int32_t n_busy;       // splat tiles that some point reaches
     int32_t mc_active;    // marching-cubes blocks left for the classification (mc_classify)
+    int32_t n_zplanes;    // z planes some splat tile reaches (read by the z pass)
 };
 constexpr uint32_t kFlagInvalid = 1u;
 constexpr uint32_t kFlagOpen = 2u;
@@ -143,8 +144,8 @@ size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc);
 // derivative terms: plane0 <- F_y(plane0) + j w_y F_y(plane1); plane2 <- F_y(plane2).
 // Rows of unoccupied tiles are read as zero; a z plane with no occupied tile
 // is neither read nor written and gets zocc[z] = 0 (1 otherwise).
-hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, const Grid &g,
-                            const FftAxis &ay, hipStream_t s);
+hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, DevStatus *st,
+                            const Grid &g, const FftAxis &ax, hipStream_t s);
 // Forward z transform of planes 0 and 2, the spectral solve, inverse z:
 // plane0 <- F_z^-1[(F_z plane0 + j w_z F_z plane2) / |w|^2], DC -> 0.
 // Planes with zocc[z] = 0 are read as zero.

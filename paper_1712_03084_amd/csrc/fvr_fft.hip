@@ -103,7 +103,7 @@ __device__ __forceinline__ void store_pencils(float2 *__restrict__ dstg, const f
 template <int PF>
 __global__ void __launch_bounds__(kPassThreads)
 fft_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
-                 uint8_t *__restrict__ zocc, Grid g, FftAxis ay) {
+                 uint8_t *__restrict__ zocc, DevStatus *__restrict__ st, Grid g, FftAxis ay) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
     __shared__ uint8_t keep[kMaxDim];
     __shared__ int any;
@@ -122,7 +122,10 @@ fft_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
         if (o) any = 1;
     }
     __syncthreads();
-    if (chunk == 0 && threadIdx.x == 0) zocc[z] = any ? 1 : 0;
+    if (chunk == 0 && threadIdx.x == 0) {
+        zocc[z] = any ? 1 : 0;
+        if (any) atomicAdd(&st->n_zplanes, 1);  // planes the later passes read
+    }
     if (!any) return;  // an all-zero plane stays zero through the y transform
     float2 *A = lds, *B = lds + Ny * kChunk, *tw = lds + 2 * Ny * kChunk;
     const int tot = Ny * kChunk;
@@ -378,7 +381,8 @@ struct Pencil {
 template <int N1, int N2>
 __global__ void __launch_bounds__(16 * N2)
 pen_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
-                 uint8_t *__restrict__ zocc, Grid g, const float2 *__restrict__ twg) {
+                 uint8_t *__restrict__ zocc, DevStatus *__restrict__ st, Grid g,
+                 const float2 *__restrict__ twg) {
     using Pn = Pencil<N1, N2>;
     constexpr int N = Pn::N;  // = Ny
     __shared__ float2 ex[Pn::EX];
@@ -402,7 +406,10 @@ pen_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
     }
     for (int i = threadIdx.x; i < N; i += Pn::THREADS) tw[i] = twg[i];
     __syncthreads();
-    if (chunk == 0 && threadIdx.x == 0) zocc[z] = any ? 1 : 0;
+    if (chunk == 0 && threadIdx.x == 0) {
+        zocc[z] = any ? 1 : 0;
+        if (any) atomicAdd(&st->n_zplanes, 1);  // planes the later passes read
+    }
     if (!any) return;  // an all-zero plane stays zero through the y transform
     const bool col = k0 + c < H;
     // byte offsets: rows of tiles that no point reaches (and idle lanes) get
@@ -793,14 +800,14 @@ hipError_t fft_configure() {
 // pencil buffers plus the twiddle table
 static size_t pass_lds(int n, int bufs) { return ((size_t)bufs * n * kChunk + n) * sizeof(float2); }
 
-hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, const Grid &g,
-                            const FftAxis &ax, hipStream_t s) {
+hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, DevStatus *st,
+                            const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
     if (const int pc = pencil_code(g.n[1])) {
-        FVR_PEN_SWITCH(pc, pen_y_fwd_kernel, (spec, occ, zocc, g, ax.tw), dim3(nch * g.n[2]))
+        FVR_PEN_SWITCH(pc, pen_y_fwd_kernel, (spec, occ, zocc, st, g, ax.tw), dim3(nch * g.n[2]))
         return hipGetLastError();
     }
-    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, (spec, occ, zocc, g, ax), dim3(nch * g.n[2]),
+    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, (spec, occ, zocc, st, g, ax), dim3(nch * g.n[2]),
                   dim3(kPassThreads), pass_lds(g.n[1], 2), s)
     return hipGetLastError();
 }

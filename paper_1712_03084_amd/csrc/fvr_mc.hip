@@ -73,6 +73,7 @@ __global__ void prep_kernel(DevStatus *st, int32_t *bins, int nbins) {
         st->tile_ticket = 0;
         st->n_busy = 0;
         st->mc_active = 0;
+        st->n_zplanes = 0;
     }
     if (bins && i < nbins) bins[i] = 0;
 }

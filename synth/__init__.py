@@ -38,6 +38,7 @@ __all__ = [
     "CONFIGS",
     "isolated_weights_frame",
     "spread_weights",
+    "repose",
 ]
 
 
@@ -414,3 +415,32 @@ def spread_weights(frame: Frame, decades: float = 4.0, seed: int = 0) -> Frame:
     info["weight_decades"] = decades
     return Frame(frame.points, frame.normals, _f32(w), frame.dims, frame.bbox,
                  name=frame.name + f"_w{decades:g}dec", info=info)
+
+
+# ---------------------------------------------------------------------------
+# Cheap variants of a captured frame
+# ---------------------------------------------------------------------------
+def repose(frame: Frame, seed: int, max_shift: float = 0.05) -> Frame:
+    """The same capture with the whole rig turned about the vertical axis
+    through the box centre by a seeded yaw in [0, 2 pi) and shifted by a
+    seeded horizontal offset of at most ``max_shift`` (metres) per axis:
+    points and normals are rotated, weights kept.  Ray-casting a human-proxy
+    frame takes seconds; a pool of many distinct frames for a benchmark is
+    made from a few captures this way (each variant lands on different
+    voxels and tiles, so no two frames share their binned data)."""
+    rng = np.random.default_rng(seed)
+    yaw = rng.uniform(0.0, 2.0 * math.pi)
+    shift = rng.uniform(-max_shift, max_shift, 2)
+    c, s_ = math.cos(yaw), math.sin(yaw)
+    R = np.array([[c, 0.0, s_], [0.0, 1.0, 0.0], [-s_, 0.0, c]])
+    b = np.asarray(frame.bbox, np.float64)
+    ctr = 0.5 * (b[:3] + b[3:])
+    ctr[1] = 0.0
+    p = (frame.points.astype(np.float64) - ctr) @ R.T + ctr
+    p[:, 0] += shift[0]
+    p[:, 2] += shift[1]
+    n = frame.normals.astype(np.float64) @ R.T
+    info = dict(frame.info or {})
+    info.update(repose_seed=seed, yaw=yaw, shift=tuple(shift))
+    return Frame(_f32(p), _f32(n), frame.weights.copy(), frame.dims, frame.bbox,
+                 name=frame.name + f"_repose{seed}", info=info)

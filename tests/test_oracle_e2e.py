@@ -93,3 +93,22 @@ def test_open_surface_flag_definition():
     r = np.sqrt(x * x + y * y + z * z)
     assert oracle.open_surface(0.6 - r, 0.0) is False
     assert oracle.open_surface(1.1 - r, 0.0) is True
+
+
+def test_threaded_oracle_matches_the_single_threaded_one():
+    """The all-cores configuration of the oracle (the benchmark's CPU
+    baseline) splits voxel planes and marching-cubes planes over threads
+    without changing any sum or numbering: splat and mesh are bit-identical;
+    the transforms (scipy's FFT with workers) agree to rounding."""
+    f = synth.sphere_frame(seed=6, m=8_000, grid=24)
+    V1, S1, D1, r1 = oracle.splat(f.points, f.normals, f.weights, f.dims, f.bbox)
+    V4, S4, D4, r4 = oracle.splat(f.points, f.normals, f.weights, f.dims, f.bbox, threads=4)
+    assert r1 == r4 and np.array_equal(S1, S4) and np.array_equal(D1, D4) and np.array_equal(V1, V4)
+    A1 = oracle.indicator(V1, f.dims, f.bbox)
+    A4 = oracle.indicator(V1, f.dims, f.bbox, threads=4)
+    assert np.abs(A1 - A4).max() <= 1e-12 * (A1.max() - A1.min())
+    L, _ = oracle.level(A1, f.points, f.dims, f.bbox)
+    v1, t1, c1 = oracle.extract(A1, L, f.dims, f.bbox)
+    v4, t4, c4 = oracle.extract(A1, L, f.dims, f.bbox, threads=4)
+    assert np.array_equal(v1, v4) and np.array_equal(t1, t4) and np.array_equal(c1, c4)
+    assert len(t1) > 1000

@@ -154,6 +154,95 @@ def _load_frame(synth, config, seed, cache):
     return f
 
 
+def bench_batch(args, fvr, synth, torch, np, dev):
+    """Batched workload: the same uneven frames through the plain
+    single-frame call (one synchronisation per frame) and through a batch
+    (one captured graph per launch, one synchronisation per batch)."""
+    print(f"[bench] batched workload: {args.batch} frames", file=sys.stderr, flush=True)
+    frames, _ = synth.batch_frames(args.batch, seed=4000)
+    devs = [tuple(torch.from_numpy(a).to(dev) for a in (f.points, f.normals, f.weights)) + (f.dims, f.bbox)
+            for f in frames]
+    vcap = 400_000
+    outs = [(torch.empty((vcap, 3), dtype=torch.float32, device=dev),
+             torch.empty((2 * vcap, 3), dtype=torch.int32, device=dev)) for _ in frames]
+    n = len(frames)
+    reps = max(1, args.steps // n)
+    ctx = fvr.Context(0)
+    tuned = {}
+    if args.autotune:
+        # the project's autotuner picks radix orders and splat tiles per grid
+        # shape on the first frame of each shape; every later call (plain and
+        # batched) uses them
+        from paper_1712_03084_amd import autotune
+        for i, f in enumerate(frames):
+            if f.dims in tuned:
+                continue
+            d = devs[i]
+            r = autotune.tune(ctx, d[0], d[1], d[2], f.dims, f.bbox, reps=10)
+            tuned[f.dims] = r
+            if args.tune_cache:
+                autotune.save_entry(f.dims, r, path=args.tune_cache)
+            print(f"[bench] autotune {f.dims}: {r['default_us']:.1f} -> {r['us']:.1f} us per frame "
+                  f"({r['tried']} tried) {r['params']}", file=sys.stderr, flush=True)
+    plain = [ctx.prepare(d[0], d[1], d[2], grid_dim=d[3], bbox=d[4], out=o) for d, o in zip(devs, outs)]
+    for p in plain:
+        p.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p in plain:
+            p.run()
+    torch.cuda.synchronize()
+    plain_fps = reps * n / (time.perf_counter() - t0)
+    sweep = {}
+    best = None
+    for slots in [int(x) for x in args.batch_slots.split(",") if x]:
+        b = fvr.Batch(slots=slots, graph=True)
+        pb = b.prepare(devs, outs)
+        for _ in range(2):
+            pb.run()  # capture, then a replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pb.run()
+        fps = reps * n / (time.perf_counter() - t0)
+        sweep[slots] = round(fps, 2)
+        if best is None or fps > best[1]:
+            best = (slots, fps, b, pb)
+        else:
+            b.close()
+    slots, fps, b, pb = best
+    lat = []
+    for _ in range(max(args.latency_frames, args.steps)):
+        ts = time.perf_counter()
+        pb.run()
+        lat.append(time.perf_counter() - ts)
+    lat = np.asarray(lat) * 1e3
+    # the graph-free form of the same batch
+    b.use_graph(False)
+    pb2 = b.prepare(devs, outs)
+    pb2.run()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pb2.run()
+    nograph_fps = reps * n / (time.perf_counter() - t0)
+    b.close()
+    grids = [f.dims[0] for f in frames]
+    pts = [f.n_points for f in frames]
+    return {"workload": f"{n} human-proxy frames of 2-6 views, grids from {{96,128,160,192}}^3 "
+                        f"({grids}), {min(pts)}-{max(pts)} points",
+            "frames": n, "unit": "frames/s",
+            "plain_value": round(plain_fps, 2),
+            "batched_value": round(fps, 2), "slots": slots, "slots_sweep": sweep,
+            "batched_no_graph_value": round(nograph_fps, 2),
+            "batch_p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "batch_p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "batch_latency_samples": len(lat),
+            "alg_bytes_per_batch": sum(frame_alg_bytes(f.dims, f.n_points, 0, 0) for f in frames),
+            "autotuned": {"x".join(map(str, k)): {"params": v["params"], "default_us": v["default_us"],
+                                                  "tuned_us": v["us"]} for k, v in tuned.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +257,14 @@ def main():
     ap.add_argument("--secondary", default="proxy128",
                     help="comma-separated workloads measured after the headline one and reported "
                          "under 'secondary' (empty: none)")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="frames of the batched workload (16 uneven frames on {96..192}^3 grids) "
+                         "measured after the headline one, batched and plain (0: skip)")
+    ap.add_argument("--batch-slots", default="1,2,4,8,16",
+                    help="slot counts of the batched measurement; the fastest is reported")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="measure the batched workload on the default plans")
+    ap.add_argument("--tune-cache", default=None, help="JSON file the autotuner's choices are added to")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the all-cores CPU baseline (0: the host's CPUs, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -366,6 +463,9 @@ def main():
         del sprep
     if sec:
         result["secondary"] = sec
+
+    if args.batch > 0:
+        result["batched"] = bench_batch(args, fvr, synth, torch, np, dev)
 
     if not args.no_cpu_baseline:
         # the oracle as it stands (FP64), on whole frames of the same workload:

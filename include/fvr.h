@@ -151,6 +151,31 @@ fvr_status fvr_extract(fvr_ctx *ctx, const float *field, const int32_t dims[3],
  * component-major) written by the same splat kernel the path uses. */
 fvr_status fvr_debug_splat(fvr_ctx *ctx, const fvr_frame *frame, float *v_out);
 
+/* Batches: several frames as one unit of device work (Sec. III-B per
+ * frame).  A batch owns `slots` contexts, each with its own scratch, status
+ * block and stream (default priority); frame i runs on slot i mod slots, so
+ * frames of different slots overlap on the device.  fvr_batch_reconstruct
+ * captures the fork from the batch's stream to the slot streams, every
+ * frame's stages and the join into one HIP graph, launches it and waits
+ * once; a later call with the same frames (fields and pointers), outputs
+ * and scratch replays the instantiated graph without capturing (up to 8
+ * graphs are kept).  `hip_stream` is the stream the batch forks from (NULL:
+ * a stream the batch makes; the null stream cannot be captured).  Each
+ * frame's result is the one fvr_reconstruct gives for it, bit for bit.
+ * Inputs and outputs are borrowed as for fvr_reconstruct.  All frames are
+ * checked, and every slot's scratch grown, before anything is enqueued.
+ * Returns the first frame error (FVR_E_CAPACITY: that mesh holds the
+ * required counts); every mesh is filled.  A batch is used by one host
+ * thread at a time. */
+typedef struct fvr_batch fvr_batch;
+fvr_status fvr_batch_create(int device, void *hip_stream, int slots, fvr_batch **out);
+void fvr_batch_destroy(fvr_batch *batch);
+fvr_status fvr_batch_set_stream(fvr_batch *batch, void *hip_stream);
+/* enable = 0: enqueue the same work directly, without a graph */
+fvr_status fvr_batch_use_graph(fvr_batch *batch, int enable);
+fvr_status fvr_batch_reconstruct(fvr_batch *batch, const fvr_frame *frames, fvr_mesh *meshes, int n);
+const char *fvr_batch_last_error(const fvr_batch *batch);
+
 /* Work counters of the context's last completed fvr_reconstruct,
  * fvr_reconstruct_noalloc or fvr_indicator call, from the status block that
  * call read back (no device work): how much of the grid the sparse passes
@@ -163,6 +188,26 @@ typedef struct {
     int64_t points_used, points_rejected; /* accepted points in the level, points outside the bbox */
 } fvr_stats;
 fvr_status fvr_last_stats(const fvr_ctx *ctx, fvr_stats *out);
+
+/* Plan parameters of one grid shape, as chosen by an autotuner: the radix
+ * order of each axis's mixed-radix (Stockham) passes - radices from
+ * {2, 3, 4, 5, 8} whose product is the axis length, at most 8 stages;
+ * nstages 0 keeps the default order (8s first, then a 4 or 2, 3s, 5s) - and
+ * the splat tile of ty x tz full x-rows (0 x 0 keeps the default; ty tz even,
+ * ty tz Nx <= 2048, (ty + 3)(tz + 3) <= 128).  Lengths 16..256 that are
+ * powers of two run register pencils whose schedule is fixed.  The radix
+ * order changes the rounding of the transforms, not what they compute. */
+typedef struct {
+    int32_t nstages[3];
+    int32_t radices[3][8];
+    int32_t splat_ty, splat_tz;
+} fvr_tuning;
+/* Set (t != NULL) or clear (t == NULL) the tuning of grid shape `dims` for
+ * the whole process: every context and batch builds its plans from it from
+ * the next call on.  FVR_E_INVALID if a parameter does not fit. */
+fvr_status fvr_set_tuning(const int32_t dims[3], const fvr_tuning *t);
+/* The parameters plans of shape `dims` use now (tuned or default). */
+fvr_status fvr_get_tuning(const int32_t dims[3], fvr_tuning *t);
 
 /* Host-only helpers (no device work; callable without a GPU). */
 /* Check dims and bbox as fvr_reconstruct would. */

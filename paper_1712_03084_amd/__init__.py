@@ -21,7 +21,8 @@ import os
 from collections import namedtuple
 
 __all__ = [
-    "FvrError", "FvrUnavailable", "Context", "PreparedFrame", "Mesh", "reconstruct", "indicator",
+    "FvrError", "FvrUnavailable", "Context", "PreparedFrame", "Batch", "PreparedBatch", "Mesh",
+    "reconstruct", "indicator",
     "extract", "debug_splat", "mc_table", "check_grid", "check_frame", "library_path", "load_library",
     "STATUS",
 ]
@@ -95,6 +96,14 @@ def load_library():
     lib.fvr_check_grid.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
     lib.fvr_check_frame.argtypes = [ctypes.POINTER(_Frame)]
     lib.fvr_last_stats.argtypes = [P, ctypes.POINTER(_Stats)]
+    lib.fvr_batch_create.argtypes = [I, P, I, ctypes.POINTER(P)]
+    lib.fvr_batch_destroy.argtypes = [P]
+    lib.fvr_batch_destroy.restype = None
+    lib.fvr_batch_set_stream.argtypes = [P, P]
+    lib.fvr_batch_use_graph.argtypes = [P, I]
+    lib.fvr_batch_reconstruct.argtypes = [P, ctypes.POINTER(_Frame), ctypes.POINTER(_Mesh), I]
+    lib.fvr_batch_last_error.argtypes = [P]
+    lib.fvr_batch_last_error.restype = ctypes.c_char_p
     lib.fvr_mc_table.argtypes = [P, P]
     lib.fvr_timing_enable.argtypes = [P, I]
     lib.fvr_timing_select.argtypes = [P, ctypes.c_uint32]
@@ -110,7 +119,8 @@ def load_library():
     for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_reconstruct_noalloc",
                "fvr_indicator", "fvr_extract",
                "fvr_debug_splat", "fvr_check_grid", "fvr_check_frame", "fvr_last_stats", "fvr_mc_table",
-               "fvr_timing_enable",
+               "fvr_timing_enable", "fvr_batch_create", "fvr_batch_set_stream", "fvr_batch_use_graph",
+               "fvr_batch_reconstruct",
                "fvr_timing_select", "fvr_timing_reset", "fvr_timing_get"):
         getattr(lib, fn).restype = I
     _lib = lib
@@ -471,3 +481,96 @@ def extract(field, bbox, level, with_cases=False, **kw):
 def debug_splat(points, normals, weights=None, grid_dim=(128, 128, 128),
                 bbox=((-1, -1, -1), (1, 1, 1))):
     return _ctx(points.device.index).debug_splat(points, normals, weights, grid_dim, bbox)
+
+
+class Batch:
+    """An fvr_batch: frames reconstructed together as one captured HIP graph
+    over ``slots`` per-slot contexts (scratch, status, stream each), frame i
+    on slot i mod slots.  Each frame's mesh is the one ``Context.reconstruct``
+    gives for it, bit for bit."""
+
+    def __init__(self, slots: int = 4, device: int | None = None, graph: bool = True):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        st = self.lib.fvr_batch_create(self.device, None, int(slots), ctypes.byref(h))
+        if st:
+            raise FvrError(st, (self.lib.fvr_batch_last_error(None) or b"").decode())
+        self.handle = h
+        self.slots = int(slots)
+        self.use_graph(graph)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fvr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def use_graph(self, enable: bool):
+        self._check(self.lib.fvr_batch_use_graph(self.handle, 1 if enable else 0))
+
+    def _check(self, st):
+        if st:
+            raise FvrError(st, (self.lib.fvr_batch_last_error(self.handle) or b"").decode())
+
+    def prepare(self, frames, outs):
+        """Marshal a list of frames once: ``frames`` holds (points, normals,
+        weights, grid_dim, bbox) tuples of device tensors, ``outs`` the
+        (vertices, triangles) buffers of each.  Returns a PreparedBatch whose
+        ``run()`` reconstructs them all (the same call each time, so the
+        captured graph is replayed)."""
+        return PreparedBatch(self, frames, outs)
+
+    def reconstruct(self, frames, outs):
+        """One batch call; returns the list of Mesh results."""
+        pb = self.prepare(frames, outs)
+        pb.run()
+        return pb.meshes()
+
+
+class PreparedBatch:
+    def __init__(self, batch, frames, outs):
+        if len(frames) != len(outs):
+            raise ValueError("one (vertices, triangles) pair per frame")
+        self._batch = batch
+        n = len(frames)
+        self._n = n
+        self._frames = (_Frame * max(n, 1))()
+        self._meshes = (_Mesh * max(n, 1))()
+        self._keep = []
+        helper = Context.__new__(Context)  # marshalling only: no fvr_ctx is made
+        helper.device = batch.device
+        for i, (fr, (verts, tris)) in enumerate(zip(frames, outs)):
+            points, normals, weights, grid_dim, bbox = fr
+            f, keep = Context._frame(helper, points, normals, weights, grid_dim, bbox)
+            self._frames[i] = f
+            self._keep.append((keep, verts, tris))
+            m = self._meshes[i]
+            m.vertices = verts.data_ptr()
+            m.triangles = tris.data_ptr()
+            m.vertex_capacity = verts.shape[0]
+            m.triangle_capacity = tris.shape[0]
+
+    def run(self):
+        torch = _torch()
+        b = self._batch
+        # the batch forks from a stream of its own: work already queued on
+        # torch's stream (uploads of the inputs) must be complete first
+        torch.cuda.current_stream(b.device).synchronize()
+        b._check(b.lib.fvr_batch_reconstruct(b.handle, self._frames, self._meshes, self._n))
+        return [(m.n_vertices, m.n_triangles) for m in self._meshes[:self._n]]
+
+    def meshes(self):
+        out = []
+        for i in range(self._n):
+            m = self._meshes[i]
+            _, verts, tris = self._keep[i]
+            out.append(Mesh(verts[:m.n_vertices], tris[:m.n_triangles], m.level, int(m.n_rejected),
+                            bool(m.flags & FVR_FLAG_OPEN_SURFACE)))
+        return out

@@ -53,6 +53,7 @@ struct Plan {
     int dims[3];
     FftAxis ax[3];
     SplatConsts sc;
+    uint64_t tune_gen = 0;  // tuning table generation the plan was built from
 };
 
 // Radix schedule: as many 8s as possible, then a 4 or 2, then 3s and 5s
@@ -74,6 +75,17 @@ bool factor(int n, int rad[kMaxStages], int &ns) {
     return n == 1;
 }
 
+// Tuned plan parameters per grid shape (fvr_set_tuning), shared by every
+// context and batch of the process so that all paths compute the same bits.
+struct Tuning {
+    int radices[3][kMaxStages];
+    int nstages[3];  // 0: the default schedule for that axis
+    int splat_ty, splat_tz;  // 0: the default splat tile
+};
+std::mutex g_tune_mutex;
+std::map<std::array<int, 3>, Tuning> g_tuning;
+uint64_t g_tune_gen = 1;
+
 }  // namespace
 
 struct fvr_ctx {
@@ -85,6 +97,7 @@ struct fvr_ctx {
     unsigned char *arena = nullptr;  // non-null during such a call
     size_t arena_off = 0;
     uint64_t arena_epoch = 0;
+    uint64_t scratch_gen = 0;  // bumped whenever an owned buffer moves
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
         lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm, mc_list;
     DevStatus *host_status = nullptr;
@@ -135,8 +148,10 @@ hipError_t ensure(DevBuf &b, size_t bytes) {
 hipError_t get(fvr_ctx *c, DevBuf &b, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (!c->arena) {
+        void *before = b.p;
         hipError_t e = ensure(b, bytes);
         if (e == hipSuccess) b.view = b.p;
+        if (b.p != before) ++c->scratch_gen;  // captured graphs hold the old address
         b.epoch = 0;
         return e;
     }
@@ -247,13 +262,37 @@ Grid make_grid(const int32_t dims[3], const float bbox[6]) {
     return g;
 }
 
+// Default splat tile: ty x tz full x-rows, R = ty tz rows with R Nx within
+// the kernel's plane bound (4 <= R <= 64; Nx <= 512 keeps 4 rows in bound).
+void default_splat_tile(int nx, int &ty, int &tz) {
+    int R = 64;
+    while (R > 4 && R * nx > splat_max_plane()) R /= 2;
+    tz = R >= 64 ? 8 : R >= 32 ? 8 : R >= 16 ? 4 : R >= 8 ? 4 : 2;
+    ty = R / tz;
+}
+
 // Radix schedules, twiddles (the device's static table: nothing to allocate)
 // and splat tiling of a grid shape.
 fvr_status build_plan(fvr_ctx *c, const int32_t dims[3], Plan &np) {
     std::memcpy(np.dims, dims, sizeof(np.dims));
+    Tuning tu{};
+    bool tuned = false;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        auto it = g_tuning.find({dims[0], dims[1], dims[2]});
+        if (it != g_tuning.end()) {
+            tu = it->second;
+            tuned = true;
+        }
+        np.tune_gen = g_tune_gen;
+    }
     for (int a = 0; a < 3; ++a) {
         int r[kMaxStages], ns;
         if (!factor(dims[a], r, ns)) return fail(c, FVR_E_UNSUPPORTED, "grid dim must be 2^a 3^b 5^c");
+        if (tuned && tu.nstages[a] > 0) {  // a tuned radix order (validated when it was set)
+            ns = tu.nstages[a];
+            for (int k = 0; k < ns; ++k) r[k] = tu.radices[a][k];
+        }
         np.ax[a].n = dims[a];
         np.ax[a].nstages = ns;
         np.ax[a].radices = 0;
@@ -261,15 +300,21 @@ fvr_status build_plan(fvr_ctx *c, const int32_t dims[3], Plan &np) {
         np.ax[a].tw = statics_twiddles(c->device, dims[a]);
         if (!np.ax[a].tw) return fail(c, FVR_E_DEVICE, "twiddle table missing for this length");
     }
-    // splat tile: ty x tz full x-rows, R = ty tz rows with R Nx within the
-    // kernel's plane bound (4 <= R <= 64; Nx <= 512 keeps 4 rows in bound)
-    const int nx = dims[0];
-    int R = 64;
-    while (R > 4 && R * nx > splat_max_plane()) R /= 2;
-    np.sc.tz = R >= 64 ? 8 : R >= 32 ? 8 : R >= 16 ? 4 : R >= 8 ? 4 : 2;
-    np.sc.ty = R / np.sc.tz;
+    default_splat_tile(dims[0], np.sc.ty, np.sc.tz);
+    if (tuned && tu.splat_ty > 0) {
+        np.sc.ty = tu.splat_ty;
+        np.sc.tz = tu.splat_tz;
+    }
     np.sc.tiles_y = (dims[1] + np.sc.ty - 1) / np.sc.ty;
     return FVR_OK;
+}
+
+// A splat tile of ty x tz full x-rows fits the kernel: an even number of rows
+// (the x transform pairs rows of one channel), at most kSplatMaxPlane voxels
+// per channel, at most 128 footprint bins.
+bool splat_tile_ok(int nx, int ty, int tz) {
+    const int R = ty * tz;
+    return ty >= 1 && tz >= 1 && R % 2 == 0 && R * nx <= splat_max_plane() && (ty + 3) * (tz + 3) <= 128;
 }
 
 // Geometry-dependent splat constants (the bbox may change between calls).
@@ -292,6 +337,15 @@ fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan
     const std::array<int, 3> key = {dims[0], dims[1], dims[2]};
     auto it = c->plans.find(key);
     Plan *p;
+    uint64_t gen;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        gen = g_tune_gen;
+    }
+    if (it != c->plans.end() && it->second.tune_gen != gen) {  // the tuning changed
+        c->plans.erase(it);
+        it = c->plans.end();
+    }
     if (it == c->plans.end()) {
         Plan np;
         fvr_status r = build_plan(c, dims, np);
@@ -459,8 +513,11 @@ fvr_status run_level(fvr_ctx *c, const fvr_frame *f, const Grid &g, const float 
 // already be reset.  Fills mesh counts; writes arrays only if they fit.
 // With rowmm, level_nb > 0 says the level's level_nb block partials are still to
 // be reduced (run_level with final = false); the classification does it.
-fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *rowmm, fvr_mesh *mesh,
-                  uint8_t *cases_out, bool check_invalid, int level_nb = 0) {
+// Marching cubes enqueued; block 0 of mc_generate copies the final status
+// block to host_dst (pinned host memory).
+fvr_status enqueue_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *rowmm,
+                      const fvr_mesh *mesh, uint8_t *cases_out, bool check_invalid, int level_nb,
+                      DevStatus *host_dst) {
     const int nb = mc_blocks(g);
     const MeshCaps caps = mesh_caps(g, mesh, check_invalid);
     fvr_status r0 = mc_bufs(c, g, caps, rowmm != nullptr);
@@ -493,15 +550,16 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
     { Timed t(c, K_MC_GENERATE);
       HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
                                     P<int32_t>(c->mc_off), P<uint32_t>(c->mc_codes), mesh->vertices,
-                                    P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, c->host_status, s),
+                                    P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, host_dst, s),
               "mc_generate"); }
     { Timed t(c, K_MC_TRIANGLES);
       HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), P<int32_t>(c->vidx), g, mesh->triangles, st,
                                      caps, s), "mc_triangles"); }
-    // mc_generate copied the final status block to c->host_status
-    fvr_status r = sync(c);
-    if (r != FVR_OK) return r;
-    const DevStatus hs = *c->host_status;
+    return FVR_OK;
+}
+
+// The mesh counts, flags and errors of a finished frame from its status block.
+fvr_status finish_mesh(fvr_ctx *c, const DevStatus &hs, fvr_mesh *mesh, bool check_invalid) {
     if (check_invalid && (hs.flags & kFlagInvalid))
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
     mesh->n_vertices = hs.mc_total[0];
@@ -513,6 +571,46 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
     if (hs.mc_total[0] > 0 && !mesh->vertices) return fail(c, FVR_E_INVALID, "vertices is NULL");
     if (hs.mc_total[1] > 0 && !mesh->triangles) return fail(c, FVR_E_INVALID, "triangles is NULL");
     return FVR_OK;
+}
+
+// Marching cubes on `field` at the level in c->level_f32 (status block
+// already reset), waited for; fills the mesh counts.
+fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *rowmm, fvr_mesh *mesh,
+                  uint8_t *cases_out, bool check_invalid, int level_nb = 0) {
+    fvr_status r = enqueue_mc(c, g, field, rowmm, mesh, cases_out, check_invalid, level_nb, c->host_status);
+    if (r != FVR_OK) return r;
+    if ((r = sync(c)) != FVR_OK) return r;
+    const DevStatus hs = *c->host_status;
+    return finish_mesh(c, hs, mesh, check_invalid);
+}
+
+// All stages of one frame enqueued on c's stream (plan and scratch ready);
+// the final status block goes to host_dst.
+fvr_status enqueue_reconstruct(fvr_ctx *c, const fvr_frame *f, Plan *p, const fvr_mesh *mesh,
+                               DevStatus *host_dst) {
+    const Grid g = make_grid(f->dims, f->bbox);
+    fvr_status r;
+    GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
+    if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
+    // the fused inverse pass left each row's range of A: blocks of cells
+    // entirely on one side of the level skip the field, and their
+    // classification also finishes the level
+    const bool fused = fft_yx_fused(g);
+    const int level_nb = level_blocks((int)f->n_points);
+    if ((r = run_level(c, f, g, P<float>(c->field), !fused || level_nb == 0)) != FVR_OK) return r;
+    return enqueue_mc(c, g, P<float>(c->field), fused ? P<float2>(c->rowmm) : nullptr, mesh, nullptr, true,
+                      fused ? level_nb : 0, host_dst);
+}
+
+// Every scratch buffer of one frame, requested before anything is enqueued.
+fvr_status frame_bufs(fvr_ctx *c, const fvr_frame *f, const Plan *p, const fvr_mesh *mesh) {
+    const Grid g = make_grid(f->dims, f->bbox);
+    const int m = (int)f->n_points;
+    GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
+    fvr_status r;
+    if ((r = field_bufs(c, g, p, m)) != FVR_OK) return r;
+    if ((r = level_bufs(c, m)) != FVR_OK) return r;
+    return mc_bufs(c, g, mesh_caps(g, mesh, true), fft_yx_fused(g));
 }
 
 }  // namespace
@@ -586,18 +684,11 @@ fvr_status fvr_reconstruct(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mesh) {
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     Plan *p;
     if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
-    const Grid g = make_grid(f->dims, f->bbox);
-    GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
-    if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
-    // the fused inverse pass left each row's range of A: blocks of cells
-    // entirely on one side of the level skip the field, and their
-    // classification also finishes the level
-    const bool fused = fft_yx_fused(g);
-    const int level_nb = level_blocks((int)f->n_points);
-    if ((r = run_level(c, f, g, P<float>(c->field), !fused || level_nb == 0)) != FVR_OK) return r;
-    r = run_mc(c, g, P<float>(c->field), fused ? P<float2>(c->rowmm) : nullptr, mesh, nullptr, true,
-               fused ? level_nb : 0);
-    mesh->level = c->host_status->level;
+    if ((r = enqueue_reconstruct(c, f, p, mesh, c->host_status)) != FVR_OK) return r;
+    if ((r = sync(c)) != FVR_OK) return r;
+    const DevStatus hs = *c->host_status;
+    r = finish_mesh(c, hs, mesh, true);
+    mesh->level = hs.level;
     return r;
 }
 
@@ -632,19 +723,13 @@ fvr_status fvr_reconstruct_noalloc(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mes
     } call(c, arena);
     // carve every buffer of the path before anything is enqueued, so a frame
     // beyond the static scratch is refused without side effects
-    const int m = (int)f->n_points;
-    GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
-    if ((r = field_bufs(c, g, &plan, m)) != FVR_OK) return r;
-    if ((r = level_bufs(c, m)) != FVR_OK) return r;
-    const bool fused = fft_yx_fused(g);
-    if ((r = mc_bufs(c, g, mesh_caps(g, mesh, true), fused)) != FVR_OK) return r;
+    if ((r = frame_bufs(c, f, &plan, mesh)) != FVR_OK) return r;
     // the same stages as fvr_reconstruct on the carved buffers
-    if ((r = run_field(c, f, &plan, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
-    const int level_nb = level_blocks(m);
-    if ((r = run_level(c, f, g, P<float>(c->field), !fused || level_nb == 0)) != FVR_OK) return r;
-    r = run_mc(c, g, P<float>(c->field), fused ? P<float2>(c->rowmm) : nullptr, mesh, nullptr, true,
-               fused ? level_nb : 0);
-    mesh->level = c->host_status->level;
+    if ((r = enqueue_reconstruct(c, f, &plan, mesh, c->host_status)) != FVR_OK) return r;
+    if ((r = sync(c)) != FVR_OK) return r;
+    const DevStatus hs = *c->host_status;
+    r = finish_mesh(c, hs, mesh, true);
+    mesh->level = hs.level;
     return r;
 }
 
@@ -713,6 +798,255 @@ fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
     return FVR_OK;
 }
 
+}  // extern "C"
+
+// A batch runs several frames as one unit of device work: frame i goes to
+// slot i mod S, each slot a context of its own (scratch, status block and a
+// stream of default priority), so frames of different slots overlap on the
+// device.  The whole batch - a fork from the caller's stream to the slot
+// streams, every frame's stages, a join - is captured once into a HIP graph
+// and launched as one; a later batch with the same frames, outputs and
+// scratch addresses replays the instantiated graph without capturing.
+struct fvr_batch {
+    int device = 0;
+    hipStream_t origin = nullptr;
+    hipStream_t own_origin = nullptr;  // made by the batch when the caller gave none
+    std::vector<fvr_ctx *> slots;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    DevStatus *host_st = nullptr;  // pinned, one status block per frame
+    int host_cap = 0;
+    int use_graph = 1;
+    std::string err;
+    struct Cached {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Cached> graphs;  // most recent last
+};
+
+namespace {
+
+constexpr size_t kMaxCachedGraphs = 8;
+
+fvr_status bfail(fvr_batch *b, fvr_status s, const std::string &msg) {
+    if (b) b->err = msg;
+    g_error = msg;
+    return s;
+}
+
+fvr_status bhip(fvr_batch *b, hipError_t e, const char *what) {
+    return bfail(b, e == hipErrorOutOfMemory ? FVR_E_NOMEM : FVR_E_DEVICE,
+                 std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void drop_graphs(fvr_batch *b) {
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
+
+// Everything a captured graph depends on: the frames and outputs, the
+// status array, and the scratch generation of every slot.
+std::vector<unsigned char> batch_key(const fvr_batch *b, const fvr_frame *frames, const fvr_mesh *meshes,
+                                     int n) {
+    std::vector<unsigned char> k;
+    auto put = [&](const void *p, size_t len) {
+        const unsigned char *q = static_cast<const unsigned char *>(p);
+        k.insert(k.end(), q, q + len);
+    };
+    put(&n, sizeof(n));
+    put(&b->host_st, sizeof(b->host_st));
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        put(&g_tune_gen, sizeof(g_tune_gen));
+    }
+    for (fvr_ctx *c : b->slots) put(&c->scratch_gen, sizeof(c->scratch_gen));
+    for (int i = 0; i < n; ++i) {
+        put(&frames[i], sizeof(fvr_frame));
+        put(&meshes[i].vertices, sizeof(meshes[i].vertices));
+        put(&meshes[i].triangles, sizeof(meshes[i].triangles));
+        put(&meshes[i].vertex_capacity, sizeof(int64_t));
+        put(&meshes[i].triangle_capacity, sizeof(int64_t));
+    }
+    return k;
+}
+
+// Fork, every frame's stages on its slot's stream, join.
+fvr_status batch_enqueue(fvr_batch *b, const fvr_frame *frames, fvr_mesh *meshes, int n,
+                         std::vector<Plan *> &plans) {
+    const int S = (int)b->slots.size();
+    hipError_t e = hipEventRecord(b->fork, b->origin);
+    if (e != hipSuccess) return bhip(b, e, "batch fork");
+    for (int k = 0; k < S && k < n; ++k)
+        if ((e = hipStreamWaitEvent(b->slots[k]->stream, b->fork, 0)) != hipSuccess) return bhip(b, e, "batch fork");
+    for (int i = 0; i < n; ++i) {
+        fvr_ctx *c = b->slots[i % S];
+        fvr_status r = enqueue_reconstruct(c, &frames[i], plans[i], &meshes[i], b->host_st + i);
+        if (r != FVR_OK) return bfail(b, r, c->err);
+    }
+    for (int k = 0; k < S && k < n; ++k) {
+        if ((e = hipEventRecord(b->join[k], b->slots[k]->stream)) != hipSuccess) return bhip(b, e, "batch join");
+        if ((e = hipStreamWaitEvent(b->origin, b->join[k], 0)) != hipSuccess) return bhip(b, e, "batch join");
+    }
+    return FVR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fvr_status fvr_batch_create(int device, void *hip_stream, int slots, fvr_batch **out) {
+    if (!out) return bfail(nullptr, FVR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (slots < 1 || slots > 64) return bfail(nullptr, FVR_E_INVALID, "slots must be in 1..64");
+    fvr_batch *b = new fvr_batch();
+    b->device = device;
+    b->origin = (hipStream_t)hip_stream;
+    for (int k = 0; k < slots; ++k) {
+        fvr_ctx *c = nullptr;
+        fvr_status r = fvr_create(device, nullptr, &c);
+        hipStream_t st = nullptr;
+        hipError_t e = r == FVR_OK ? hipStreamCreateWithFlags(&st, hipStreamNonBlocking) : hipSuccess;
+        hipEvent_t ev = nullptr;
+        if (r == FVR_OK && e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (r != FVR_OK || e != hipSuccess) {
+            if (st) (void)hipStreamDestroy(st);
+            if (c) fvr_destroy(c);
+            fvr_batch_destroy(b);
+            return r != FVR_OK ? r : bhip(nullptr, e, "batch stream");
+        }
+        c->stream = st;
+        b->slots.push_back(c);
+        b->join.push_back(ev);
+    }
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    // the null stream cannot be captured: without a caller stream the batch
+    // forks from a stream of its own
+    if (e == hipSuccess && !b->origin) {
+        e = hipStreamCreateWithFlags(&b->own_origin, hipStreamNonBlocking);
+        b->origin = b->own_origin;
+    }
+    if (e != hipSuccess) {
+        fvr_batch_destroy(b);
+        return bhip(nullptr, e, "batch event");
+    }
+    *out = b;
+    return FVR_OK;
+}
+
+void fvr_batch_destroy(fvr_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    for (fvr_ctx *c : b->slots) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(b);
+    for (fvr_ctx *c : b->slots) {
+        hipStream_t st = c->stream;
+        fvr_destroy(c);
+        if (st) (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->host_st) (void)hipHostFree(b->host_st);
+    if (b->own_origin) (void)hipStreamDestroy(b->own_origin);
+    delete b;
+}
+
+fvr_status fvr_batch_set_stream(fvr_batch *b, void *hip_stream) {
+    if (!b) return bfail(nullptr, FVR_E_INVALID, "batch is NULL");
+    b->origin = hip_stream ? (hipStream_t)hip_stream : b->own_origin;
+    if (!b->origin) {
+        hipError_t e = hipStreamCreateWithFlags(&b->own_origin, hipStreamNonBlocking);
+        if (e != hipSuccess) return bhip(b, e, "batch stream");
+        b->origin = b->own_origin;
+    }
+    drop_graphs(b);
+    return FVR_OK;
+}
+
+fvr_status fvr_batch_use_graph(fvr_batch *b, int enable) {
+    if (!b) return bfail(nullptr, FVR_E_INVALID, "batch is NULL");
+    b->use_graph = enable ? 1 : 0;
+    return FVR_OK;
+}
+
+fvr_status fvr_batch_reconstruct(fvr_batch *b, const fvr_frame *frames, fvr_mesh *meshes, int n) {
+    if (!b) return bfail(nullptr, FVR_E_INVALID, "batch is NULL");
+    if (n < 0 || (n > 0 && (!frames || !meshes))) return bfail(b, FVR_E_INVALID, "frames or meshes is NULL");
+    if (n == 0) return FVR_OK;
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return bhip(b, e, "hipSetDevice");
+    const int S = (int)b->slots.size();
+    // host checks, plans and every slot's scratch, all before any enqueue
+    std::vector<Plan *> plans((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        fvr_ctx *c = b->slots[i % S];
+        fvr_status r = check_frame(c, &frames[i]);
+        if (r == FVR_OK) r = get_plan(c, frames[i].dims, frames[i].bbox, &plans[i]);
+        if (r == FVR_OK) r = frame_bufs(c, &frames[i], plans[i], &meshes[i]);
+        if (r != FVR_OK) return bfail(b, r, std::string("frame ") + std::to_string(i) + ": " + c->err);
+    }
+    if (n > b->host_cap) {
+        drop_graphs(b);
+        if (b->host_st) (void)hipHostFree(b->host_st);
+        b->host_st = nullptr;
+        b->host_cap = 0;
+        if ((e = hipHostMalloc((void **)&b->host_st, sizeof(DevStatus) * (size_t)n)) != hipSuccess)
+            return bhip(b, e, "batch status blocks");
+        b->host_cap = n;
+    }
+    if (b->use_graph) {
+        std::vector<unsigned char> key = batch_key(b, frames, meshes, n);
+        hipGraphExec_t exec = nullptr;
+        for (size_t k = 0; k < b->graphs.size(); ++k)
+            if (b->graphs[k].key == key) {
+                exec = b->graphs[k].exec;
+                std::rotate(b->graphs.begin() + k, b->graphs.begin() + k + 1, b->graphs.end());
+                break;
+            }
+        if (!exec) {
+            if ((e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return bhip(b, e, "hipStreamBeginCapture");
+            fvr_status r = batch_enqueue(b, frames, meshes, n, plans);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(b->origin, &graph);
+            if (r != FVR_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return r;
+            }
+            if (e != hipSuccess) return bhip(b, e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return bhip(b, e, "hipGraphInstantiate");
+            if (b->graphs.size() == kMaxCachedGraphs) {
+                (void)hipGraphExecDestroy(b->graphs.front().exec);
+                b->graphs.erase(b->graphs.begin());
+            }
+            b->graphs.push_back({std::move(key), exec});
+        }
+        if ((e = hipGraphLaunch(exec, b->origin)) != hipSuccess) return bhip(b, e, "hipGraphLaunch");
+    } else {
+        fvr_status r = batch_enqueue(b, frames, meshes, n, plans);
+        if (r != FVR_OK) return r;
+    }
+    if ((e = hipStreamSynchronize(b->origin)) != hipSuccess) return bhip(b, e, "hipStreamSynchronize");
+    // per-frame results; the first error is returned, every mesh is filled
+    fvr_status first = FVR_OK;
+    for (int i = 0; i < n; ++i) {
+        fvr_ctx *c = b->slots[i % S];
+        const DevStatus hs = b->host_st[i];
+        fvr_status r = finish_mesh(c, hs, &meshes[i], true);
+        meshes[i].level = hs.level;
+        if (r != FVR_OK && first == FVR_OK) {
+            first = r;
+            b->err = std::string("frame ") + std::to_string(i) + ": " + c->err;
+        }
+    }
+    if (first != FVR_OK) g_error = b->err;
+    return first;
+}
+
+const char *fvr_batch_last_error(const fvr_batch *b) { return b ? b->err.c_str() : g_error.c_str(); }
+
 fvr_status fvr_last_stats(const fvr_ctx *c, fvr_stats *out) {
     if (!c || !out) return fail(nullptr, FVR_E_INVALID, "context or out is NULL");
     *out = c->last;
@@ -722,6 +1056,74 @@ fvr_status fvr_last_stats(const fvr_ctx *c, fvr_stats *out) {
     if (out->mc_blocks_listed < 0) out->mc_blocks_listed = h.mc_active;
     out->points_used = h.n_used;
     out->points_rejected = h.rejected;
+    return FVR_OK;
+}
+
+fvr_status fvr_set_tuning(const int32_t dims[3], const fvr_tuning *t) {
+    if (!dims) return fail(nullptr, FVR_E_INVALID, "dims is NULL");
+    const float unit_box[6] = {0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
+    fvr_status r = check_grid(nullptr, dims, unit_box);
+    if (r != FVR_OK) return r;
+    const std::array<int, 3> key = {dims[0], dims[1], dims[2]};
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    ++g_tune_gen;
+    if (!t) {
+        g_tuning.erase(key);
+        return FVR_OK;
+    }
+    Tuning tu{};
+    for (int a = 0; a < 3; ++a) {
+        const int ns = t->nstages[a];
+        if (ns < 0 || ns > kMaxStages) return fail(nullptr, FVR_E_INVALID, "nstages out of range");
+        int prod = 1;
+        for (int k = 0; k < ns; ++k) {
+            const int rad = t->radices[a][k];
+            if (rad != 2 && rad != 3 && rad != 4 && rad != 5 && rad != 8)
+                return fail(nullptr, FVR_E_INVALID, "radix must be 2, 3, 4, 5 or 8");
+            prod *= rad;
+            tu.radices[a][k] = rad;
+        }
+        if (ns > 0 && prod != dims[a]) return fail(nullptr, FVR_E_INVALID, "radices do not multiply to the dim");
+        tu.nstages[a] = ns;
+    }
+    if (t->splat_ty || t->splat_tz) {
+        if (!splat_tile_ok(dims[0], t->splat_ty, t->splat_tz))
+            return fail(nullptr, FVR_E_INVALID, "splat tile does not fit the kernel");
+        tu.splat_ty = t->splat_ty;
+        tu.splat_tz = t->splat_tz;
+    }
+    g_tuning[key] = tu;
+    return FVR_OK;
+}
+
+fvr_status fvr_get_tuning(const int32_t dims[3], fvr_tuning *t) {
+    if (!dims || !t) return fail(nullptr, FVR_E_INVALID, "dims or out is NULL");
+    const float unit_box[6] = {0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
+    fvr_status r = check_grid(nullptr, dims, unit_box);
+    if (r != FVR_OK) return r;
+    // the plan's parameters: tuned where set, the defaults otherwise
+    std::memset(t, 0, sizeof(*t));
+    for (int a = 0; a < 3; ++a) {
+        int rr[kMaxStages], ns;
+        factor(dims[a], rr, ns);
+        t->nstages[a] = ns;
+        for (int k = 0; k < ns; ++k) t->radices[a][k] = rr[k];
+    }
+    default_splat_tile(dims[0], t->splat_ty, t->splat_tz);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tuning.find({dims[0], dims[1], dims[2]});
+    if (it != g_tuning.end()) {
+        const Tuning &tu = it->second;
+        for (int a = 0; a < 3; ++a)
+            if (tu.nstages[a] > 0) {
+                t->nstages[a] = tu.nstages[a];
+                for (int k = 0; k < tu.nstages[a]; ++k) t->radices[a][k] = tu.radices[a][k];
+            }
+        if (tu.splat_ty > 0) {
+            t->splat_ty = tu.splat_ty;
+            t->splat_tz = tu.splat_tz;
+        }
+    }
     return FVR_OK;
 }
 

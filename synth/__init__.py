@@ -39,6 +39,9 @@ __all__ = [
     "isolated_weights_frame",
     "spread_weights",
     "repose",
+    "subsample",
+    "batch_frames",
+    "BATCH_GRIDS",
 ]
 
 
@@ -444,3 +447,44 @@ def repose(frame: Frame, seed: int, max_shift: float = 0.05) -> Frame:
     info.update(repose_seed=seed, yaw=yaw, shift=tuple(shift))
     return Frame(_f32(p), _f32(n), frame.weights.copy(), frame.dims, frame.bbox,
                  name=frame.name + f"_repose{seed}", info=info)
+
+
+def subsample(frame: Frame, m: int, seed: int) -> Frame:
+    """``m`` of the frame's points (seeded, without replacement, original
+    order kept), or all of them if it has fewer."""
+    if frame.n_points <= m:
+        return frame
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(frame.n_points, size=m, replace=False))
+    return Frame(frame.points[idx], frame.normals[idx], frame.weights[idx], frame.dims, frame.bbox,
+                 name=frame.name + f"_m{m}", info=frame.info)
+
+
+# Batched workload: 16 frames of uneven size.
+BATCH_GRIDS = (96, 128, 160, 192)
+_BATCH_CAPTURES = ((2, 7), (4, 5), (6, 4))  # (views, supersampling): >= 800k samples each
+
+
+def batch_frames(n: int = 16, seed: int = 4000, captures: dict | None = None):
+    """Frames of the batched workload: frame f draws (seeded by seed + f) a
+    capture of 2, 4 or 6 views of the human proxy, a point count
+    M ~ U[100k, 800k], a grid from {96, 128, 160, 192}^3 and a repose of the
+    rig (yaw and shift), over the same 2.0 m box.  The three captures are
+    ray-cast once (seeds seed + views; at 4x4 to 6x6 rays per depth pixel so
+    that each holds at least 800k samples) and passed in ``captures`` to
+    reuse them.  Returns (frames, captures)."""
+    if captures is None:
+        captures = {v: human_proxy_frame(seed=seed + v, views=v, m=None, grid=128, ss=ss)
+                    for v, ss in _BATCH_CAPTURES}
+    views = sorted(captures)
+    out = []
+    for f in range(n):
+        rng = np.random.default_rng(seed + f)
+        v = views[int(rng.integers(0, len(views)))]
+        m = int(rng.integers(100_000, 800_001))
+        g = int(BATCH_GRIDS[int(rng.integers(0, len(BATCH_GRIDS)))])
+        fr = repose(subsample(captures[v], m, seed=seed + 100 + f), seed=seed + 200 + f)
+        out.append(Frame(fr.points, fr.normals, fr.weights, (g, g, g), fr.bbox,
+                         name=f"batch{seed}_{f}_{v}v_{g}_{fr.n_points}",
+                         info={"views": v, "m": fr.n_points, "grid": g}))
+    return out, captures

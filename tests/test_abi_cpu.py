@@ -93,3 +93,34 @@ def test_bench_covers_every_timed_kernel():
     priced = set(bench.kernel_alg_bytes((256, 256, 256), 700_000, 40_000, 80_000))
     assert priced <= names, priced - names
     assert names - priced <= {"prep", "mc_scan"}, names - priced
+
+
+def test_tuning_set_get_and_validation():
+    """Plan parameters set for a grid shape come back from fvr_get_tuning;
+    parameters that do not fit the kernels are refused; clearing restores
+    the defaults (host-only calls)."""
+    from paper_1712_03084_amd import autotune as at
+    d = (96, 160, 192)
+    default = at.get_tuning(d)
+    assert default["radices"][0] == [8, 4, 3] and default["radices"][1] == [8, 4, 5]
+    t = {"radices": [[3, 8, 4], [], [2, 4, 8, 3]], "splat_tile": [2, 2]}
+    at.set_tuning(d, t)
+    got = at.get_tuning(d)
+    assert got["radices"][0] == [3, 8, 4] and got["radices"][1] == [8, 4, 5]
+    assert got["radices"][2] == [2, 4, 8, 3] and got["splat_tile"] == [2, 2]
+    for bad in ({"radices": [[8, 4, 4], [], []]},            # product is not Nx
+                {"radices": [[6, 16], [], []]},               # radix outside {2,3,4,5,8}
+                {"radices": [[], [], []], "splat_tile": [1, 3]},    # odd row count
+                {"radices": [[], [], []], "splat_tile": [16, 4]},   # 64 rows x 96 > 2048 voxels
+                {"radices": [[2] * 5 + [3], [], []]}):        # fine (6 stages): accepted
+        if bad.get("radices")[0] == [2] * 5 + [3]:
+            at.set_tuning(d, bad)
+            continue
+        with pytest.raises(fvr.FvrError):
+            at.set_tuning(d, bad)
+    at.set_tuning(d, None)
+    assert at.get_tuning(d) == default
+    cand = at.candidates((96, 128, 160))
+    assert [8, 4, 3] in cand["radices"][0] and [3, 4, 8] in cand["radices"][0]
+    assert cand["radices"][1] == [[8, 8, 2]]          # y = 128 runs a fixed pencil
+    assert [4, 4] in cand["splat_tile"]

@@ -83,7 +83,15 @@ typedef struct {
     int64_t n_points;     /* 0 <= M <= FVR_MAX_POINTS, else FVR_E_INVALID */
     int32_t dims[3];      /* Nx, Ny, Nz: each even, 8..512, 2^a 3^b 5^c */
     float bbox[6];        /* xmin, ymin, zmin, xmax, ymax, zmax (max > min) */
+    uint32_t options;     /* FVR_SPLAT_* bits; 0: the weighted splat of eqs. (1)-(2) */
 } fvr_frame;
+
+/* fvr_frame.options: the non-weighted splat of Sec. III-B ("simplest
+ * version"): each point's normal goes to its nearest voxel (the grid cell
+ * that contains it: floor((X - bmin)/h) in float32, clamped to the grid)
+ * and V is the mean of the normals that land in a voxel (0 where none do);
+ * weights are ignored (still validated). */
+#define FVR_SPLAT_NEAREST 1u
 
 typedef struct {
     float *vertices;            /* out: capacity x 3 */
@@ -95,6 +103,12 @@ typedef struct {
     double level;               /* out: iso-level L */
     int64_t n_rejected;         /* out: points outside the bbox (not an error) */
     uint32_t flags;             /* out: FVR_FLAG_* */
+    float *normals;             /* out, optional (NULL: not computed): vertex_capacity x 3
+                                   unit vertex normals -grad A (Sec. III-B lists normals
+                                   among the mesh outputs): central differences of A at the
+                                   edge's two grid points (one-sided on the grid's outer
+                                   layer), interpolated with the vertex's t, normalised;
+                                   written with the vertices */
 } fvr_mesh;
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`

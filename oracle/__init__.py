@@ -32,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fvr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-__all__ = ["build", "splat", "indicator", "level", "mc_table", "extract",
+__all__ = ["build", "splat", "splat_nearest", "indicator", "level", "mc_table", "extract",
            "reconstruct", "geometry", "open_surface"]
 
 
@@ -60,10 +60,12 @@ def _load():
         i64 = ctypes.c_int64
         lib.oracle_splat.argtypes = [P, P, P, i64, P, P, P, P, P, ctypes.c_int]
         lib.oracle_splat.restype = i64
+        lib.oracle_splat_nearest.argtypes = [P, P, i64, P, P, P, P, P]
+        lib.oracle_splat_nearest.restype = i64
         lib.oracle_level.argtypes = [P, P, P, P, i64, P]
         lib.oracle_level.restype = ctypes.c_double
         lib.oracle_marching_cubes.argtypes = [P, P, P, ctypes.c_double, P, P,
-                                              P, i64, P, i64, P, P, P, ctypes.c_int]
+                                              P, i64, P, i64, P, P, P, ctypes.c_int, P]
         lib.oracle_marching_cubes.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -104,6 +106,22 @@ def splat(points, normals, weights, dims, bbox, threads: int = 1):
     rej = lib.oracle_splat(_ptr(p), _ptr(nrm), _ptr(w), m, _ptr(d), _ptr(b),
                            _ptr(S), _ptr(D), _ptr(V), int(threads))
     return V, S, D, int(rej)
+
+
+def splat_nearest(points, normals, dims, bbox):
+    """The non-weighted splat of Sec. III-B: each sample to its nearest
+    voxel, V = mean of the normals per voxel (0 where none).  Returns
+    (V (3, Nz, Ny, Nx), counts (Nz, Ny, Nx) int64, n_rejected)."""
+    lib = _load()
+    p = _f32c(points).reshape(-1, 3)
+    nrm = _f32c(normals).reshape(-1, 3)
+    Nx, Ny, Nz = (int(x) for x in dims)
+    S = np.empty((3, Nz, Ny, Nx))
+    cnt = np.empty((Nz, Ny, Nx), np.int64)
+    V = np.empty((3, Nz, Ny, Nx))
+    rej = lib.oracle_splat_nearest(_ptr(p), _ptr(nrm), p.shape[0], _ptr(np.asarray(dims, np.int32)),
+                                   _ptr(np.asarray(bbox, np.float32)), _ptr(S), _ptr(cnt), _ptr(V))
+    return V, cnt, int(rej)
 
 
 def _wavenumbers(n: int) -> np.ndarray:
@@ -187,10 +205,12 @@ def mc_table():
     return _TABLE
 
 
-def extract(A, L, dims, bbox, with_cases: bool = True, threads: int = 1):
+def extract(A, L, dims, bbox, with_cases: bool = True, threads: int = 1, with_normals: bool = False):
     """Marching cubes at level L.  Returns (verts (V,3) f64, tris (T,3) i32,
-    cases uint8 (Nz-1, Ny-1, Nx-1) or None).  threads > 1 spreads the z
-    planes over OpenMP threads (same output)."""
+    cases uint8 (Nz-1, Ny-1, Nx-1) or None), plus the unit vertex normals
+    -grad A (V,3) when with_normals (central differences at the edge's grid
+    points, one-sided on the outer layer, interpolated with the vertex's t).
+    threads > 1 spreads the z planes over OpenMP threads (same output)."""
     lib = _load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     Nx, Ny, Nz = (int(x) for x in dims)
@@ -201,12 +221,15 @@ def extract(A, L, dims, bbox, with_cases: bool = True, threads: int = 1):
             float(L), _ptr(count), _ptr(edges))
     # first pass sizes the output, second pass fills it
     lib.oracle_marching_cubes(*args, None, 0, None, 0, _ptr(cases),
-                              ctypes.byref(nv), ctypes.byref(nt), int(threads))
+                              ctypes.byref(nv), ctypes.byref(nt), int(threads), None)
     verts = np.empty((max(nv.value, 1), 3))
     tris = np.empty((max(nt.value, 1), 3), np.int32)
+    nrm = np.empty((max(nv.value, 1), 3)) if with_normals else None
     rc = lib.oracle_marching_cubes(*args, _ptr(verts), nv.value, _ptr(tris), nt.value,
-                                   None, ctypes.byref(nv), ctypes.byref(nt), int(threads))
+                                   None, ctypes.byref(nv), ctypes.byref(nt), int(threads), _ptr(nrm))
     assert rc == 0
+    if with_normals:
+        return verts[:nv.value], tris[:nt.value], cases, nrm[:nv.value]
     return verts[:nv.value], tris[:nt.value], cases
 
 
@@ -219,15 +242,24 @@ def open_surface(A, L) -> bool:
     return bool(np.any(A[shell] > L))
 
 
-def reconstruct(points, normals, weights, dims, bbox, with_cases=False, threads: int = 1):
+def reconstruct(points, normals, weights, dims, bbox, with_cases=False, threads: int = 1,
+                splat_variant: str = "gaussian", with_normals: bool = False):
     """The whole path: splat, spectral integration, level, marching cubes.
     threads > 1 runs the splat, the transforms and marching cubes on that
-    many host threads (see each step)."""
-    V, _, _, rej = splat(points, normals, weights, dims, bbox, threads=threads)
+    many host threads (see each step).  splat_variant "nearest" takes the
+    non-weighted splat; with_normals adds the vertex normals."""
+    if splat_variant == "nearest":
+        V, _, rej = splat_nearest(points, normals, dims, bbox)
+    else:
+        V, _, _, rej = splat(points, normals, weights, dims, bbox, threads=threads)
     A = indicator(V, dims, bbox, threads=threads)
     L, used = level(A, points, dims, bbox)
     if used == 0:
         L = 0.0
-    verts, tris, cases = extract(A, L, dims, bbox, with_cases=with_cases, threads=threads)
-    return dict(V=V, A=A, level=L, n_used=used, n_rejected=rej, verts=verts,
-                tris=tris, cases=cases, open_surface=open_surface(A, L))
+    ex = extract(A, L, dims, bbox, with_cases=with_cases, threads=threads, with_normals=with_normals)
+    verts, tris, cases = ex[:3]
+    out = dict(V=V, A=A, level=L, n_used=used, n_rejected=rej, verts=verts,
+               tris=tris, cases=cases, open_surface=open_surface(A, L))
+    if with_normals:
+        out["normals"] = ex[3]
+    return out

@@ -126,6 +126,53 @@ int64_t oracle_splat(const float *points, const float *normals, const float *wei
     return rejected;
 }
 
+/* Nearest voxel centre of x: the grid cell containing the point,
+ * floor((x - bmin) / h) in float32 (h = (bmax - bmin) / N in float32), clamped
+ * to the grid - the same float32 formula as the GPU kernel, since floating
+ * point decides an integer here. */
+static int nearest_voxel_f32(float x, float bmin, float bmax, int n)
+{
+    volatile float h = (bmax - bmin) / (float)n;
+    volatile float d = x - bmin;
+    volatile float u = d / h;
+    int i = (int)floorf(u);
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    return i;
+}
+
+/*
+ * Non-weighted splat, the simplest version of Sec. III-B: each accepted
+ * sample is assigned ("clamped") to its nearest voxel, and the vector field
+ * is the sum of the normals assigned to a voxel divided by their number;
+ * V = 0 where no sample lands.  Weights play no part.  S holds the sums
+ * (3 arrays), cnt the counts; returns the number of rejected points.
+ */
+int64_t oracle_splat_nearest(const float *points, const float *normals, int64_t m,
+                             const int32_t *dims, const float *bbox, double *S, int64_t *cnt,
+                             double *V)
+{
+    const int Nx = dims[0], Ny = dims[1], Nz = dims[2];
+    const int64_t n = (int64_t)Nx * Ny * Nz;
+    memset(S, 0, sizeof(double) * 3 * n);
+    memset(cnt, 0, sizeof(int64_t) * n);
+    int64_t rejected = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        const float *X = points + 3 * i;
+        if (!point_accepted(X, bbox)) { ++rejected; continue; }
+        const int qx = nearest_voxel_f32(X[0], bbox[0], bbox[3], Nx);
+        const int qy = nearest_voxel_f32(X[1], bbox[1], bbox[4], Ny);
+        const int qz = nearest_voxel_f32(X[2], bbox[2], bbox[5], Nz);
+        const int64_t l = qx + (int64_t)Nx * (qy + (int64_t)Ny * qz);
+        for (int c = 0; c < 3; ++c) S[c * n + l] += (double)normals[3 * i + c];
+        cnt[l] += 1;
+    }
+    for (int64_t l = 0; l < n; ++l)
+        for (int c = 0; c < 3; ++c)
+            V[c * n + l] = cnt[l] > 0 ? S[c * n + l] / (double)cnt[l] : 0.0;
+    return rejected;
+}
+
 /*
  * Iso-level L: mean of A at the input sample locations (text before the
  * CUDA remark closing Sec. III-B).  R: A is sampled by trilinear
@@ -193,12 +240,28 @@ double oracle_level(const double *A, const int32_t *dims, const float *bbox,
  * Output sizes are checked against the capacities; the required counts are
  * always written.  Returns 0, or -1 if a capacity is too small.  nthreads > 1
  * spreads the z planes over OpenMP threads; the output is the same.
+ * normals (optional, V x 3): the unit vertex normals -grad A described at
+ * mc_plane_vertices (Sec. III-B lists normals among the mesh outputs).
  */
+/* dA/dx_b at grid point q by central differences, one-sided on the grid's
+ * outer layer (reading of the normals the extraction outputs). */
+static double grad_axis(const double *A, const int32_t *dims, const double *h, const int q[3], int b)
+{
+    const int64_t stride[3] = {1, dims[0], (int64_t)dims[0] * dims[1]};
+    const int64_t l = q[0] + stride[1] * q[1] + stride[2] * q[2];
+    const int lo = q[b] == 0, hi = q[b] == dims[b] - 1;
+    const double ap = hi ? A[l] : A[l + stride[b]];
+    const double am = lo ? A[l] : A[l - stride[b]];
+    return (ap - am) / ((lo || hi ? 1.0 : 2.0) * h[b]);
+}
+
 /* Vertices whose grid point lies in plane qz, in (l, axis) order; writes
- * ids from `first` (and positions, if they fit) when vid is not NULL. */
+ * ids from `first` (and positions, if they fit) when vid is not NULL.
+ * Normals (optional): -grad A, the gradients at the edge's two grid points
+ * interpolated linearly with t, normalised (zero where that is zero). */
 static int64_t mc_plane_vertices(const double *A, const int32_t *dims, const float *bbox,
                                  const double *h, double level, int qz, int64_t first,
-                                 int32_t *vid, double *verts, int64_t vert_cap)
+                                 int32_t *vid, double *verts, int64_t vert_cap, double *normals)
 {
     const int Nx = dims[0], Ny = dims[1];
     int64_t nv = first;
@@ -219,6 +282,19 @@ static int64_t mc_plane_vertices(const double *A, const int32_t *dims, const flo
                             double p = (double)bbox[b] + (q[b] + 0.5) * h[b];
                             if (b == a) p += t * h[a];
                             verts[3 * nv + b] = p;
+                        }
+                        if (normals) {
+                            int q1[3] = {qx, qy, qz};
+                            q1[a] += 1;
+                            double g[3], len2 = 0.0;
+                            for (int b = 0; b < 3; ++b) {
+                                const double g0 = grad_axis(A, dims, h, q, b);
+                                const double g1 = grad_axis(A, dims, h, q1, b);
+                                g[b] = -((1.0 - t) * g0 + t * g1);
+                                len2 += g[b] * g[b];
+                            }
+                            const double len = sqrt(len2);
+                            for (int b = 0; b < 3; ++b) normals[3 * nv + b] = len > 0.0 ? g[b] / len : 0.0;
                         }
                     }
                     vid[3 * l + a] = (int32_t)nv;
@@ -277,7 +353,8 @@ static int64_t mc_plane_triangles(const double *A, const int32_t *dims, double l
 int oracle_marching_cubes(const double *A, const int32_t *dims, const float *bbox,
                           double level, const uint8_t *tri_count, const int8_t *tri_edges,
                           double *verts, int64_t vert_cap, int32_t *tris, int64_t tri_cap,
-                          uint8_t *cases, int64_t *n_verts, int64_t *n_tris, int nthreads)
+                          uint8_t *cases, int64_t *n_verts, int64_t *n_tris, int nthreads,
+                          double *normals)
 {
     const int Nx = dims[0], Ny = dims[1], Nz = dims[2];
     const int64_t n = (int64_t)Nx * Ny * Nz;
@@ -302,11 +379,11 @@ int oracle_marching_cubes(const double *A, const int32_t *dims, const float *bbo
     vfirst[0] = 0;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
     for (int qz = 0; qz < Nz; ++qz)
-        vfirst[qz + 1] = mc_plane_vertices(A, dims, bbox, h, level, qz, 0, NULL, NULL, 0);
+        vfirst[qz + 1] = mc_plane_vertices(A, dims, bbox, h, level, qz, 0, NULL, NULL, 0, NULL);
     for (int qz = 0; qz < Nz; ++qz) vfirst[qz + 1] += vfirst[qz];
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
     for (int qz = 0; qz < Nz; ++qz)
-        mc_plane_vertices(A, dims, bbox, h, level, qz, vfirst[qz], vid, verts, vert_cap);
+        mc_plane_vertices(A, dims, bbox, h, level, qz, vfirst[qz], vid, verts, vert_cap, normals);
 
     /* Triangles, cell by cell in (l(c), table) order, the same way per plane
      * of cells. */

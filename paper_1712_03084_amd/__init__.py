@@ -48,7 +48,8 @@ class FvrUnavailable(RuntimeError):
 class _Frame(ctypes.Structure):
     _fields_ = [("points", ctypes.c_void_p), ("normals", ctypes.c_void_p),
                 ("weights", ctypes.c_void_p), ("n_points", ctypes.c_int64),
-                ("dims", ctypes.c_int32 * 3), ("bbox", ctypes.c_float * 6)]
+                ("dims", ctypes.c_int32 * 3), ("bbox", ctypes.c_float * 6),
+                ("options", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
@@ -62,10 +63,33 @@ class _Mesh(ctypes.Structure):
                 ("vertex_capacity", ctypes.c_int64), ("triangle_capacity", ctypes.c_int64),
                 ("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
                 ("level", ctypes.c_double), ("n_rejected", ctypes.c_int64),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("normals", ctypes.c_void_p)]
 
 
-Mesh = namedtuple("Mesh", "vertices triangles level n_rejected open_surface")
+FVR_SPLAT_NEAREST = 1
+# splat variants of Sec. III-B: the weighted Gaussian splat of eqs. (1)-(2),
+# and the non-weighted one (each normal to its nearest voxel, mean per voxel)
+SPLATS = {"gaussian": 0, "nearest": FVR_SPLAT_NEAREST}
+
+Mesh = namedtuple("Mesh", "vertices triangles level n_rejected open_surface normals", defaults=(None,))
+
+
+def _fill_mesh(m, out):
+    """Point a _Mesh at output buffers (vertices, triangles[, normals])."""
+    verts, tris = out[0], out[1]
+    nrm = out[2] if len(out) > 2 else None
+    m.vertices = verts.data_ptr()
+    m.triangles = tris.data_ptr()
+    m.normals = nrm.data_ptr() if nrm is not None else None
+    m.vertex_capacity = verts.shape[0] if nrm is None else min(verts.shape[0], nrm.shape[0])
+    m.triangle_capacity = tris.shape[0]
+
+
+def _result(m, out):
+    """Mesh of a finished call as views of its output buffers."""
+    nrm = out[2][:m.n_vertices] if len(out) > 2 and out[2] is not None else None
+    return Mesh(out[0][:m.n_vertices], out[1][:m.n_triangles], m.level, int(m.n_rejected),
+                bool(m.flags & FVR_FLAG_OPEN_SURFACE), nrm)
 
 _lib = None
 
@@ -189,13 +213,12 @@ class PreparedFrame:
 
     def __init__(self, ctx, frame, keep, out, stream):
         self._ctx, self._f, self._keep, self._stream = ctx, frame, keep, stream
-        self.vertices_buf, self.triangles_buf = out
+        self._out = tuple(out)
+        self.vertices_buf, self.triangles_buf = self._out[0], self._out[1]
         m = _Mesh()
-        m.vertices = self.vertices_buf.data_ptr()
-        m.triangles = self.triangles_buf.data_ptr()
-        m.vertex_capacity = self.vertices_buf.shape[0]
-        m.triangle_capacity = self.triangles_buf.shape[0]
+        _fill_mesh(m, self._out)
         self._m = m
+        self._vcap, self._tcap = m.vertex_capacity, m.triangle_capacity
         self._args = (ctx.handle, ctypes.byref(frame), ctypes.byref(m))
         self._fn = ctx.lib.fvr_reconstruct
 
@@ -207,8 +230,8 @@ class PreparedFrame:
             _check(ctx.lib, ctx.lib.fvr_set_stream(ctx.handle, ctypes.c_void_p(self._stream)), ctx.handle)
             ctx._cur_stream = self._stream
         m = self._m
-        m.vertex_capacity = self.vertices_buf.shape[0]
-        m.triangle_capacity = self.triangles_buf.shape[0]
+        m.vertex_capacity = self._vcap
+        m.triangle_capacity = self._tcap
         st = self._fn(*self._args)
         if st:
             _check(ctx.lib, st, ctx.handle)
@@ -216,9 +239,7 @@ class PreparedFrame:
 
     def mesh(self) -> Mesh:
         """The last run's result as views of the output buffers."""
-        m = self._m
-        return Mesh(self.vertices_buf[:m.n_vertices], self.triangles_buf[:m.n_triangles], m.level,
-                    int(m.n_rejected), bool(m.flags & FVR_FLAG_OPEN_SURFACE))
+        return _result(self._m, self._out)
 
 
 class Context:
@@ -254,7 +275,7 @@ class Context:
             _check(self.lib, self.lib.fvr_set_stream(self.handle, ctypes.c_void_p(s)), self.handle)
             self._cur_stream = s
 
-    def _frame(self, points, normals, weights, grid_dim, bbox):
+    def _frame(self, points, normals, weights, grid_dim, bbox, splat="gaussian"):
         points = _dev_f32(points, "points", self.device, 3)
         normals = _dev_f32(normals, "normals", self.device, 3)
         if normals.shape[0] != points.shape[0]:
@@ -272,51 +293,53 @@ class Context:
         gd = (grid_dim,) * 3 if isinstance(grid_dim, int) else tuple(grid_dim)
         f.dims[:] = [int(x) for x in gd]
         f.bbox[:] = [float(x) for x in _flat_bbox(bbox)]
+        if splat not in SPLATS:
+            raise ValueError(f"splat must be one of {sorted(SPLATS)}")
+        f.options = SPLATS[splat]
         return f, (points, normals, weights)
 
-    def _run_mesh(self, call, dims, out, vcap, tcap):
+    def _run_mesh(self, call, dims, out, vcap, tcap, want_normals=False):
         torch = _torch()
-        if out is not None:
-            verts, tris = out
-        else:
+        dev = f"cuda:{self.device}"
+        if out is None:
             if vcap is None:
                 nx, ny, nz = dims
                 vcap = max(4096, 6 * (nx * ny + ny * nz + nx * nz))
             if tcap is None:
                 tcap = 2 * vcap
-            verts = torch.empty((vcap, 3), dtype=torch.float32, device=f"cuda:{self.device}")
-            tris = torch.empty((tcap, 3), dtype=torch.int32, device=f"cuda:{self.device}")
         for attempt in range(2):
+            if out is not None:
+                bufs = tuple(out)
+            else:
+                bufs = (torch.empty((vcap, 3), dtype=torch.float32, device=dev),
+                        torch.empty((tcap, 3), dtype=torch.int32, device=dev))
+                if want_normals:
+                    bufs += (torch.empty((vcap, 3), dtype=torch.float32, device=dev),)
             m = _Mesh()
-            m.vertices = verts.data_ptr()
-            m.triangles = tris.data_ptr()
-            m.vertex_capacity = verts.shape[0]
-            m.triangle_capacity = tris.shape[0]
+            _fill_mesh(m, bufs)
             st = call(m)
             if st == -4 and attempt == 0 and out is None:
-                verts = torch.empty((max(m.n_vertices, 1), 3), dtype=torch.float32,
-                                    device=f"cuda:{self.device}")
-                tris = torch.empty((max(m.n_triangles, 1), 3), dtype=torch.int32,
-                                   device=f"cuda:{self.device}")
+                vcap, tcap = max(m.n_vertices, 1), max(m.n_triangles, 1)
                 continue
             _check(self.lib, st, self.handle)
             break
-        return Mesh(verts[:m.n_vertices], tris[:m.n_triangles], m.level, int(m.n_rejected),
-                    bool(m.flags & FVR_FLAG_OPEN_SURFACE))
+        return _result(m, bufs)
 
     # -- API ----------------------------------------------------------------
     def reconstruct(self, points, normals, weights=None, grid_dim=(128, 128, 128),
                     bbox=((-1, -1, -1), (1, 1, 1)), out=None, vertex_capacity=None,
-                    triangle_capacity=None) -> Mesh:
+                    triangle_capacity=None, vertex_normals=False, splat="gaussian") -> Mesh:
         """Sec. III-B end to end: returns Mesh(vertices [V,3] f32, triangles
-        [T,3] i32, level, n_rejected, open_surface).  ``out`` = (verts, tris)
-        preallocated buffers, used without retry."""
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        [T,3] i32, level, n_rejected, open_surface, normals [V,3] f32 or
+        None).  ``out`` = (verts, tris[, normals]) preallocated buffers, used
+        without retry; ``vertex_normals`` asks for normals when out is None;
+        ``splat`` is "gaussian" (eqs. (1)-(2)) or "nearest"."""
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
         self._stream()
         dims = tuple(f.dims)
         return self._run_mesh(lambda m: self.lib.fvr_reconstruct(self.handle, ctypes.byref(f),
                                                                  ctypes.byref(m)),
-                              dims, out, vertex_capacity, triangle_capacity)
+                              dims, out, vertex_capacity, triangle_capacity, vertex_normals)
 
     def last_stats(self) -> dict:
         """Work counters of the last reconstruction or indicator call
@@ -327,7 +350,7 @@ class Context:
         return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
 
     def reconstruct_noalloc(self, points, normals, weights=None, grid_dim=(128, 128, 128),
-                            bbox=((-1, -1, -1), (1, 1, 1)), out=None) -> Mesh:
+                            bbox=((-1, -1, -1), (1, 1, 1)), out=None, splat="gaussian") -> Mesh:
         """``reconstruct`` through ``fvr_reconstruct_noalloc``: the library
         allocates no device memory in the call (its scratch is the device's
         static array of FVR_NOALLOC_SCRATCH_BYTES).  ``out`` = (verts, tris)
@@ -335,29 +358,24 @@ class Context:
         scratch raises FvrError."""
         if out is None:
             raise ValueError("reconstruct_noalloc needs preallocated out=(vertices, triangles)")
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
         self._stream()
-        verts, tris = out
         m = _Mesh()
-        m.vertices = verts.data_ptr()
-        m.triangles = tris.data_ptr()
-        m.vertex_capacity = verts.shape[0]
-        m.triangle_capacity = tris.shape[0]
+        _fill_mesh(m, out)
         _check(self.lib, self.lib.fvr_reconstruct_noalloc(self.handle, ctypes.byref(f), ctypes.byref(m)),
                self.handle)
-        return Mesh(verts[:m.n_vertices], tris[:m.n_triangles], m.level, int(m.n_rejected),
-                    bool(m.flags & FVR_FLAG_OPEN_SURFACE))
+        return _result(m, out)
 
     def prepare(self, points, normals, weights=None, grid_dim=(128, 128, 128),
                 bbox=((-1, -1, -1), (1, 1, 1)), out=None, vertex_capacity=None,
-                triangle_capacity=None) -> "PreparedFrame":
+                triangle_capacity=None, splat="gaussian") -> "PreparedFrame":
         """A frame for repeated reconstruction: the tensors are checked and
         the call's arguments marshalled once.  ``run()`` then enqueues the
         same work as ``reconstruct`` on the stream that was current here,
         reading the tensors' contents at each call (a serving loop refills
         the same input and output buffers between runs).  The output
         buffers are ``out`` or allocated once; a capacity shortfall raises."""
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
         self._stream()
         torch = _torch()
         if out is None:
@@ -369,10 +387,10 @@ class Context:
         return PreparedFrame(self, f, keep, out, self._cur_stream)
 
     def indicator(self, points, normals, weights=None, grid_dim=(128, 128, 128),
-                  bbox=((-1, -1, -1), (1, 1, 1))):
+                  bbox=((-1, -1, -1), (1, 1, 1)), splat="gaussian"):
         """Steps up to the iso-level: returns (A [Nz, Ny, Nx] f32 tensor, L)."""
         torch = _torch()
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
         self._stream()
         nx, ny, nz = tuple(f.dims)
         A = torch.empty((nz, ny, nx), dtype=torch.float32, device=f"cuda:{self.device}")
@@ -382,7 +400,7 @@ class Context:
         return A, lvl.value
 
     def extract(self, field, bbox, level, with_cases=False, out=None, vertex_capacity=None,
-                triangle_capacity=None):
+                triangle_capacity=None, vertex_normals=False):
         """Marching cubes of a device field (Nz, Ny, Nx) at ``level``.
         Returns Mesh, plus the case bytes (Nz-1, Ny-1, Nx-1) if requested."""
         torch = _torch()
@@ -402,14 +420,14 @@ class Context:
         mesh = self._run_mesh(
             lambda m: self.lib.fvr_extract(self.handle, field.data_ptr(), d, b, float(level),
                                            ctypes.byref(m), cases.data_ptr() if cases is not None else None),
-            (nx, ny, nz), out, vertex_capacity, triangle_capacity)
+            (nx, ny, nz), out, vertex_capacity, triangle_capacity, vertex_normals)
         return (mesh, cases) if with_cases else mesh
 
     def debug_splat(self, points, normals, weights=None, grid_dim=(128, 128, 128),
-                    bbox=((-1, -1, -1), (1, 1, 1))):
+                    bbox=((-1, -1, -1), (1, 1, 1)), splat="gaussian"):
         """The splat kernel's V field (3, Nz, Ny, Nx) f32."""
         torch = _torch()
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox)
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
         self._stream()
         nx, ny, nz = tuple(f.dims)
         V = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=f"cuda:{self.device}")
@@ -470,8 +488,8 @@ def reconstruct(points, normals, weights=None, grid_dim=(128, 128, 128),
 
 
 def indicator(points, normals, weights=None, grid_dim=(128, 128, 128),
-              bbox=((-1, -1, -1), (1, 1, 1))):
-    return _ctx(points.device.index).indicator(points, normals, weights, grid_dim, bbox)
+              bbox=((-1, -1, -1), (1, 1, 1)), **kw):
+    return _ctx(points.device.index).indicator(points, normals, weights, grid_dim, bbox, **kw)
 
 
 def extract(field, bbox, level, with_cases=False, **kw):
@@ -479,8 +497,8 @@ def extract(field, bbox, level, with_cases=False, **kw):
 
 
 def debug_splat(points, normals, weights=None, grid_dim=(128, 128, 128),
-                bbox=((-1, -1, -1), (1, 1, 1))):
-    return _ctx(points.device.index).debug_splat(points, normals, weights, grid_dim, bbox)
+                bbox=((-1, -1, -1), (1, 1, 1)), **kw):
+    return _ctx(points.device.index).debug_splat(points, normals, weights, grid_dim, bbox, **kw)
 
 
 class Batch:
@@ -546,16 +564,13 @@ class PreparedBatch:
         self._keep = []
         helper = Context.__new__(Context)  # marshalling only: no fvr_ctx is made
         helper.device = batch.device
-        for i, (fr, (verts, tris)) in enumerate(zip(frames, outs)):
-            points, normals, weights, grid_dim, bbox = fr
-            f, keep = Context._frame(helper, points, normals, weights, grid_dim, bbox)
+        for i, (fr, o) in enumerate(zip(frames, outs)):
+            points, normals, weights, grid_dim, bbox = fr[:5]
+            f, keep = Context._frame(helper, points, normals, weights, grid_dim, bbox,
+                                     fr[5] if len(fr) > 5 else "gaussian")
             self._frames[i] = f
-            self._keep.append((keep, verts, tris))
-            m = self._meshes[i]
-            m.vertices = verts.data_ptr()
-            m.triangles = tris.data_ptr()
-            m.vertex_capacity = verts.shape[0]
-            m.triangle_capacity = tris.shape[0]
+            self._keep.append((keep, tuple(o)))
+            _fill_mesh(self._meshes[i], tuple(o))
 
     def run(self):
         torch = _torch()
@@ -567,10 +582,4 @@ class PreparedBatch:
         return [(m.n_vertices, m.n_triangles) for m in self._meshes[:self._n]]
 
     def meshes(self):
-        out = []
-        for i in range(self._n):
-            m = self._meshes[i]
-            _, verts, tris = self._keep[i]
-            out.append(Mesh(verts[:m.n_vertices], tris[:m.n_triangles], m.level, int(m.n_rejected),
-                            bool(m.flags & FVR_FLAG_OPEN_SURFACE)))
-        return out
+        return [_result(self._meshes[i], self._keep[i][1]) for i in range(self._n)]

@@ -317,8 +317,11 @@ bool splat_tile_ok(int nx, int ty, int tz) {
     return ty >= 1 && tz >= 1 && R % 2 == 0 && R * nx <= splat_max_plane() && (ty + 3) * (tz + 3) <= 128;
 }
 
-// Geometry-dependent splat constants (the bbox may change between calls).
-void plan_geometry(Plan *p, const int32_t dims[3], const float bbox[6]) {
+// Frame-dependent splat constants: the Gaussians' exponents (the bbox may
+// change between calls) and the splat variant.
+void plan_geometry(Plan *p, const fvr_frame *f) {
+    const int32_t *dims = f->dims;
+    const float *bbox = f->bbox;
     double h[3], s1sq = 0.0;
     for (int a = 0; a < 3; ++a) {
         h[a] = ((double)bbox[a + 3] - (double)bbox[a]) / (double)dims[a];
@@ -330,10 +333,17 @@ void plan_geometry(Plan *p, const int32_t dims[3], const float bbox[6]) {
         p->sc.e1[a] = (float)(-h[a] * h[a] / s1sq * log2e);
         p->sc.e2[a] = (float)(-h[a] * h[a] / s2sq * log2e);
     }
-    p->sc.vscale = (float)std::sqrt(1.5);
+    const bool nearest = (f->options & FVR_SPLAT_NEAREST) != 0;
+    p->sc.nearest = nearest ? 1 : 0;
+    p->sc.fp_lo = nearest ? 0 : -1;
+    p->sc.fp_hi = nearest ? 0 : 2;
+    // V = S / D carries the ratio sigma2/sigma1 of the two 1/sigma factors;
+    // the nearest-voxel splat is a plain mean
+    p->sc.vscale = nearest ? 1.0f : (float)std::sqrt(1.5);
 }
 
-fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan **out) {
+fvr_status get_plan(fvr_ctx *c, const fvr_frame *f, Plan **out) {
+    const int32_t *dims = f->dims;
     const std::array<int, 3> key = {dims[0], dims[1], dims[2]};
     auto it = c->plans.find(key);
     Plan *p;
@@ -354,7 +364,7 @@ fvr_status get_plan(fvr_ctx *c, const int32_t dims[3], const float bbox[6], Plan
     } else {
         p = &it->second;
     }
-    plan_geometry(p, dims, bbox);
+    plan_geometry(p, f);
     *out = p;
     return FVR_OK;
 }
@@ -367,6 +377,7 @@ fvr_status check_frame_fields(fvr_ctx *c, const fvr_frame *f) {
     if (f->n_points > FVR_MAX_POINTS) return fail(c, FVR_E_INVALID, "n_points above FVR_MAX_POINTS");
     if (f->n_points > 0 && (!f->points || !f->normals))
         return fail(c, FVR_E_INVALID, "points or normals is NULL");
+    if (f->options & ~FVR_SPLAT_NEAREST) return fail(c, FVR_E_INVALID, "unknown frame option bits");
     return check_grid(c, f->dims, f->bbox);
 }
 
@@ -465,7 +476,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
     hipStream_t s = c->stream;
     { Timed t(c, K_PREP); HIP_TRY(c, launch_prep(st, P<int32_t>(c->bin_count), nbins, s), "prep"); }
     { Timed t(c, K_BIN_COUNT);
-      HIP_TRY(c, launch_bin_count(f->points, f->normals, f->weights, m, g, P<int32_t>(c->bin_count),
+      HIP_TRY(c, launch_bin_count(f->points, f->normals, f->weights, m, g, p->sc.nearest, P<int32_t>(c->bin_count),
                                   P<int32_t>(c->key), P<int32_t>(c->rank), P<uint2>(c->blk_max), st, s),
               "bin_count"); }
     { Timed t(c, K_TILE_LIST);
@@ -475,7 +486,8 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
               "tile_list"); }
     { Timed t(c, K_BIN_SCATTER);
       HIP_TRY(c, launch_bin_scatter(f->points, f->normals, f->weights, m, g, P<int32_t>(c->key),
-                                    P<int32_t>(c->rank), P<int32_t>(c->bin_off), st, P<float4>(c->rec), s),
+                                    P<int32_t>(c->rank), P<int32_t>(c->bin_off), st, p->sc.nearest,
+                                    P<float4>(c->rec), s),
               "bin_scatter"); }
     { Timed t(c, K_SPLAT_FFT_X);
       HIP_TRY(c, launch_splat_fft_x(P<float4>(c->rec), P<int32_t>(c->bin_off), g, p->sc, p->ax[0],
@@ -550,7 +562,8 @@ fvr_status enqueue_mc(fvr_ctx *c, const Grid &g, const float *field, const float
     { Timed t(c, K_MC_GENERATE);
       HIP_TRY(c, launch_mc_generate(field, P<float>(c->level_f32), list, g, P<int32_t>(c->mc_cnt),
                                     P<int32_t>(c->mc_off), P<uint32_t>(c->mc_codes), mesh->vertices,
-                                    P<int32_t>(c->vidx), P<int4>(c->cells), st, caps, host_dst, s),
+                                    mesh->normals, P<int32_t>(c->vidx), P<int4>(c->cells), st, caps,
+                                    host_dst, s),
               "mc_generate"); }
     { Timed t(c, K_MC_TRIANGLES);
       HIP_TRY(c, launch_mc_triangles(P<int4>(c->cells), P<int32_t>(c->vidx), g, mesh->triangles, st,
@@ -683,7 +696,7 @@ fvr_status fvr_reconstruct(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mesh) {
     if (!mesh) return fail(c, FVR_E_INVALID, "mesh is NULL");
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     Plan *p;
-    if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
+    if ((r = get_plan(c, f, &p)) != FVR_OK) return r;
     if ((r = enqueue_reconstruct(c, f, p, mesh, c->host_status)) != FVR_OK) return r;
     if ((r = sync(c)) != FVR_OK) return r;
     const DevStatus hs = *c->host_status;
@@ -703,7 +716,7 @@ fvr_status fvr_reconstruct_noalloc(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mes
     // the device's static table
     Plan plan;
     if ((r = build_plan(c, f->dims, plan)) != FVR_OK) return r;
-    plan_geometry(&plan, f->dims, f->bbox);
+    plan_geometry(&plan, f);
     const Grid g = make_grid(f->dims, f->bbox);
     // arena mode for this call: every scratch buffer is a slice of the static
     // array; timing events (created on first use) are off
@@ -739,7 +752,7 @@ fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, doubl
     if (!field_out) return fail(c, FVR_E_INVALID, "field_out is NULL");
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     Plan *p;
-    if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
+    if ((r = get_plan(c, f, &p)) != FVR_OK) return r;
     const Grid g = make_grid(f->dims, f->bbox);
     // the transform writes into the context's field first: on invalid input
     // the caller's buffer stays untouched
@@ -784,7 +797,7 @@ fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
     if (!v_out) return fail(c, FVR_E_INVALID, "v_out is NULL");
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     Plan *p;
-    if ((r = get_plan(c, f->dims, f->bbox, &p)) != FVR_OK) return r;
+    if ((r = get_plan(c, f, &p)) != FVR_OK) return r;
     const Grid g = make_grid(f->dims, f->bbox);
     // the splat writes V only on tiles that some point reaches
     HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(v_out), 3 * (int64_t)g.n[0] * g.n[1] * g.n[2], 0,
@@ -864,6 +877,7 @@ std::vector<unsigned char> batch_key(const fvr_batch *b, const fvr_frame *frames
     for (int i = 0; i < n; ++i) {
         put(&frames[i], sizeof(fvr_frame));
         put(&meshes[i].vertices, sizeof(meshes[i].vertices));
+        put(&meshes[i].normals, sizeof(meshes[i].normals));
         put(&meshes[i].triangles, sizeof(meshes[i].triangles));
         put(&meshes[i].vertex_capacity, sizeof(int64_t));
         put(&meshes[i].triangle_capacity, sizeof(int64_t));
@@ -873,7 +887,7 @@ std::vector<unsigned char> batch_key(const fvr_batch *b, const fvr_frame *frames
 
 // Fork, every frame's stages on its slot's stream, join.
 fvr_status batch_enqueue(fvr_batch *b, const fvr_frame *frames, fvr_mesh *meshes, int n,
-                         std::vector<Plan *> &plans) {
+                         std::vector<Plan> &plans) {
     const int S = (int)b->slots.size();
     hipError_t e = hipEventRecord(b->fork, b->origin);
     if (e != hipSuccess) return bhip(b, e, "batch fork");
@@ -881,7 +895,7 @@ fvr_status batch_enqueue(fvr_batch *b, const fvr_frame *frames, fvr_mesh *meshes
         if ((e = hipStreamWaitEvent(b->slots[k]->stream, b->fork, 0)) != hipSuccess) return bhip(b, e, "batch fork");
     for (int i = 0; i < n; ++i) {
         fvr_ctx *c = b->slots[i % S];
-        fvr_status r = enqueue_reconstruct(c, &frames[i], plans[i], &meshes[i], b->host_st + i);
+        fvr_status r = enqueue_reconstruct(c, &frames[i], &plans[i], &meshes[i], b->host_st + i);
         if (r != FVR_OK) return bfail(b, r, c->err);
     }
     for (int k = 0; k < S && k < n; ++k) {
@@ -976,13 +990,19 @@ fvr_status fvr_batch_reconstruct(fvr_batch *b, const fvr_frame *frames, fvr_mesh
     hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return bhip(b, e, "hipSetDevice");
     const int S = (int)b->slots.size();
-    // host checks, plans and every slot's scratch, all before any enqueue
-    std::vector<Plan *> plans((size_t)n);
+    // host checks, plans and every slot's scratch, all before any enqueue;
+    // each frame keeps its own copy of the plan (frames of one shape may
+    // differ in bbox and splat)
+    std::vector<Plan> plans((size_t)n);
     for (int i = 0; i < n; ++i) {
         fvr_ctx *c = b->slots[i % S];
+        Plan *pp = nullptr;
         fvr_status r = check_frame(c, &frames[i]);
-        if (r == FVR_OK) r = get_plan(c, frames[i].dims, frames[i].bbox, &plans[i]);
-        if (r == FVR_OK) r = frame_bufs(c, &frames[i], plans[i], &meshes[i]);
+        if (r == FVR_OK) r = get_plan(c, &frames[i], &pp);
+        if (r == FVR_OK) {
+            plans[i] = *pp;
+            r = frame_bufs(c, &frames[i], &plans[i], &meshes[i]);
+        }
         if (r != FVR_OK) return bfail(b, r, std::string("frame ") + std::to_string(i) + ": " + c->err);
     }
     if (n > b->host_cap) {

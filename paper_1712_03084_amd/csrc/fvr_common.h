@@ -53,9 +53,11 @@ struct Grid {
 struct SplatConsts {
     float e1[3];
     float e2[3];
-    float vscale;      // sigma2 / sigma1: the ratio of the two 1/sigma prefactors
+    float vscale;      // sigma2 / sigma1: the ratio of the two 1/sigma prefactors (1: nearest)
     int ty, tz;        // tile rows along y and z (full x rows per tile)
     int tiles_y;       // ceil(Ny / ty)
+    int nearest;       // 1: the non-weighted splat (each point to its nearest voxel)
+    int fp_lo, fp_hi;  // rows a point of origin row i reaches: i + fp_lo .. i + fp_hi
 };
 
 // Device-side status block, read back once per frame.
@@ -108,13 +110,13 @@ int bin_count_blocks(int m);
 // blk_max: per bin_count block, the bits of its largest W and W |N_c|
 // (reduced by tile_order into st->wmax_bits, st->wnmax_bits)
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
-                            const Grid &g, int32_t *bin_count, int32_t *key, int32_t *rank,
+                            const Grid &g, int nearest, int32_t *bin_count, int32_t *key, int32_t *rank,
                             uint2 *blk_max, DevStatus *st, hipStream_t s);
 // Splat, stage 2: scatter packed records (fractional voxel offsets, W, W N,
 // x footprint origin) into bin order.
 hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
                               const Grid &g, const int32_t *key, const int32_t *rank,
-                              const int32_t *bin_off, const DevStatus *st, float4 *rec,
+                              const int32_t *bin_off, const DevStatus *st, int nearest, float4 *rec,
                               hipStream_t s);
 // Splat, stage 3 fused with the forward real FFT along x: each block owns
 // ty x tz full x-rows, accumulates S_x, S_y, S_z and D in LDS (64-bit fixed
@@ -205,8 +207,9 @@ struct MeshCaps {
 };
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                               const int32_t *blk_counts, const int32_t *blk_offsets,
-                              const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
-                              const DevStatus *st, MeshCaps caps, DevStatus *host_status, hipStream_t s);
+                              const uint32_t *codes, float *verts, float *normals, int32_t *vidx,
+                              int4 *cells, const DevStatus *st, MeshCaps caps, DevStatus *host_status,
+                              hipStream_t s);
 // (host_status, if not null: pinned host memory that receives a copy of the
 // final status block, as launch_status_publish would write it)
 hipError_t launch_mc_triangles(const int4 *cells, const int32_t *vidx, const Grid &g, int32_t *tris,

@@ -718,12 +718,43 @@ __device__ __forceinline__ bool mesh_fits(const DevStatus *st, const MeshCaps &c
            st->mc_total[2] <= caps.cells && !(caps.check_invalid && (st->flags & kFlagInvalid));
 }
 
+// Derivative of A along axis b at grid point q (linear index l) by central
+// differences, one-sided on the grid's outer layer (physical units).
+__device__ __forceinline__ float grad_axis(const float *__restrict__ A, const Grid &g, size_t l,
+                                           const int q[3], int b, float aq) {
+    const size_t step = b == 0 ? 1 : b == 1 ? (size_t)g.n[0] : (size_t)g.n[0] * g.n[1];
+    const bool lo = q[b] == 0, hi = q[b] == g.n[b] - 1;
+    const float ap = hi ? aq : A[l + step];
+    const float am = lo ? aq : A[l - step];
+    return (ap - am) / ((lo || hi ? 1.0f : 2.0f) * g.h[b]);
+}
+
+// Output normal of the vertex on grid edge (q0, q0 + e_a) at parameter t:
+// -grad A (A is larger inside), the gradients of the two ends interpolated
+// linearly with t, normalised (zero where the interpolated gradient is).
+__device__ void edge_normal(const float *__restrict__ A, const Grid &g, size_t l0, const int q0[3], int a,
+                            size_t step, float a0, float a1, float t, float nv[3]) {
+    const int q1[3] = {q0[0] + (a == 0), q0[1] + (a == 1), q0[2] + (a == 2)};
+    float len2 = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const float g0 = grad_axis(A, g, l0, q0, b, a0);
+        const float g1 = grad_axis(A, g, l0 + step, q1, b, a1);
+        nv[b] = -fmaf(t, g1 - g0, g0);
+        len2 = fmaf(nv[b], nv[b], len2);
+    }
+    const float inv = len2 > 0.0f ? 1.0f / sqrtf(len2) : 0.0f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) nv[b] *= inv;
+}
+
 __global__ void __launch_bounds__(kMcThreads)
 mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_f32, Grid g,
                    const int32_t *__restrict__ list, const int32_t *__restrict__ blk_counts,
                    const int32_t *__restrict__ blk_off, const uint32_t *__restrict__ codes,
-                   float *__restrict__ verts, int32_t *__restrict__ vidx, int4 *__restrict__ cells,
-                   const DevStatus *st, MeshCaps caps, uint32_t *__restrict__ host_status) {
+                   float *__restrict__ verts, float *__restrict__ nrms, int32_t *__restrict__ vidx,
+                   int4 *__restrict__ cells, const DevStatus *st, MeshCaps caps,
+                   uint32_t *__restrict__ host_status) {
     __shared__ int red[12];
     __shared__ uint8_t s_ntri[256];
     // The status block is final here (the mesh kernels only read it): block 0
@@ -822,6 +853,14 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
                 verts[3 * (size_t)vbase + 0] = p[0];
                 verts[3 * (size_t)vbase + 1] = p[1];
                 verts[3 * (size_t)vbase + 2] = p[2];
+                if (nrms) {
+                    const int q0[3] = {x, y, z};
+                    float nv[3];
+                    edge_normal(A, g, l, q0, a, step, a0, a1, t, nv);
+                    nrms[3 * (size_t)vbase + 0] = nv[0];
+                    nrms[3 * (size_t)vbase + 1] = nv[1];
+                    nrms[3 * (size_t)vbase + 2] = nv[2];
+                }
                 vidx[3 * l + a] = vbase;
                 ++vbase;
             }
@@ -900,10 +939,11 @@ hipError_t launch_mc_count(const float *A, const float *level_f32, const int32_t
 
 hipError_t launch_mc_generate(const float *A, const float *level_f32, const int32_t *list, const Grid &g,
                               const int32_t *blk_counts, const int32_t *blk_offsets,
-                              const uint32_t *codes, float *verts, int32_t *vidx, int4 *cells,
-                              const DevStatus *st, MeshCaps caps, DevStatus *host_status, hipStream_t s) {
+                              const uint32_t *codes, float *verts, float *normals, int32_t *vidx,
+                              int4 *cells, const DevStatus *st, MeshCaps caps, DevStatus *host_status,
+                              hipStream_t s) {
     mc_generate_kernel<<<dim3(mc_grid(g, list)), dim3(kMcThreads), 0, s>>>(
-        A, level_f32, g, list, blk_counts, blk_offsets, codes, verts, vidx, cells, st, caps,
+        A, level_f32, g, list, blk_counts, blk_offsets, codes, verts, normals, vidx, cells, st, caps,
         reinterpret_cast<uint32_t *>(host_status));
     return hipGetLastError();
 }

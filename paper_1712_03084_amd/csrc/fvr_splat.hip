@@ -80,6 +80,14 @@ __device__ __forceinline__ int unit_exp(float mx) {
     return fr >= 1.0f - 0x1p-10f ? e + 1 : e;
 }
 
+// Nearest voxel centre of x (the non-weighted splat): the cell containing
+// the point, floor((x - bmin)/h) in float32 with each operation correctly
+// rounded, clamped to the grid.
+__device__ __forceinline__ int nearest_voxel(float x, float bmin, float h, int n) {
+    const int i = (int)floorf(__fdiv_rn(__fsub_rn(x, bmin), h));
+    return min(max(i, 0), n - 1);
+}
+
 __device__ __forceinline__ bool finite3(float a, float b, float c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
@@ -90,7 +98,7 @@ constexpr int kBinThreads = 1024;
 
 __global__ void __launch_bounds__(kBinThreads)
 bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
-                 const float *__restrict__ w, int m, Grid g, int32_t *__restrict__ bin_count,
+                 const float *__restrict__ w, int m, Grid g, int nearest, int32_t *__restrict__ bin_count,
                  int32_t *__restrict__ key, int32_t *__restrict__ rank, uint2 *__restrict__ blk_max,
                  DevStatus *st) {
     constexpr int kHash = 2 * kBinThreads;  // power of two, twice the block: probing always ends
@@ -118,14 +126,23 @@ bin_count_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
             const bool acc = x >= g.bmin[0] && x <= g.bmax[0] && y >= g.bmin[1] &&
                              y <= g.bmax[1] && z >= g.bmin[2] && z <= g.bmax[2];
             if (acc) {
-                wmax = wi;
-                wnmax = wi * fmaxf(fabsf(nx), fmaxf(fabsf(ny), fabsf(nz)));
-                int ix = (int)floorf(voxel_coord(x, g.bmin[0], g.h[0]));
-                int iy = (int)floorf(voxel_coord(y, g.bmin[1], g.h[1]));
-                int iz = (int)floorf(voxel_coord(z, g.bmin[2], g.h[2]));
-                ix = min(max(ix, -1), g.n[0] - 1);
-                iy = min(max(iy, -1), g.n[1] - 1);
-                iz = min(max(iz, -1), g.n[2] - 1);
+                // the nearest-voxel splat sums unweighted normals: W = 1 there
+                const float wu = nearest ? 1.0f : wi;
+                wmax = wu;
+                wnmax = wu * fmaxf(fabsf(nx), fmaxf(fabsf(ny), fabsf(nz)));
+                int ix, iy, iz;
+                if (nearest) {
+                    ix = nearest_voxel(x, g.bmin[0], g.h[0], g.n[0]);
+                    iy = nearest_voxel(y, g.bmin[1], g.h[1], g.n[1]);
+                    iz = nearest_voxel(z, g.bmin[2], g.h[2], g.n[2]);
+                } else {
+                    ix = (int)floorf(voxel_coord(x, g.bmin[0], g.h[0]));
+                    iy = (int)floorf(voxel_coord(y, g.bmin[1], g.h[1]));
+                    iz = (int)floorf(voxel_coord(z, g.bmin[2], g.h[2]));
+                    ix = min(max(ix, -1), g.n[0] - 1);
+                    iy = min(max(iy, -1), g.n[1] - 1);
+                    iz = min(max(iz, -1), g.n[2] - 1);
+                }
                 k = (iz + 1) * (g.n[1] + 1) + (iy + 1);
                 kx = ix + 1;
             } else {
@@ -225,7 +242,7 @@ __global__ void __launch_bounds__(256)
 bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
                    const float *__restrict__ w, int m, Grid g, const int32_t *__restrict__ key,
                    const int32_t *__restrict__ rank, const int32_t *__restrict__ bin_off,
-                   const DevStatus *__restrict__ st, float4 *__restrict__ rec) {
+                   const DevStatus *__restrict__ st, int nearest, float4 *__restrict__ rec) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const int k = key[i];
@@ -235,6 +252,15 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
     // < 2^kUnitBits (ldexp scales exactly, whatever the exponent)
     const int sw = kUnitBits - unit_exp(__uint_as_float(st->wmax_bits));
     const int sn = kUnitBits - unit_exp(__uint_as_float(st->wnmax_bits));
+    if (nearest) {
+        // one unit per point and its normal as given, at its nearest voxel
+        const float x = pts[3 * i];
+        rec[2 * pos] = make_float4(0.0f, 0.0f, 0.0f, ldexpf(1.0f, sw));
+        rec[2 * pos + 1] = make_float4(ldexpf(nrm[3 * i], sn), ldexpf(nrm[3 * i + 1], sn),
+                                       ldexpf(nrm[3 * i + 2], sn),
+                                       __int_as_float(nearest_voxel(x, g.bmin[0], g.h[0], g.n[0])));
+        return;
+    }
     const float wi = w ? w[i] : 1.0f;
     float f[3];
     int ix = 0;
@@ -270,6 +296,7 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
 // point an item spends 6 exponentials on its 4 x-voxels of the row: the
 // (y, z) factor of each Gaussian and, per Gaussian, the x factor at the first
 // centre and its ratio to the next (the later x factors follow by products).
+template <bool kNearest>
 __global__ void __launch_bounds__(kSplatThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
                    SplatConsts sc, FftAxis ax, DevStatus *__restrict__ st,
@@ -313,16 +340,18 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     const int by = tile % sc.tiles_y, bz = tile / sc.tiles_y;
     const int y0 = by * TY, z0 = bz * TZ;
 
-    // bins of footprint origins (iy, iz) whose 4-row footprints overlap the
-    // tile: iy in [y0-2, y0+TY], iz in [z0-2, z0+TZ] (clipped to [-1, N-1])
-    const int iz_lo = max(z0 - 2, -1), iz_hi = min(z0 + TZ, Nz - 1);
-    const int iy_lo = max(y0 - 2, -1), iy_hi = min(y0 + TY, Ny - 1);
+    // bins of origin rows (iy, iz) whose rows i + fp_lo .. i + fp_hi overlap
+    // the tile (4-row footprints: iy in [y0-2, y0+TY], clipped to [-1, N-1];
+    // nearest voxels: the tile's own rows)
+    const int flo = sc.fp_lo, fhi = sc.fp_hi;
+    const int iz_lo = max(z0 - fhi, -1), iz_hi = min(z0 + TZ - 1 - flo, Nz - 1);
+    const int iy_lo = max(y0 - fhi, -1), iy_hi = min(y0 + TY - 1 - flo, Ny - 1);
     const int nby = iy_hi - iy_lo + 1, nbins = nby * (iz_hi - iz_lo + 1);
     for (int t = threadIdx.x; t < nbins; t += blockDim.x) {
         const int iy = iy_lo + t % nby, iz = iz_lo + t / nby;
         const int kb = (iz + 1) * (Ny + 1) + (iy + 1);
-        const int qy0 = max(iy - 1, y0), qy1 = min(min(iy + 2, y0 + TY - 1), Ny - 1);
-        const int qz0 = max(iz - 1, z0), qz1 = min(min(iz + 2, z0 + TZ - 1), Nz - 1);
+        const int qy0 = max(iy + flo, y0), qy1 = min(min(iy + fhi, y0 + TY - 1), Ny - 1);
+        const int qz0 = max(iz + flo, z0), qz1 = min(min(iz + fhi, z0 + TZ - 1), Nz - 1);
         const int ny = max(qy1 - qy0 + 1, 0), nz = max(qz1 - qz0 + 1, 0);
         const int cnt = bin_off[kb + 1] - bin_off[kb];
         const int nchunk = (cnt + kChunkPts - 1) / kChunkPts;
@@ -444,6 +473,7 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int ox = 0; ox < 4; ++ox) {
+                if (kNearest && ox != 1) continue;  // the point's own voxel x = run_ix only
                 atomicAdd(&acc[c * aplane + l + ox], run_value(run[ox][c]));
                 run[ox][c] = kBias;
             }
@@ -470,6 +500,18 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
             if (ix != run_ix) {
                 flush();
                 run_ix = ix;
+            }
+            if (kNearest) {
+                // the non-weighted splat: the normal and one count, at the
+                // point's nearest voxel (run slot ox = 1 is voxel x = i0_x);
+                // adding an odd-significand s below 2^48 rounds as g s does
+                run[1][0] += odd_significand((double)r1.x);
+                run[1][1] += odd_significand((double)r1.y);
+                run[1][2] += odd_significand((double)r1.z);
+                run[1][3] += odd_significand((double)r0.w);
+                r0 = n0;
+                r1 = n1;
+                continue;
             }
             // offsets of this row's centre from the point, in voxels
             const float dy = r0.y + (float)(iy - qy);
@@ -591,7 +633,8 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
 static int g_splat_blocks = 256;
 
 hipError_t splat_configure() {
-    hipError_t e = raise_dynamic_lds((const void *)splat_fft_x_kernel);
+    hipError_t e = raise_dynamic_lds((const void *)splat_fft_x_kernel<false>);
+    if (e == hipSuccess) e = raise_dynamic_lds((const void *)splat_fft_x_kernel<true>);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
     e = hipGetDevice(&dev);
@@ -614,21 +657,21 @@ size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc) {
 int bin_count_blocks(int m) { return m > 0 ? (m + kBinThreads - 1) / kBinThreads : 0; }
 
 hipError_t launch_bin_count(const float *pts, const float *nrm, const float *w, int m,
-                            const Grid &g, int32_t *bin_count, int32_t *key, int32_t *rank,
+                            const Grid &g, int nearest, int32_t *bin_count, int32_t *key, int32_t *rank,
                             uint2 *blk_max, DevStatus *st, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    bin_count_kernel<<<dim3(bin_count_blocks(m)), dim3(kBinThreads), 0, s>>>(pts, nrm, w, m, g, bin_count, key,
-                                                                     rank, blk_max, st);
+    bin_count_kernel<<<dim3(bin_count_blocks(m)), dim3(kBinThreads), 0, s>>>(pts, nrm, w, m, g, nearest,
+                                                                     bin_count, key, rank, blk_max, st);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w, int m,
                               const Grid &g, const int32_t *key, const int32_t *rank,
-                              const int32_t *bin_off, const DevStatus *st, float4 *rec,
+                              const int32_t *bin_off, const DevStatus *st, int nearest, float4 *rec,
                               hipStream_t s) {
     if (m <= 0) return hipSuccess;
     bin_scatter_kernel<<<dim3((m + 255) / 256), dim3(256), 0, s>>>(pts, nrm, w, m, g, key, rank,
-                                                                   bin_off, st, rec);
+                                                                   bin_off, st, nearest, rec);
     return hipGetLastError();
 }
 
@@ -648,17 +691,19 @@ tile_list_kernel(const int32_t *__restrict__ bin_count, int nbins, int nscan,
         const int Ny = g.n[1], Nz = g.n[2];
         const int y0 = (tile % sc.tiles_y) * sc.ty, z0 = (tile / sc.tiles_y) * sc.tz;
         const int y1 = min(y0 + sc.ty, Ny) - 1, z1 = min(z0 + sc.tz, Nz) - 1;  // last tile rows
-        const int iz_lo = max(z0 - 2, -1), iz_hi = min(z0 + sc.tz, Nz - 1);
-        const int iy_lo = max(y0 - 2, -1), iy_hi = min(y0 + sc.ty, Ny - 1);
+        // origin rows i whose rows i + lo .. i + hi meet the tile
+        const int lo = sc.fp_lo, hi = sc.fp_hi;
+        const int iz_lo = max(z0 - hi, -1), iz_hi = min(z0 + sc.tz - 1 - lo, Nz - 1);
+        const int iy_lo = max(y0 - hi, -1), iy_hi = min(y0 + sc.ty - 1 - lo, Ny - 1);
         // the loads of a bin row are independent: unrolled, they are in flight together
         for (int iz = iz_lo; iz <= iz_hi; ++iz) {
-            const int nz = min(iz + 2, z1) - max(iz - 1, z0) + 1;
+            const int nz = min(iz + hi, z1) - max(iz + lo, z0) + 1;
             const int row = (iz + 1) * (Ny + 1) + 1;
             long long sum = 0;
 #pragma unroll 8
             for (int iy = iy_lo; iy <= iy_hi; ++iy)
-                sum += (long long)bin_count[row + iy] * (min(iy + 2, y1) - max(iy - 1, y0) + 1);
-            cost += nz * sum;
+                sum += (long long)bin_count[row + iy] * max(min(iy + hi, y1) - max(iy + lo, y0) + 1, 0);
+            cost += max(nz, 0) * sum;
         }
         occ[tile] = cost > 0 ? 1 : 0;
     }
@@ -783,8 +828,12 @@ hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const G
     const int tiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     const int blocks = tiles < g_splat_blocks ? tiles : g_splat_blocks;
     const size_t lds = splat_lds_bytes(g, sc);
-    splat_fft_x_kernel<<<dim3(blocks), dim3(kSplatThreads), lds, s>>>(
-        rec, bin_off, g, sc, ax, st, list, spec, v_out);
+    if (sc.nearest)
+        splat_fft_x_kernel<true><<<dim3(blocks), dim3(kSplatThreads), lds, s>>>(
+            rec, bin_off, g, sc, ax, st, list, spec, v_out);
+    else
+        splat_fft_x_kernel<false><<<dim3(blocks), dim3(kSplatThreads), lds, s>>>(
+            rec, bin_off, g, sc, ax, st, list, spec, v_out);
     return hipGetLastError();
 }
 

@@ -188,6 +188,31 @@ def test_marching_cubes_bit_exact_on_oracle_field_sphere(ctx):
     _mc_compare(ctx, r["A"], r["level"], f.dims, f.bbox)
 
 
+def test_vertex_normals_on_oracle_field(ctx):
+    """Vertex normals -grad A (central differences interpolated along the
+    edge, normalised) against the oracle's, vertex by vertex, on the
+    oracle's field rounded to float32; and outward on the sphere."""
+    f = synth.sphere_frame(seed=0, m=50_000, grid=64)
+    r = oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+    A32 = r["A"].astype(np.float32)
+    L32 = np.float32(r["level"])
+    mesh = ctx.extract(_dev(A32), f.bbox, float(L32), vertex_normals=True)
+    vo, to, _, no = oracle.extract(A32.astype(np.float64), float(L32), f.dims, f.bbox, with_normals=True)
+    n = mesh.normals.cpu().numpy().astype(np.float64)
+    err = np.abs(n - no).max()
+    v = mesh.vertices.cpu().numpy().astype(np.float64)
+    cosr = np.sum(n * v / np.linalg.norm(v, axis=1, keepdims=True), axis=1)
+    print(f"  normals: max err {err:.3g}, min cos to radial {cosr.min():.4f}")
+    assert n.shape == no.shape and err <= 1e-5
+    assert cosr.min() > 0.95
+    # the whole path returns the same normals for its own field
+    dev = _frame_dev(f)
+    rec = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox, vertex_normals=True)
+    A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
+    ext = ctx.extract(A, f.bbox, L, vertex_normals=True)
+    assert torch.equal(rec.normals, ext.normals) and torch.equal(rec.vertices, ext.vertices)
+
+
 @pytest.mark.parametrize("seed,dims", [(0, (36, 22, 30)), (1, (36, 22, 30)), (2, (30, 14, 18)),
                                        (3, (7, 5, 9))])
 def test_marching_cubes_bit_exact_random_fields(ctx, seed, dims):

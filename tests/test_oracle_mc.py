@@ -274,3 +274,36 @@ def test_ties_count_as_outside():
                np.count_nonzero(inside[:, 1:, :] != inside[:, :-1, :]) +
                np.count_nonzero(inside[1:, :, :] != inside[:-1, :, :]))
     assert len(v) == n_edges
+
+
+def test_vertex_normals_of_an_affine_field_are_exact():
+    """For A = c - <a, p>, central and one-sided differences are exact, so
+    every vertex normal -grad A / |grad A| is a / |a| (the outward
+    direction: A is larger inside)."""
+    dims = (9, 7, 8)
+    bbox = (0.0, 0.0, 0.0, 0.9, 1.4, 0.8)
+    h = np.array([0.1, 0.2, 0.1])
+    a = np.array([0.3, -0.5, 0.8])
+    z, y, x = np.meshgrid(*[(np.arange(n) + 0.5) * hh for n, hh in zip(dims[::-1], h[::-1])],
+                          indexing="ij")
+    A = 0.4 - (a[0] * x + a[1] * y + a[2] * z)
+    v, t, _, nrm = oracle.extract(A, 0.0, dims, bbox, with_normals=True)
+    assert len(v) > 20
+    np.testing.assert_allclose(nrm, np.tile(a / np.linalg.norm(a), (len(v), 1)), atol=1e-12)
+
+
+def test_vertex_normals_of_a_sphere_are_radial_and_outward():
+    """SDF ball A = R - |p|: normals are the radial direction up to O(h^2),
+    unit length, and agree with the winding of the triangles around them."""
+    n = 32
+    dims = (n, n, n)
+    bbox = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
+    c = (np.arange(n) + 0.5) * (2.0 / n) - 1.0
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    A = 0.7 - np.sqrt(x * x + y * y + z * z)
+    v, t, _, nrm = oracle.extract(A, 0.0, dims, bbox, with_normals=True)
+    np.testing.assert_allclose(np.linalg.norm(nrm, axis=1), 1.0, atol=1e-12)
+    radial = v / np.linalg.norm(v, axis=1, keepdims=True)
+    assert np.max(np.arccos(np.clip(np.sum(nrm * radial, axis=1), -1, 1))) < 0.03
+    fn = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+    assert np.all(np.sum(fn * (nrm[t[:, 0]] + nrm[t[:, 1]] + nrm[t[:, 2]]), axis=1) > 0)

@@ -137,3 +137,41 @@ def test_footprint_clipped_at_grid_border():
     # floor(-0.3) = -1 -> x offsets -2..1, only 0 and 1 exist
     assert np.array_equal(np.nonzero(D.any(axis=(0, 1)))[0], [0, 1])
     assert not D[:, :, -1].any()
+
+
+def test_nearest_splat_single_point_and_mean():
+    """Non-weighted splat (Sec. III-B, simplest version): one point puts its
+    normal on the one voxel that contains it; coincident points give the
+    mean of their normals; nothing else is touched; weights play no part."""
+    dims = (8, 6, 10)
+    bbox = (-1.0, -0.75, -1.25, 1.0, 0.75, 1.25)   # h = 0.25 on every axis
+    p = np.array([[0.1, 0.3, -0.6]], np.float32)    # cell (4, 4, 2): well inside
+    n = np.array([[0.2, -0.5, 0.7]], np.float32)
+    V, cnt, rej = oracle.splat_nearest(p, n, dims, bbox)
+    assert rej == 0 and cnt.sum() == 1 and cnt[2, 4, 4] == 1
+    expect = np.zeros_like(V)
+    expect[:, 2, 4, 4] = n[0]
+    np.testing.assert_array_equal(V, expect)
+    rng = np.random.default_rng(3)
+    q = np.tile(p, (5, 1)) + rng.uniform(-0.05, 0.05, (5, 3)).astype(np.float32)
+    nn = rng.standard_normal((5, 3)).astype(np.float32)
+    V, cnt, _ = oracle.splat_nearest(q, nn, dims, bbox)
+    assert cnt[2, 4, 4] == 5 and cnt.sum() == 5
+    np.testing.assert_allclose(V[:, 2, 4, 4], nn.astype(np.float64).mean(0), rtol=0, atol=1e-15)
+
+
+def test_nearest_splat_counts_faces_and_rejection():
+    """Points on the bbox's upper faces fall in the last cell (clamped);
+    points outside are rejected; every accepted point is counted once."""
+    dims = (4, 4, 4)
+    bbox = (0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    p = np.array([[1.0, 1.0, 1.0], [0.0, 0.0, 0.0], [1.5, 0.5, 0.5], [0.5, 0.5, 0.5]], np.float32)
+    n = np.ones((4, 3), np.float32)
+    V, cnt, rej = oracle.splat_nearest(p, n, dims, bbox)
+    assert rej == 1 and cnt.sum() == 3
+    assert cnt[3, 3, 3] == 1 and cnt[0, 0, 0] == 1 and cnt[2, 2, 2] == 1
+    rng = np.random.default_rng(4)
+    q = rng.uniform(-0.2, 1.2, (2000, 3)).astype(np.float32)
+    V, cnt, rej = oracle.splat_nearest(q, rng.standard_normal((2000, 3)).astype(np.float32), dims, bbox)
+    inside = np.all((q >= 0) & (q <= 1), axis=1)
+    assert rej == int((~inside).sum()) and cnt.sum() == int(inside.sum())

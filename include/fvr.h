@@ -190,6 +190,35 @@ fvr_status fvr_batch_use_graph(fvr_batch *batch, int enable);
 fvr_status fvr_batch_reconstruct(fvr_batch *batch, const fvr_frame *frames, fvr_mesh *meshes, int n);
 const char *fvr_batch_last_error(const fvr_batch *batch);
 
+/* The front end of Sec. III-A: K depth maps (one per calibrated view) to the
+ * raw oriented, confidence-weighted points that fvr_reconstruct takes.  Per
+ * foreground pixel u (depth > 0 and finite): the point X = R X_loc + t with
+ * X_loc = ((u_x - c_x) D / f_x, (u_y - c_y) D / f_y, D); the normal R N_loc,
+ * N_loc the mean of the unit normals of the triangles of an organized
+ * triangulation that contain u (each 2 x 2 pixel quad is split along the
+ * diagonal whose ends differ less in depth; a triangle is kept when its three
+ * pixels are foreground and no two of its depths differ by more than
+ * step_threshold, the step-discontinuity constraint); the weight W = W1 W2
+ * with W1 = max(<-X_loc/|X_loc|, N_loc>, 0) (viewing angle) and W2 the
+ * fraction of foreground pixels in the (2 box_radius + 1)^2 square around u
+ * (outside the image counts as background; silhouette confidence).  Pixels
+ * in no kept triangle give no point.  Points are written view by view in
+ * raster order. */
+typedef struct {
+    const float *depth;    /* device, views x height x width, metres along the optical axis */
+    const float *cameras;  /* host, views x 16: fx, fy, cx, cy, R (3 x 3 row-major,
+                              camera to world), t (camera centre in world) */
+    int32_t views;         /* 1..16 */
+    int32_t height, width; /* pixels per map (at most 2^24) */
+    float step_threshold;  /* metres; the paper's captures: a few cm */
+    int32_t box_radius;    /* pixels; 10 in the paper's experiments */
+} fvr_depth_views;
+/* Writes n_points points (device arrays of capacity points x 3, normals x 3,
+ * weights), waiting for completion.  FVR_E_CAPACITY: *n_points holds the
+ * required count and nothing is written. */
+fvr_status fvr_depth_to_points(fvr_ctx *ctx, const fvr_depth_views *views, float *points, float *normals,
+                               float *weights, int64_t capacity, int64_t *n_points);
+
 /* Work counters of the context's last completed fvr_reconstruct,
  * fvr_reconstruct_noalloc or fvr_indicator call, from the status block that
  * call read back (no device work): how much of the grid the sparse passes

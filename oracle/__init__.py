@@ -14,7 +14,11 @@ Steps, each a plain and literal rendering of the method:
   level      mean of the trilinearly sampled A at the accepted input points
              (C loop, compensated sum)
   extract    marching cubes with the rule-generated table (``mc_rule``)
-             and a welded, indexed mesh (C loops)
+             and a welded, indexed mesh, with optional vertex normals
+             (C loops)
+  splat_nearest  the non-weighted splat: each normal to its nearest voxel,
+             mean per voxel (C loop)
+  frontend   depth maps to oriented, weighted points (Sec. III-A; numpy)
 
 Readings of points the paper leaves open are stated where they are used.
 """
@@ -26,7 +30,7 @@ import subprocess
 
 import numpy as np
 
-from . import mc_rule
+from . import frontend, mc_rule  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fvr_oracle.c")

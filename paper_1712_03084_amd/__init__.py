@@ -58,6 +58,12 @@ class _Stats(ctypes.Structure):
         "points_used", "points_rejected")]
 
 
+class _DepthViews(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("cameras", ctypes.c_void_p), ("views", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("step_threshold", ctypes.c_float),
+                ("box_radius", ctypes.c_int32)]
+
+
 class _Mesh(ctypes.Structure):
     _fields_ = [("vertices", ctypes.c_void_p), ("triangles", ctypes.c_void_p),
                 ("vertex_capacity", ctypes.c_int64), ("triangle_capacity", ctypes.c_int64),
@@ -120,6 +126,8 @@ def load_library():
     lib.fvr_check_grid.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
     lib.fvr_check_frame.argtypes = [ctypes.POINTER(_Frame)]
     lib.fvr_last_stats.argtypes = [P, ctypes.POINTER(_Stats)]
+    lib.fvr_depth_to_points.argtypes = [P, ctypes.POINTER(_DepthViews), P, P, P, i64,
+                                        ctypes.POINTER(i64)]
     lib.fvr_batch_create.argtypes = [I, P, I, ctypes.POINTER(P)]
     lib.fvr_batch_destroy.argtypes = [P]
     lib.fvr_batch_destroy.restype = None
@@ -143,7 +151,7 @@ def load_library():
     for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_reconstruct_noalloc",
                "fvr_indicator", "fvr_extract",
                "fvr_debug_splat", "fvr_check_grid", "fvr_check_frame", "fvr_last_stats", "fvr_mc_table",
-               "fvr_timing_enable", "fvr_batch_create", "fvr_batch_set_stream", "fvr_batch_use_graph",
+               "fvr_timing_enable", "fvr_depth_to_points", "fvr_batch_create", "fvr_batch_set_stream", "fvr_batch_use_graph",
                "fvr_batch_reconstruct",
                "fvr_timing_select", "fvr_timing_reset", "fvr_timing_get"):
         getattr(lib, fn).restype = I
@@ -340,6 +348,34 @@ class Context:
         return self._run_mesh(lambda m: self.lib.fvr_reconstruct(self.handle, ctypes.byref(f),
                                                                  ctypes.byref(m)),
                               dims, out, vertex_capacity, triangle_capacity, vertex_normals)
+
+    def depth_to_points(self, depth, cameras, step_threshold=0.05, box_radius=10, capacity=None):
+        """The front end of Sec. III-A on the device: depth (K, H, W) float32
+        tensor on this device (metres; <= 0 is background), cameras (K, 16)
+        array (fx, fy, cx, cy, R row-major camera to world, t).  Returns
+        (points [M,3], normals [M,3], weights [M]) float32 tensors."""
+        import numpy as np
+        torch = _torch()
+        if depth.device.type != "cuda" or depth.device.index != self.device:
+            raise ValueError(f"depth must live on cuda:{self.device}")
+        if depth.dtype != torch.float32 or depth.dim() != 3:
+            raise TypeError("depth must be a (K, H, W) float32 tensor")
+        depth = depth.contiguous()
+        K, H, W = depth.shape
+        cams = np.ascontiguousarray(np.asarray(cameras, np.float32).reshape(K, 16))
+        cap = K * H * W if capacity is None else int(capacity)
+        dev = f"cuda:{self.device}"
+        pts = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+        nrm = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+        w = torch.empty((max(cap, 1),), dtype=torch.float32, device=dev)
+        dv = _DepthViews(depth.data_ptr(), cams.ctypes.data, K, H, W, float(step_threshold), int(box_radius))
+        n = ctypes.c_int64()
+        self._stream()
+        _check(self.lib, self.lib.fvr_depth_to_points(self.handle, ctypes.byref(dv), pts.data_ptr(),
+                                                      nrm.data_ptr(), w.data_ptr(), cap, ctypes.byref(n)),
+               self.handle)
+        m = n.value
+        return pts[:m], nrm[:m], w[:m]
 
     def last_stats(self) -> dict:
         """Work counters of the last reconstruction or indicator call

@@ -20,7 +20,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfvr.so")
 
 SOURCES = ["fvr_api.cpp", "fvr_mc_table.cpp", "fvr_splat.hip", "fvr_fft.hip", "fvr_mc.hip",
-           "fvr_static.hip"]
+           "fvr_static.hip", "fvr_frontend.hip"]
 ARCH = "gfx950"
 
 

@@ -99,7 +99,8 @@ struct fvr_ctx {
     uint64_t arena_epoch = 0;
     uint64_t scratch_gen = 0;  // bumped whenever an owned buffer moves
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
-        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm, mc_list;
+        lvl_sum, lvl_cnt, status, level_f32, scan_part, occ, zocc, tiles, tile_pend, blk_max, rowmm, mc_list,
+        fe_rowcnt, fe_dense, fe_flag, fe_off;
     DevStatus *host_status = nullptr;
     fvr_stats last{};  // sizes of the last call; the counters come from host_status
     uint32_t timing_mask = 0;  // bit k: time kernel k
@@ -673,7 +674,8 @@ void fvr_destroy(fvr_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
                       &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max, &c->rowmm, &c->mc_list};
+                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max, &c->rowmm, &c->mc_list,
+                      &c->fe_rowcnt, &c->fe_dense, &c->fe_flag, &c->fe_off};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {
@@ -1066,6 +1068,57 @@ fvr_status fvr_batch_reconstruct(fvr_batch *b, const fvr_frame *frames, fvr_mesh
 }
 
 const char *fvr_batch_last_error(const fvr_batch *b) { return b ? b->err.c_str() : g_error.c_str(); }
+
+fvr_status fvr_depth_to_points(fvr_ctx *c, const fvr_depth_views *dv, float *points, float *normals,
+                               float *weights, int64_t capacity, int64_t *n_points) {
+    if (!c) return fail(nullptr, FVR_E_INVALID, "context is NULL");
+    if (!dv || !n_points) return fail(c, FVR_E_INVALID, "views or n_points is NULL");
+    *n_points = 0;
+    if (!dv->depth || !dv->cameras) return fail(c, FVR_E_INVALID, "depth or cameras is NULL");
+    if (dv->views < 1 || dv->views > kFeMaxViews) return fail(c, FVR_E_INVALID, "views must be 1..16");
+    if (dv->height < 2 || dv->width < 2 || (int64_t)dv->height * dv->width > (1 << 24))
+        return fail(c, FVR_E_INVALID, "depth maps must be at least 2 x 2 and at most 2^24 pixels");
+    const int64_t npix = (int64_t)dv->views * dv->height * dv->width;
+    if (npix > FVR_MAX_POINTS) return fail(c, FVR_E_INVALID, "too many pixels");
+    if (!(dv->step_threshold >= 0.0f) || !std::isfinite(dv->step_threshold))
+        return fail(c, FVR_E_INVALID, "step_threshold must be finite and >= 0");
+    if (dv->box_radius < 0 || dv->box_radius > 1000) return fail(c, FVR_E_INVALID, "box_radius must be 0..1000");
+    if (capacity < 0 || (capacity > 0 && (!points || !normals || !weights)))
+        return fail(c, FVR_E_INVALID, "output arrays are NULL");
+    FeCams cams{};
+    for (int k = 0; k < dv->views; ++k)
+        for (int j = 0; j < 16; ++j) {
+            const float x = dv->cameras[16 * k + j];
+            if (!std::isfinite(x)) return fail(c, FVR_E_INVALID, "camera parameters must be finite");
+            cams.c[k][j] = x;
+        }
+    for (int k = 0; k < dv->views; ++k)
+        if (cams.c[k][0] == 0.0f || cams.c[k][1] == 0.0f) return fail(c, FVR_E_INVALID, "zero focal length");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    const int n = (int)npix;
+    GET(c, c->status, sizeof(DevStatus), "status");
+    GET(c, c->fe_rowcnt, sizeof(int32_t) * (size_t)n, "front-end row counts");
+    GET(c, c->fe_dense, sizeof(float) * 7 * (size_t)n, "front-end pixels");
+    GET(c, c->fe_flag, sizeof(int32_t) * (size_t)n, "front-end flags");
+    GET(c, c->fe_off, sizeof(int32_t) * ((size_t)n + 1), "front-end offsets");
+    GET(c, c->scan_part, sizeof(int32_t) * (size_t)scan_partials(n), "scan scratch");
+    FeParams fp{dv->views, dv->height, dv->width, dv->box_radius, dv->step_threshold};
+    DevStatus *st = P<DevStatus>(c->status);
+    hipStream_t s = c->stream;
+    HIP_TRY(c, launch_prep(st, nullptr, 0, s), "prep");
+    HIP_TRY(c, launch_fe_pixels(dv->depth, fp, cams, P<int32_t>(c->fe_rowcnt), P<float>(c->fe_dense),
+                                P<int32_t>(c->fe_flag), s), "front end");
+    HIP_TRY(c, launch_scan(P<int32_t>(c->fe_flag), P<int32_t>(c->fe_off), n, 1, P<int32_t>(c->scan_part),
+                           &st->fe_points, s), "front-end scan");
+    HIP_TRY(c, launch_fe_scatter(P<float>(c->fe_dense), P<int32_t>(c->fe_flag), P<int32_t>(c->fe_off), n, st,
+                                 capacity, points, normals, weights, s), "front-end scatter");
+    HIP_TRY(c, launch_status_publish(st, c->host_status, s), "status readback");
+    fvr_status r = sync(c);
+    if (r != FVR_OK) return r;
+    *n_points = c->host_status->fe_points;
+    if (*n_points > capacity) return fail(c, FVR_E_CAPACITY, "point output capacity too small");
+    return FVR_OK;
+}
 
 fvr_status fvr_last_stats(const fvr_ctx *c, fvr_stats *out) {
     if (!c || !out) return fail(nullptr, FVR_E_INVALID, "context or out is NULL");

@@ -73,6 +73,7 @@ struct DevStatus {
     int32_t n_busy;       // splat tiles that some point reaches
     int32_t mc_active;    // marching-cubes blocks left for the classification (mc_classify)
     int32_t n_zplanes;    // z planes some splat tile reaches (read by the z pass)
+    int32_t fe_points;    // points the depth front end produced
 };
 constexpr uint32_t kFlagInvalid = 1u;
 constexpr uint32_t kFlagOpen = 2u;
@@ -97,7 +98,7 @@ unsigned char *statics_scratch(int device);              // FVR_NOALLOC_SCRATCH_
 // Copy of the status block into pinned host memory (hipHostMalloc) by a kernel.
 hipError_t launch_status_publish(const DevStatus *st, DevStatus *host, hipStream_t s);
 
-// Exclusive scan of `n` items of `C` interleaved int32 components (C = 3):
+// Exclusive scan of `n` items of `C` interleaved int32 components (C = 1 or 3):
 // out[i*C + c] = sum_{j<i} in[j*C + c]; out[n*C + c] = total; totals[c] = total.
 // `partial` is scratch of scan_partials(n) * C ints.
 int scan_partials(int n);
@@ -222,4 +223,21 @@ hipError_t fft_configure();
 // Host-side marching-cubes table generation (library's own generator).
 void mc_generate_table(uint8_t counts[256], int8_t edges[256 * kMcRow]);
 
+}  // namespace fvr
+
+namespace fvr {
+// Depth front end (Sec. III-A): depth maps to oriented, weighted points.
+constexpr int kFeMaxViews = 16;
+struct FeCams {
+    float c[kFeMaxViews][16];  // per view: fx fy cx cy, R (3x3 row-major, camera to world), t
+};
+struct FeParams {
+    int views, height, width, radius;
+    float tau;  // largest depth difference inside a triangle
+};
+hipError_t launch_fe_pixels(const float *depth, const FeParams &fp, const FeCams &cams, int32_t *rowcnt,
+                            float *dense, int32_t *flag, hipStream_t s);
+hipError_t launch_fe_scatter(const float *dense, const int32_t *flag, const int32_t *off, int n,
+                             const DevStatus *st, long long cap, float *pts, float *nrm, float *w,
+                             hipStream_t s);
 }  // namespace fvr

@@ -74,6 +74,7 @@ __global__ void prep_kernel(DevStatus *st, int32_t *bins, int nbins) {
         st->n_busy = 0;
         st->mc_active = 0;
         st->n_zplanes = 0;
+        st->fe_points = 0;
     }
     if (bins && i < nbins) bins[i] = 0;
 }
@@ -279,9 +280,15 @@ int scan_partials(int n) { return scan_tiles(n); }
 hipError_t launch_scan(const int32_t *in, int32_t *out, int n, int C, int32_t *partial,
                        int32_t *totals, hipStream_t s) {
     const int nb = n > 0 ? scan_partials(n) : 1;
-    if (C != 3) return hipErrorInvalidValue;
-    scan_reduce_kernel<3><<<nb, kScanBlock, 0, s>>>(in, n, partial);
-    scan_down_kernel<3><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
+    if (C == 3) {
+        scan_reduce_kernel<3><<<nb, kScanBlock, 0, s>>>(in, n, partial);
+        scan_down_kernel<3><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
+    } else if (C == 1) {
+        scan_reduce_kernel<1><<<nb, kScanBlock, 0, s>>>(in, n, partial);
+        scan_down_kernel<1><<<nb, kScanBlock, 0, s>>>(in, out, n, partial, totals);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

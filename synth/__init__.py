@@ -41,6 +41,7 @@ __all__ = [
     "repose",
     "subsample",
     "batch_frames",
+    "depth_views",
     "BATCH_GRIDS",
 ]
 
@@ -256,9 +257,9 @@ CAM_FY = (CAM_H / 2) / math.tan(math.radians(30.0))
 CAM_CX, CAM_CY = (CAM_W - 1) / 2.0, (CAM_H - 1) / 2.0
 
 
-def _render_view(prims, theta, rng, dist=2.5, height=1.0, ss=4,
-                 noise_mm=1.5, jump=0.05):
-    """Ray-cast one depth view and return (points, normals, weights) in world."""
+def _camera(theta, dist=2.5, height=1.0):
+    """Camera centre C and camera-to-world rotation (columns: right, down,
+    forward) of a view at angle theta on the circle, looking at the body axis."""
     C = np.array([dist * math.sin(theta), height, dist * math.cos(theta)])
     f = np.array([0.0, height, 0.0]) - C
     f /= np.linalg.norm(f)
@@ -266,7 +267,13 @@ def _render_view(prims, theta, rng, dist=2.5, height=1.0, ss=4,
     right = np.cross(f, up)
     right /= np.linalg.norm(right)
     down = np.cross(f, right)
-    Rcw = np.stack([right, down, f], axis=1)  # camera -> world (columns)
+    return C, np.stack([right, down, f], axis=1)
+
+
+def _render_view(prims, theta, rng, dist=2.5, height=1.0, ss=4,
+                 noise_mm=1.5, jump=0.05):
+    """Ray-cast one depth view and return (points, normals, weights) in world."""
+    C, Rcw = _camera(theta, dist, height)  # camera -> world (columns)
 
     # pixel window covering the body (project a padded world box)
     corners = np.array([[x, y, z] for x in (-1.0, 1.0) for y in (-0.05, 1.9)
@@ -488,3 +495,39 @@ def batch_frames(n: int = 16, seed: int = 4000, captures: dict | None = None):
                          name=f"batch{seed}_{f}_{v}v_{g}_{fr.n_points}",
                          info={"views": v, "m": fr.n_points, "grid": g}))
     return out, captures
+
+
+# ---------------------------------------------------------------------------
+# Raw depth maps (the input of the front end of Sec. III-A)
+# ---------------------------------------------------------------------------
+def depth_views(seed: int = 1, views: int = 4, noise_mm: float = 1.5, dist: float = 2.5,
+                height: float = 1.0):
+    """K full depth maps of the posed human proxy at the camera's native
+    512 x 424 resolution, one ray per pixel: depth along the optical axis in
+    metres (0 where the ray misses), noise N(0, (noise_mm (z / 1 m)^2)^2).
+
+    Returns (depth (K, 424, 512) float32, cams (K, 16) float32, prims): each
+    camera row is fx, fy, cx, cy, then the camera-to-world rotation R (3 x 3,
+    row-major; columns right, down, forward) and the centre t, so that pixel
+    (u, v) at depth D is the camera-space point ((u - cx) D / fx,
+    (v - cy) D / fy, D) and the world point R x + t."""
+    rng = np.random.default_rng(seed)
+    prims = _proxy_primitives(rng)
+    depth = np.zeros((views, CAM_H, CAM_W), np.float32)
+    cams = np.zeros((views, 16), np.float32)
+    uu, vv = np.meshgrid(np.arange(CAM_W, dtype=np.float64), np.arange(CAM_H, dtype=np.float64))
+    dc = np.stack([(uu - CAM_CX) / CAM_FX, (vv - CAM_CY) / CAM_FY, np.ones_like(uu)], axis=-1)
+    dn = np.linalg.norm(dc, axis=-1)
+    for k in range(views):
+        C, Rcw = _camera(2.0 * math.pi * k / views, dist, height)
+        dw = (dc / dn[..., None]) @ Rcw.T
+        t = _ray_hits(prims, C, dw.reshape(-1, 3)).reshape(uu.shape)
+        z = t / dn
+        hit = np.isfinite(z)
+        zn = np.where(hit, z, 0.0)
+        zn = zn + hit * rng.standard_normal(z.shape) * (noise_mm * 1e-3) * zn ** 2
+        depth[k] = zn
+        cams[k, :4] = (CAM_FX, CAM_FY, CAM_CX, CAM_CY)
+        cams[k, 4:13] = Rcw.reshape(-1)
+        cams[k, 13:16] = C
+    return depth, cams, prims

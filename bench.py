@@ -243,6 +243,75 @@ def bench_batch(args, fvr, synth, torch, np, dev):
                                                   "tuned_us": v["us"]} for k, v in tuned.items()}}
 
 
+def bench_serve(args, fvr, synth, np, captures):
+    """Serving (config 5): three capture stations (128^3 with 4 views, 192^3
+    and 256^3 with 6) emit frames at 30 Hz each with exponential
+    inter-arrival times; the server admits them by device memory as slots
+    free up.  Frames come from per-station pools (reposed copies of one
+    capture each, inputs in pinned host memory, uploaded per request);
+    latency runs from arrival to the mesh in host memory."""
+    import torch
+    stations = [("128^3, 4 views", captures["proxy128"], (128, 128, 128), None),
+                ("192^3, 6 views", captures["proxy256b"], (192, 192, 192), 550_000),
+                ("256^3, 6 views", captures["proxy256"], (256, 256, 256), None)]
+    pools = []
+    for si, (name, cap, dims, m) in enumerate(stations):
+        base = synth.subsample(cap, m, seed=500 + si) if m else cap
+        pool = []
+        for j in range(args.serve_pool):
+            f = base if j == 0 else synth.repose(base, seed=9000 + 100 * si + j)
+            pool.append(tuple(torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+                              for a in (f.points, f.normals, f.weights)))
+        pools.append((name, dims, base.bbox, pool, base.n_points))
+    srv = fvr.Server(slots=args.serve_slots, hbm_budget=int(args.serve_budget_gib * (1 << 30)))
+    # warm the slots up: every station's shape once per slot, so the
+    # measured stream runs on grown scratch
+    for _ in range(args.serve_slots):
+        for name, dims, bbox, pool, _m in pools:
+            srv.submit(*pool[0], dims, bbox)
+    srv.drain()
+    rng = np.random.default_rng(5000)
+    arrivals = []
+    for si in range(len(pools)):
+        t = 0.0
+        while True:
+            t += rng.exponential(1.0 / args.serve_rate)
+            if t > args.serve_seconds:
+                break
+            arrivals.append((t, si, int(rng.integers(0, args.serve_pool))))
+    arrivals.sort()
+    print(f"[bench] serving: {len(arrivals)} requests over {args.serve_seconds} s", file=sys.stderr, flush=True)
+    results = []
+    t0 = time.perf_counter()
+    base_ms = None
+    for t, si, j in arrivals:
+        while time.perf_counter() - t0 < t:
+            results += srv.poll()
+        name, dims, bbox, pool, _m = pools[si]
+        srv.submit(*pool[j], dims, bbox, user=si)
+    results += srv.drain()
+    elapsed = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    ok = [r for r in results if r["status"] == 0]
+    lat = np.array([r["latency_ms"] for r in ok])
+    per = {}
+    for si, (name, dims, bbox, pool, m) in enumerate(pools):
+        ls = np.array([r["latency_ms"] for r in ok if r["user"] == si])
+        per[name] = {"frames": int(len(ls)), "points": m,
+                     "p50_ms": round(float(np.percentile(ls, 50)), 3) if len(ls) else None,
+                     "p99_ms": round(float(np.percentile(ls, 99)), 3) if len(ls) else None}
+    return {"workload": "3 stations x 30 Hz Poisson (128^3 4 views, 192^3 6 views, 256^3 6 views), "
+                        f"{args.serve_seconds} s stream, pools of {args.serve_pool} frames per station",
+            "requests": len(arrivals), "completed": len(ok), "unit": "frames/s",
+            "value": round(len(ok) / elapsed, 2),
+            "offered_rate": round(len(arrivals) / args.serve_seconds, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "stations": per, "slots": args.serve_slots, "max_in_flight": info["max_in_flight"],
+            "device_bytes": info["device_bytes"], "budget_bytes": info["budget"],
+            "latency": "arrival -> mesh in host memory (upload, all stages, download)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +331,12 @@ def main():
                          "measured after the headline one, batched and plain (0: skip)")
     ap.add_argument("--batch-slots", default="1,2,4,8,16",
                     help="slot counts of the batched measurement; the fastest is reported")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the simulated serving stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=30.0, help="frames/s per station")
+    ap.add_argument("--serve-pool", type=int, default=16, help="frames per station pool")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="measure the batched workload on the default plans")
     ap.add_argument("--tune-cache", default=None, help="JSON file the autotuner's choices are added to")
@@ -292,9 +367,9 @@ def main():
     print(f"[bench] generating {npose} capture(s) of {args.config}, pool of {args.pool}",
           file=sys.stderr, flush=True)
     base_seed = synth.CONFIGS[args.config]["seed"]
-    caps = [_load_frame(synth, args.config, base_seed + i, args.cache) for i in range(npose)]
-    frames = list(caps) + [synth.repose(caps[i % npose], seed=base_seed + 100 + i)
-                           for i in range(args.pool - npose)]
+    caps_pool = [_load_frame(synth, args.config, base_seed + i, args.cache) for i in range(npose)]
+    frames = list(caps_pool) + [synth.repose(caps_pool[i % npose], seed=base_seed + 100 + i)
+                                for i in range(args.pool - npose)]
     dev = torch.device("cuda:0")
     pool = [tuple(torch.from_numpy(a).to(dev) for a in (f.points, f.normals, f.weights))
             for f in frames]
@@ -431,9 +506,11 @@ def main():
     # secondary workloads: throughput and latency of the same call on other
     # grids (their own pools of one capture and reposed copies)
     sec = {}
+    sec_caps = {}
     for name in [x for x in args.secondary.split(",") if x and x != args.config]:
         print(f"[bench] secondary workload {name}", file=sys.stderr, flush=True)
         cap = _load_frame(synth, name, synth.CONFIGS[name]["seed"], args.cache)
+        sec_caps[name] = cap
         sframes = [cap] + [synth.repose(cap, seed=7000 + i) for i in range(15)]
         sdims, sbbox = cap.dims, cap.bbox
         sprep = [ctx.prepare(*(torch.from_numpy(a).to(dev) for a in (f.points, f.normals, f.weights)),
@@ -466,6 +543,13 @@ def main():
 
     if args.batch > 0:
         result["batched"] = bench_batch(args, fvr, synth, torch, np, dev)
+
+    if args.serve_seconds > 0:
+        caps = {"proxy256": caps_pool[0],
+                "proxy256b": caps_pool[1] if len(caps_pool) > 1 else synth.repose(caps_pool[0], seed=77),
+                "proxy128": sec_caps.get("proxy128") or _load_frame(synth, "proxy128",
+                                                                   synth.CONFIGS["proxy128"]["seed"], args.cache)}
+        result["serving"] = bench_serve(args, fvr, synth, np, caps)
 
     if not args.no_cpu_baseline:
         # the oracle as it stands (FP64), on whole frames of the same workload:

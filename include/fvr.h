@@ -219,6 +219,59 @@ typedef struct {
 fvr_status fvr_depth_to_points(fvr_ctx *ctx, const fvr_depth_views *views, float *points, float *normals,
                                float *weights, int64_t capacity, int64_t *n_points);
 
+/* Serving with continuous batching.  A server owns `slots` contexts (one
+ * frame each at a time, each on its own stream) and a copy stream.  Requests
+ * carry HOST arrays (the inputs, valid until the request's result has been
+ * polled; the mesh outputs, filled before the result is returned) and wait
+ * in arrival order.  A request is admitted when a slot is free and the
+ * device memory the slots would then hold (scratch, inputs and mesh of each)
+ * stays within hbm_budget bytes; one that cannot fit even with every other
+ * slot idle is refused (result status FVR_E_NOMEM).  An admitted request's
+ * upload runs on the copy stream and its stages on its slot's stream, so
+ * uploads overlap compute and frames of different slots overlap; once its
+ * counts are known its mesh comes back in exactly its size.  Each result is
+ * the one fvr_reconstruct gives for the frame, bit for bit, whatever else
+ * runs beside it.  fvr_server_poll harvests finished work, admits waiting
+ * requests as slots and memory free up, and returns finished results in
+ * completion order.  A server is used by one host thread at a time. */
+#define FVR_REQUEST_PINNED 1u /* the request's input arrays are pinned host memory */
+typedef struct {
+    const float *points, *normals, *weights; /* host, M x 3, M x 3, M (weights may be NULL) */
+    int64_t n_points;
+    int32_t dims[3];
+    float bbox[6];
+    uint32_t options;                        /* FVR_SPLAT_* */
+    uint32_t flags;                          /* FVR_REQUEST_* */
+    float *vertices;                         /* host out: vertex_capacity x 3 */
+    int32_t *triangles;                      /* host out: triangle_capacity x 3 */
+    float *normals_out;                      /* host out, optional: vertex_capacity x 3 */
+    int64_t vertex_capacity, triangle_capacity;
+    void *user;                              /* returned in the result */
+} fvr_request;
+typedef struct {
+    uint64_t ticket;
+    fvr_status status;                       /* FVR_E_CAPACITY: n_vertices / n_triangles required */
+    int64_t n_vertices, n_triangles, n_rejected;
+    double level;
+    uint32_t flags;                          /* FVR_FLAG_* */
+    void *user;
+    double submit_ms, admit_ms, done_ms;     /* host steady clock */
+    char error[96];
+} fvr_result;
+typedef struct {
+    int64_t pending, in_flight, results_waiting, admitted, completed, refused, max_in_flight;
+    int64_t device_bytes, budget;
+} fvr_server_stats;
+typedef struct fvr_server fvr_server;
+fvr_status fvr_server_create(int device, int slots, size_t hbm_budget, fvr_server **out);
+void fvr_server_destroy(fvr_server *server);
+/* Queue a request (checked on the host first); never waits for the device. */
+fvr_status fvr_server_submit(fvr_server *server, const fvr_request *request, uint64_t *ticket);
+/* Harvest, admit, and return up to max_results finished results. */
+fvr_status fvr_server_poll(fvr_server *server, fvr_result *out, int max_results, int *n_results);
+fvr_status fvr_server_info(const fvr_server *server, fvr_server_stats *out);
+const char *fvr_server_last_error(const fvr_server *server);
+
 /* Work counters of the context's last completed fvr_reconstruct,
  * fvr_reconstruct_noalloc or fvr_indicator call, from the status block that
  * call read back (no device work): how much of the grid the sparse passes

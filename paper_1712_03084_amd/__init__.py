@@ -21,7 +21,7 @@ import os
 from collections import namedtuple
 
 __all__ = [
-    "FvrError", "FvrUnavailable", "Context", "PreparedFrame", "Batch", "PreparedBatch", "Mesh",
+    "FvrError", "FvrUnavailable", "Context", "PreparedFrame", "Batch", "PreparedBatch", "Server", "Mesh",
     "reconstruct", "indicator",
     "extract", "debug_splat", "mc_table", "check_grid", "check_frame", "library_path", "load_library",
     "STATUS",
@@ -62,6 +62,28 @@ class _DepthViews(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_void_p), ("cameras", ctypes.c_void_p), ("views", ctypes.c_int32),
                 ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("step_threshold", ctypes.c_float),
                 ("box_radius", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("normals", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("n_points", ctypes.c_int64), ("dims", ctypes.c_int32 * 3), ("bbox", ctypes.c_float * 6),
+                ("options", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("vertices", ctypes.c_void_p),
+                ("triangles", ctypes.c_void_p), ("normals_out", ctypes.c_void_p),
+                ("vertex_capacity", ctypes.c_int64), ("triangle_capacity", ctypes.c_int64),
+                ("user", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int), ("n_vertices", ctypes.c_int64),
+                ("n_triangles", ctypes.c_int64), ("n_rejected", ctypes.c_int64), ("level", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("user", ctypes.c_void_p), ("submit_ms", ctypes.c_double),
+                ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double), ("error", ctypes.c_char * 96)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "pending", "in_flight", "results_waiting", "admitted", "completed", "refused", "max_in_flight",
+        "device_bytes", "budget")]
 
 
 class _Mesh(ctypes.Structure):
@@ -128,6 +150,14 @@ def load_library():
     lib.fvr_last_stats.argtypes = [P, ctypes.POINTER(_Stats)]
     lib.fvr_depth_to_points.argtypes = [P, ctypes.POINTER(_DepthViews), P, P, P, i64,
                                         ctypes.POINTER(i64)]
+    lib.fvr_server_create.argtypes = [I, I, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.fvr_server_destroy.argtypes = [P]
+    lib.fvr_server_destroy.restype = None
+    lib.fvr_server_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.fvr_server_poll.argtypes = [P, ctypes.POINTER(_Result), I, ctypes.POINTER(I)]
+    lib.fvr_server_info.argtypes = [P, ctypes.POINTER(_ServerStats)]
+    lib.fvr_server_last_error.argtypes = [P]
+    lib.fvr_server_last_error.restype = ctypes.c_char_p
     lib.fvr_batch_create.argtypes = [I, P, I, ctypes.POINTER(P)]
     lib.fvr_batch_destroy.argtypes = [P]
     lib.fvr_batch_destroy.restype = None
@@ -151,7 +181,8 @@ def load_library():
     for fn in ("fvr_create", "fvr_set_stream", "fvr_reconstruct", "fvr_reconstruct_noalloc",
                "fvr_indicator", "fvr_extract",
                "fvr_debug_splat", "fvr_check_grid", "fvr_check_frame", "fvr_last_stats", "fvr_mc_table",
-               "fvr_timing_enable", "fvr_depth_to_points", "fvr_batch_create", "fvr_batch_set_stream", "fvr_batch_use_graph",
+               "fvr_timing_enable", "fvr_depth_to_points", "fvr_server_create", "fvr_server_submit",
+               "fvr_server_poll", "fvr_server_info", "fvr_batch_create", "fvr_batch_set_stream", "fvr_batch_use_graph",
                "fvr_batch_reconstruct",
                "fvr_timing_select", "fvr_timing_reset", "fvr_timing_get"):
         getattr(lib, fn).restype = I
@@ -619,3 +650,119 @@ class PreparedBatch:
 
     def meshes(self):
         return [_result(self._meshes[i], self._keep[i][1]) for i in range(self._n)]
+
+
+class Server:
+    """An fvr_server: continuous batching over ``slots`` device slots within
+    a device-memory budget (``fvr_server_*``).  ``submit`` takes host arrays
+    (numpy float32, or pinned torch CPU tensors), ``poll`` returns finished
+    results with their meshes as numpy arrays."""
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 16 << 30, device: int | None = None):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        st = self.lib.fvr_server_create(self.device, int(slots), int(hbm_budget), ctypes.byref(h))
+        if st:
+            raise FvrError(st, (self.lib.fvr_server_last_error(None) or b"").decode())
+        self.handle = h
+        self._live = {}  # ticket -> (request, inputs and outputs kept alive)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fvr_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _host(a, name, ncols):
+        import numpy as np
+        try:
+            import torch
+            if isinstance(a, torch.Tensor):
+                if a.device.type != "cpu" or a.dtype != torch.float32 or not a.is_contiguous():
+                    raise TypeError(f"{name}: a contiguous float32 CPU tensor")
+                return a, a.data_ptr(), bool(a.is_pinned())
+        except ImportError:
+            pass
+        arr = np.ascontiguousarray(a, dtype=np.float32)
+        if ncols > 1 and (arr.ndim != 2 or arr.shape[1] != ncols):
+            raise ValueError(f"{name} has shape {arr.shape}")
+        return arr, arr.ctypes.data, False
+
+    def submit(self, points, normals, weights=None, grid_dim=(128, 128, 128), bbox=((-1, -1, -1), (1, 1, 1)),
+               splat="gaussian", vertex_capacity=None, triangle_capacity=None, vertex_normals=False,
+               user=None) -> int:
+        import numpy as np
+        p, pp, pin_p = self._host(points, "points", 3)
+        n, pn, pin_n = self._host(normals, "normals", 3)
+        keep = [p, n]
+        pw, pin_w = None, True
+        if weights is not None:
+            w, pw, pin_w = self._host(weights, "weights", 1)
+            keep.append(w)
+        gd = (grid_dim,) * 3 if isinstance(grid_dim, int) else tuple(grid_dim)
+        nx, ny, nz = (int(x) for x in gd)
+        vcap = vertex_capacity or max(4096, 6 * (nx * ny + ny * nz + nx * nz))
+        tcap = triangle_capacity or 2 * vcap
+        verts = np.empty((vcap, 3), np.float32)
+        tris = np.empty((tcap, 3), np.int32)
+        nrm = np.empty((vcap, 3), np.float32) if vertex_normals else None
+        q = _Request()
+        q.points, q.normals, q.weights = pp, pn, pw
+        q.n_points = int(p.shape[0])
+        q.dims[:] = [nx, ny, nz]
+        q.bbox[:] = [float(x) for x in _flat_bbox(bbox)]
+        q.options = SPLATS[splat]
+        q.flags = 1 if (pin_p and pin_n and pin_w) else 0
+        q.vertices, q.triangles = verts.ctypes.data, tris.ctypes.data
+        q.normals_out = nrm.ctypes.data if nrm is not None else None
+        q.vertex_capacity, q.triangle_capacity = vcap, tcap
+        t = ctypes.c_uint64()
+        st = self.lib.fvr_server_submit(self.handle, ctypes.byref(q), ctypes.byref(t))
+        if st:
+            raise FvrError(st, (self.lib.fvr_server_last_error(self.handle) or b"").decode())
+        self._live[t.value] = (q, keep, verts, tris, nrm, user)
+        return t.value
+
+    def poll(self, max_results: int = 64) -> list:
+        out = (_Result * max_results)()
+        n = ctypes.c_int()
+        st = self.lib.fvr_server_poll(self.handle, out, max_results, ctypes.byref(n))
+        if st:
+            raise FvrError(st, (self.lib.fvr_server_last_error(self.handle) or b"").decode())
+        res = []
+        for r in out[:n.value]:
+            q, keep, verts, tris, nrm, user = self._live.pop(r.ticket)
+            ok = r.status == 0
+            res.append({"ticket": r.ticket, "status": r.status, "error": r.error.decode(),
+                        "vertices": verts[:r.n_vertices] if ok else None,
+                        "triangles": tris[:r.n_triangles] if ok else None,
+                        "normals": nrm[:r.n_vertices] if (ok and nrm is not None) else None,
+                        "n_vertices": r.n_vertices, "n_triangles": r.n_triangles, "level": r.level,
+                        "open_surface": bool(r.flags & FVR_FLAG_OPEN_SURFACE), "n_rejected": r.n_rejected,
+                        "latency_ms": r.done_ms - r.submit_ms, "queue_ms": r.admit_ms - r.submit_ms,
+                        "submit_ms": r.submit_ms, "done_ms": r.done_ms, "user": user})
+        return res
+
+    def info(self) -> dict:
+        st = _ServerStats()
+        self.lib.fvr_server_info(self.handle, ctypes.byref(st))
+        return {n: int(getattr(st, n)) for n, _ in _ServerStats._fields_}
+
+    def drain(self, timeout_s: float = 60.0) -> list:
+        """Poll until every submitted request has a result."""
+        import time
+        out = []
+        t0 = time.perf_counter()
+        while self._live:
+            out += self.poll()
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"{len(self._live)} requests unfinished")
+        return out

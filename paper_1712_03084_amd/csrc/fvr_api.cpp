@@ -11,6 +11,8 @@
 //   (mesh counts, flags, level) at the end.
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <deque>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -96,6 +98,7 @@ struct fvr_ctx {
     // allocation-free calls carve their buffers from the static scratch
     unsigned char *arena = nullptr;  // non-null during such a call
     size_t arena_off = 0;
+    size_t arena_cap = FVR_NOALLOC_SCRATCH_BYTES;
     uint64_t arena_epoch = 0;
     uint64_t scratch_gen = 0;  // bumped whenever an owned buffer moves
     DevBuf bin_count, bin_off, key, rank, rec, spec, field, vidx, cells, mc_cnt, mc_off, mc_codes,
@@ -158,7 +161,7 @@ hipError_t get(fvr_ctx *c, DevBuf &b, size_t bytes) {
     }
     if (b.epoch == c->arena_epoch && b.bytes >= bytes) return hipSuccess;
     const size_t off = (c->arena_off + 255) & ~(size_t)255;
-    if (off > FVR_NOALLOC_SCRATCH_BYTES || bytes > FVR_NOALLOC_SCRATCH_BYTES - off) return hipErrorOutOfMemory;
+    if (off > c->arena_cap || bytes > c->arena_cap - off) return hipErrorOutOfMemory;
     b.view = c->arena + off;
     b.epoch = c->arena_epoch;
     b.bytes = bytes;
@@ -616,6 +619,20 @@ fvr_status enqueue_reconstruct(fvr_ctx *c, const fvr_frame *f, Plan *p, const fv
                       fused ? level_nb : 0, host_dst);
 }
 
+// Every device buffer a context owns.
+std::vector<DevBuf *> ctx_bufs(fvr_ctx *c) {
+    return {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
+            &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
+            &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend,
+            &c->blk_max, &c->rowmm, &c->mc_list, &c->fe_rowcnt, &c->fe_dense, &c->fe_flag, &c->fe_off};
+}
+
+size_t ctx_bytes(fvr_ctx *c) {
+    size_t t = 0;
+    for (DevBuf *b : ctx_bufs(c)) t += b->cap;
+    return t;
+}
+
 // Every scratch buffer of one frame, requested before anything is enqueued.
 fvr_status frame_bufs(fvr_ctx *c, const fvr_frame *f, const Plan *p, const fvr_mesh *mesh) {
     const Grid g = make_grid(f->dims, f->bbox);
@@ -672,11 +689,7 @@ void fvr_destroy(fvr_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf *bufs[] = {&c->bin_count, &c->bin_off, &c->key, &c->rank, &c->rec, &c->spec, &c->field,
-                      &c->vidx, &c->cells, &c->mc_cnt, &c->mc_off, &c->mc_codes, &c->lvl_sum, &c->lvl_cnt,
-                      &c->status, &c->level_f32, &c->scan_part, &c->occ, &c->zocc, &c->tiles, &c->tile_pend, &c->blk_max, &c->rowmm, &c->mc_list,
-                      &c->fe_rowcnt, &c->fe_dense, &c->fe_flag, &c->fe_off};
-    for (DevBuf *b : bufs)
+    for (DevBuf *b : ctx_bufs(c))
         if (b->p) (void)hipFree(b->p);
     for (auto &pr : c->ev) {
         (void)hipEventDestroy(pr.first);
@@ -1068,6 +1081,428 @@ fvr_status fvr_batch_reconstruct(fvr_batch *b, const fvr_frame *frames, fvr_mesh
 }
 
 const char *fvr_batch_last_error(const fvr_batch *b) { return b ? b->err.c_str() : g_error.c_str(); }
+
+}  // extern "C"
+
+// A serving loop with continuous batching.  Requests (host arrays in, host
+// mesh out) queue in arrival order; a request is admitted when a slot is
+// free and the device memory the slots would then hold stays within the
+// budget.  An admitted request's upload runs on a shared copy stream, its
+// stages on the slot's stream (so uploads overlap other slots' compute, and
+// frames of different slots overlap each other), and its mesh comes back in
+// exactly its size once the counts are known.  Completions are harvested by
+// fvr_server_poll, which also admits the waiting requests as slots and
+// memory free up.
+struct fvr_server {
+    int device = 0;
+    size_t budget = 0;
+    hipStream_t copy = nullptr;
+    fvr_ctx *measure = nullptr;  // sizes a frame's scratch (arena arithmetic only)
+    struct Slot {
+        fvr_ctx *c = nullptr;
+        int state = 0;  // 0 free, 1 computing, 2 copying the mesh back
+        fvr_request req{};
+        uint64_t ticket = 0;
+        double t_submit = 0.0, t_admit = 0.0;
+        DevBuf d_in, d_verts, d_tris, d_nrm;
+        float *h_in = nullptr;
+        size_t h_in_cap = 0;
+        unsigned char *h_out = nullptr;  // pinned mesh staging
+        size_t h_out_cap = 0;
+        hipEvent_t h2d = nullptr, done = nullptr;
+        fvr_mesh mesh{};
+        DevStatus st{};
+        fvr_status status = FVR_OK;
+    };
+    std::vector<Slot> slots;
+    struct Pending {
+        fvr_request req;
+        uint64_t ticket;
+        double t_submit;
+        size_t scratch;  // the frame's scratch bytes
+    };
+    std::deque<Pending> pending;
+    std::deque<fvr_result> results;
+    uint64_t next_ticket = 1;
+    int64_t admitted = 0, completed = 0, rejected = 0, max_in_flight = 0;
+    std::string err;
+};
+
+namespace {
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+fvr_status sfail(fvr_server *v, fvr_status st, const std::string &msg) {
+    if (v) v->err = msg;
+    g_error = msg;
+    return st;
+}
+
+// Bytes a request needs on the device: its scratch plus inputs and mesh.
+size_t io_bytes(const fvr_request &r) {
+    const size_t m = (size_t)std::max<int64_t>(r.n_points, 0);
+    const size_t v = (size_t)std::max<int64_t>(r.vertex_capacity, 1);
+    return align256(28 * m) + align256(12 * v) + align256(12 * (size_t)std::max<int64_t>(r.triangle_capacity, 1)) +
+           (r.normals_out ? align256(12 * v) : 0);
+}
+
+size_t slot_bytes(fvr_server::Slot &s) {
+    return ctx_bytes(s.c) + s.d_in.cap + s.d_verts.cap + s.d_tris.cap + s.d_nrm.cap;
+}
+
+// Device bytes slot k would hold after taking a frame of `scratch` + `io`
+// bytes (its buffers only grow).
+size_t slot_bytes_after(fvr_server::Slot &s, size_t scratch, size_t io) {
+    return std::max(ctx_bytes(s.c), scratch) + std::max(s.d_in.cap + s.d_verts.cap + s.d_tris.cap + s.d_nrm.cap, io);
+}
+
+// The scratch bytes of a frame: the allocation-free carving arithmetic over
+// a dummy base (no memory is touched).
+fvr_status frame_scratch_bytes(fvr_server *v, const fvr_frame *f, const fvr_mesh *mesh, size_t *out) {
+    fvr_ctx *c = v->measure;
+    Plan plan;
+    fvr_status r = build_plan(c, f->dims, plan);
+    if (r != FVR_OK) return r;
+    plan_geometry(&plan, f);
+    c->arena = reinterpret_cast<unsigned char *>((uintptr_t)4096);
+    c->arena_cap = (size_t)1 << 50;
+    c->arena_off = 0;
+    ++c->arena_epoch;
+    r = frame_bufs(c, f, &plan, mesh);
+    c->arena = nullptr;
+    c->arena_cap = FVR_NOALLOC_SCRATCH_BYTES;
+    *out = c->arena_off;
+    return r;
+}
+
+fvr_frame device_frame(const fvr_request &q, const float *d_in) {
+    fvr_frame f{};
+    const size_t m = (size_t)q.n_points;
+    f.points = d_in;
+    f.normals = d_in + 3 * m;
+    f.weights = q.weights ? d_in + 6 * m : nullptr;
+    f.n_points = q.n_points;
+    std::memcpy(f.dims, q.dims, sizeof(f.dims));
+    std::memcpy(f.bbox, q.bbox, sizeof(f.bbox));
+    f.options = q.options;
+    return f;
+}
+
+void push_result(fvr_server *v, const fvr_server::Slot &s, fvr_status st, const std::string &msg) {
+    fvr_result r{};
+    r.ticket = s.ticket;
+    r.status = st;
+    r.n_vertices = s.mesh.n_vertices;
+    r.n_triangles = s.mesh.n_triangles;
+    r.level = s.mesh.level;
+    r.n_rejected = s.mesh.n_rejected;
+    r.flags = s.mesh.flags;
+    r.user = s.req.user;
+    r.submit_ms = s.t_submit;
+    r.admit_ms = s.t_admit;
+    r.done_ms = now_ms();
+    std::snprintf(r.error, sizeof(r.error), "%s", msg.c_str());
+    v->results.push_back(r);
+}
+
+// Upload, enqueue and start one request on slot k.
+fvr_status launch_on(fvr_server *v, int k, const fvr_server::Pending &pd) {
+    fvr_server::Slot &s = v->slots[k];
+    fvr_ctx *c = s.c;
+    const fvr_request &q = pd.req;
+    const size_t m = (size_t)q.n_points;
+    const size_t in_floats = (q.weights ? 7 : 6) * m;
+    HIP_TRY(c, ensure(s.d_in, sizeof(float) * std::max<size_t>(in_floats, 1)), "server inputs");
+    HIP_TRY(c, ensure(s.d_verts, 12 * (size_t)std::max<int64_t>(q.vertex_capacity, 1)), "server vertices");
+    HIP_TRY(c, ensure(s.d_tris, 12 * (size_t)std::max<int64_t>(q.triangle_capacity, 1)), "server triangles");
+    if (q.normals_out) HIP_TRY(c, ensure(s.d_nrm, 12 * (size_t)std::max<int64_t>(q.vertex_capacity, 1)), "server normals");
+    float *din = static_cast<float *>(s.d_in.p);
+    // inputs: straight from the caller's memory when it is pinned, else
+    // through the slot's pinned staging
+    const float *src[3] = {q.points, q.normals, q.weights};
+    const size_t len[3] = {3 * m, 3 * m, q.weights ? m : 0};
+    if (!(q.flags & FVR_REQUEST_PINNED) && in_floats > 0) {
+        if (s.h_in_cap < in_floats) {
+            if (s.h_in) (void)hipHostFree(s.h_in);
+            s.h_in = nullptr;
+            s.h_in_cap = 0;
+            HIP_TRY(c, hipHostMalloc((void **)&s.h_in, sizeof(float) * in_floats), "server staging");
+            s.h_in_cap = in_floats;
+        }
+        size_t o = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (len[a]) std::memcpy(s.h_in + o, src[a], sizeof(float) * len[a]);
+            src[a] = s.h_in + o;
+            o += len[a];
+        }
+    }
+    size_t o = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (len[a])
+            HIP_TRY(c, hipMemcpyAsync(din + o, src[a], sizeof(float) * len[a], hipMemcpyHostToDevice, v->copy),
+                    "server upload");
+        o += len[a];
+    }
+    HIP_TRY(c, hipEventRecord(s.h2d, v->copy), "server upload event");
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, s.h2d, 0), "server upload wait");
+    fvr_frame f = device_frame(q, din);
+    s.mesh = fvr_mesh{};
+    s.mesh.vertices = static_cast<float *>(s.d_verts.p);
+    s.mesh.triangles = static_cast<int32_t *>(s.d_tris.p);
+    s.mesh.normals = q.normals_out ? static_cast<float *>(s.d_nrm.p) : nullptr;
+    s.mesh.vertex_capacity = q.vertex_capacity;
+    s.mesh.triangle_capacity = q.triangle_capacity;
+    Plan *p = nullptr;
+    fvr_status r = get_plan(c, &f, &p);
+    if (r == FVR_OK) r = enqueue_reconstruct(c, &f, p, &s.mesh, c->host_status);
+    if (r != FVR_OK) return r;
+    HIP_TRY(c, hipEventRecord(s.done, c->stream), "server event");
+    s.req = q;
+    s.ticket = pd.ticket;
+    s.t_submit = pd.t_submit;
+    s.t_admit = now_ms();
+    s.state = 1;
+    ++v->admitted;
+    return FVR_OK;
+}
+
+// Admit waiting requests in arrival order while a slot is free and the
+// slots' device memory stays within the budget; a request that cannot fit
+// even with every other slot idle is refused.
+void admit(fvr_server *v) {
+    while (!v->pending.empty()) {
+        const fvr_server::Pending &pd = v->pending.front();
+        const size_t io = io_bytes(pd.req);
+        size_t held = 0;
+        int busy = 0;
+        for (auto &sl : v->slots) {
+            held += slot_bytes(sl);
+            busy += sl.state != 0;
+        }
+        // the free slot that grows least (one already large enough if any)
+        int best = -1;
+        size_t best_total = 0;
+        for (int k = 0; k < (int)v->slots.size(); ++k) {
+            fvr_server::Slot &sl = v->slots[k];
+            if (sl.state != 0) continue;
+            const size_t total = held - slot_bytes(sl) + slot_bytes_after(sl, pd.scratch, io);
+            if (best < 0 || total < best_total) {
+                best = k;
+                best_total = total;
+            }
+        }
+        if (best < 0) return;  // every slot busy
+        if (best_total > v->budget) {
+            if (busy) return;  // memory frees up as slots finish
+            fvr_server::Slot tmp;
+            tmp.ticket = pd.ticket;
+            tmp.req = pd.req;
+            tmp.t_submit = pd.t_submit;
+            tmp.t_admit = now_ms();
+            push_result(v, tmp, FVR_E_NOMEM, "frame does not fit the server's device-memory budget");
+            ++v->rejected;
+            v->pending.pop_front();
+            continue;
+        }
+        fvr_status r = launch_on(v, best, pd);
+        if (r != FVR_OK) {
+            fvr_server::Slot &sl = v->slots[best];
+            sl.ticket = pd.ticket;
+            sl.req = pd.req;
+            sl.t_submit = pd.t_submit;
+            push_result(v, sl, r, sl.c->err);
+            (void)hipStreamSynchronize(sl.c->stream);
+            sl.state = 0;
+            ++v->rejected;
+        }
+        v->pending.pop_front();
+        int in_flight = 0;
+        for (auto &sl : v->slots) in_flight += sl.state != 0;
+        v->max_in_flight = std::max<int64_t>(v->max_in_flight, in_flight);
+    }
+}
+
+// Advance the slots whose device work finished: counts known -> copy the
+// mesh back in its exact size; copy done -> result, slot free.
+void harvest(fvr_server *v) {
+    for (auto &s : v->slots) {
+        if (s.state == 0) continue;
+        if (hipEventQuery(s.done) != hipSuccess) continue;
+        fvr_ctx *c = s.c;
+        if (s.state == 1) {
+            s.st = *c->host_status;
+            s.status = finish_mesh(c, s.st, &s.mesh, true);
+            s.mesh.level = s.st.level;
+            if (s.status != FVR_OK) {
+                push_result(v, s, s.status, c->err);
+                s.state = 0;
+                ++v->completed;
+                continue;
+            }
+            const size_t nv = (size_t)s.mesh.n_vertices, nt = (size_t)s.mesh.n_triangles;
+            const size_t need = 12 * nv + 12 * nt + (s.req.normals_out ? 12 * nv : 0);
+            if (s.h_out_cap < need) {
+                if (s.h_out) (void)hipHostFree(s.h_out);
+                s.h_out = nullptr;
+                s.h_out_cap = 0;
+                if (hipHostMalloc((void **)&s.h_out, std::max<size_t>(need, 256)) != hipSuccess) {
+                    push_result(v, s, FVR_E_NOMEM, "pinned mesh staging");
+                    s.state = 0;
+                    ++v->completed;
+                    continue;
+                }
+                s.h_out_cap = std::max<size_t>(need, 256);
+            }
+            hipError_t e = hipSuccess;
+            if (nv) e = hipMemcpyAsync(s.h_out, s.d_verts.p, 12 * nv, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess && nt)
+                e = hipMemcpyAsync(s.h_out + 12 * nv, s.d_tris.p, 12 * nt, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess && nv && s.req.normals_out)
+                e = hipMemcpyAsync(s.h_out + 12 * (nv + nt), s.d_nrm.p, 12 * nv, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(s.done, c->stream);
+            if (e != hipSuccess) {
+                push_result(v, s, FVR_E_DEVICE, hipGetErrorString(e));
+                s.state = 0;
+                ++v->completed;
+                continue;
+            }
+            s.state = 2;
+            continue;
+        }
+        // state 2: the mesh is in pinned memory
+        const size_t nv = (size_t)s.mesh.n_vertices, nt = (size_t)s.mesh.n_triangles;
+        if (nv) std::memcpy(s.req.vertices, s.h_out, 12 * nv);
+        if (nt) std::memcpy(s.req.triangles, s.h_out + 12 * nv, 12 * nt);
+        if (nv && s.req.normals_out) std::memcpy(s.req.normals_out, s.h_out + 12 * (nv + nt), 12 * nv);
+        push_result(v, s, FVR_OK, "");
+        s.state = 0;
+        ++v->completed;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+fvr_status fvr_server_create(int device, int slots, size_t hbm_budget, fvr_server **out) {
+    if (!out) return sfail(nullptr, FVR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (slots < 1 || slots > 64) return sfail(nullptr, FVR_E_INVALID, "slots must be in 1..64");
+    fvr_server *v = new fvr_server();
+    v->device = device;
+    v->budget = hbm_budget;
+    fvr_status r = fvr_create(device, nullptr, &v->measure);
+    hipError_t e = r == FVR_OK ? hipStreamCreateWithFlags(&v->copy, hipStreamNonBlocking) : hipSuccess;
+    for (int k = 0; k < slots && r == FVR_OK && e == hipSuccess; ++k) {
+        fvr_server::Slot sl;
+        r = fvr_create(device, nullptr, &sl.c);
+        hipStream_t st = nullptr;
+        if (r == FVR_OK) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (r == FVR_OK && e == hipSuccess) e = hipEventCreateWithFlags(&sl.h2d, hipEventDisableTiming);
+        if (r == FVR_OK && e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (sl.c) sl.c->stream = st;
+        v->slots.push_back(sl);
+    }
+    if (r != FVR_OK || e != hipSuccess) {
+        fvr_server_destroy(v);
+        return r != FVR_OK ? r : sfail(nullptr, FVR_E_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
+    }
+    *out = v;
+    return FVR_OK;
+}
+
+void fvr_server_destroy(fvr_server *v) {
+    if (!v) return;
+    (void)hipSetDevice(v->device);
+    for (auto &s : v->slots) {
+        if (!s.c) continue;
+        hipStream_t st = s.c->stream;
+        if (st) (void)hipStreamSynchronize(st);
+        for (DevBuf *b : {&s.d_in, &s.d_verts, &s.d_tris, &s.d_nrm})
+            if (b->p) (void)hipFree(b->p);
+        if (s.h_in) (void)hipHostFree(s.h_in);
+        if (s.h_out) (void)hipHostFree(s.h_out);
+        if (s.h2d) (void)hipEventDestroy(s.h2d);
+        if (s.done) (void)hipEventDestroy(s.done);
+        fvr_destroy(s.c);
+        if (st) (void)hipStreamDestroy(st);
+    }
+    if (v->copy) {
+        (void)hipStreamSynchronize(v->copy);
+        (void)hipStreamDestroy(v->copy);
+    }
+    if (v->measure) fvr_destroy(v->measure);
+    delete v;
+}
+
+fvr_status fvr_server_submit(fvr_server *v, const fvr_request *q, uint64_t *ticket) {
+    if (!v || !q) return sfail(v, FVR_E_INVALID, "server or request is NULL");
+    fvr_frame f{};
+    f.points = q->points;
+    f.normals = q->normals;
+    f.weights = q->weights;
+    f.n_points = q->n_points;
+    std::memcpy(f.dims, q->dims, sizeof(f.dims));
+    std::memcpy(f.bbox, q->bbox, sizeof(f.bbox));
+    f.options = q->options;
+    fvr_status r = check_frame_fields(v->measure, &f);
+    if (r != FVR_OK) return sfail(v, r, v->measure->err);
+    if (q->vertex_capacity < 0 || q->triangle_capacity < 0 || !q->vertices || !q->triangles)
+        return sfail(v, FVR_E_INVALID, "mesh outputs are NULL or capacities negative");
+    if (q->flags & ~FVR_REQUEST_PINNED) return sfail(v, FVR_E_INVALID, "unknown request flag bits");
+    HIP_TRY(v->measure, hipSetDevice(v->device), "hipSetDevice");
+    fvr_mesh mm{};
+    mm.vertices = q->vertices;
+    mm.triangles = q->triangles;
+    mm.vertex_capacity = q->vertex_capacity;
+    mm.triangle_capacity = q->triangle_capacity;
+    fvr_server::Pending pd{*q, v->next_ticket++, now_ms(), 0};
+    if ((r = frame_scratch_bytes(v, &f, &mm, &pd.scratch)) != FVR_OK) return sfail(v, r, v->measure->err);
+    if (ticket) *ticket = pd.ticket;
+    v->pending.push_back(pd);
+    admit(v);
+    return FVR_OK;
+}
+
+fvr_status fvr_server_poll(fvr_server *v, fvr_result *out, int max_results, int *n_out) {
+    if (!v || !n_out || (max_results > 0 && !out)) return sfail(v, FVR_E_INVALID, "bad poll arguments");
+    *n_out = 0;
+    hipError_t e = hipSetDevice(v->device);
+    if (e != hipSuccess) return sfail(v, FVR_E_DEVICE, hipGetErrorString(e));
+    harvest(v);
+    admit(v);
+    harvest(v);  // a copy-back may already have finished
+    int n = 0;
+    while (n < max_results && !v->results.empty()) {
+        out[n++] = v->results.front();
+        v->results.pop_front();
+    }
+    *n_out = n;
+    return FVR_OK;
+}
+
+fvr_status fvr_server_info(const fvr_server *v, fvr_server_stats *out) {
+    if (!v || !out) return sfail(nullptr, FVR_E_INVALID, "server or out is NULL");
+    fvr_server_stats st{};
+    st.pending = (int64_t)v->pending.size();
+    for (const auto &s : v->slots) st.in_flight += s.state != 0;
+    st.results_waiting = (int64_t)v->results.size();
+    st.admitted = v->admitted;
+    st.completed = v->completed;
+    st.refused = v->rejected;
+    st.max_in_flight = v->max_in_flight;
+    fvr_server *w = const_cast<fvr_server *>(v);
+    for (auto &s : w->slots) st.device_bytes += slot_bytes(s);
+    st.budget = v->budget;
+    *out = st;
+    return FVR_OK;
+}
+
+const char *fvr_server_last_error(const fvr_server *v) { return v ? v->err.c_str() : g_error.c_str(); }
 
 fvr_status fvr_depth_to_points(fvr_ctx *c, const fvr_depth_views *dv, float *points, float *normals,
                                float *weights, int64_t capacity, int64_t *n_points) {

@@ -326,6 +326,9 @@ def main():
     ap.add_argument("--secondary", default="proxy128",
                     help="comma-separated workloads measured after the headline one and reported "
                          "under 'secondary' (empty: none)")
+    ap.add_argument("--storages", default="bf16,fp16",
+                    help="16-bit spectrum storages measured on the headline workload after it and "
+                         "reported under 'storage' (empty: none)")
     ap.add_argument("--batch", type=int, default=16,
                     help="frames of the batched workload (16 uneven frames on {96..192}^3 grids) "
                          "measured after the headline one, batched and plain (0: skip)")
@@ -540,6 +543,49 @@ def main():
         del sprep
     if sec:
         result["secondary"] = sec
+
+    # 16-bit spectrum storage on the headline workload: throughput of the same
+    # prepared calls, the per-kernel times, and the indicator's deviation from
+    # the float32-storage result on the first pool frame (the error against
+    # the FP64 oracle is what the precision tests bound)
+    storages = [x for x in args.storages.split(",") if x]
+    if storages:
+        stor = {}
+        A32, _ = ctx.indicator(*pool[0], grid_dim=dims, bbox=bbox)
+        arange = float(A32.max() - A32.min())
+        all_kernels = [ctx.lib.fvr_timing_name(i).decode() for i in range(ctx.lib.fvr_timing_count())]
+        for sname in storages:
+            print(f"[bench] storage {sname}", file=sys.stderr, flush=True)
+            sp = [ctx.prepare(*fr, grid_dim=dims, bbox=bbox, out=out, storage=sname) for fr in pool[:16]]
+            for k in range(args.warmup):
+                sp[k % len(sp)].run()
+            skern = {}
+            if not args.no_kernel_timing:
+                ctx.timing_select(all_kernels)
+                ctx.timing(True)
+                ctx.timing_reset()
+                for k in range(args.breakdown):
+                    sp[k % len(sp)].run()
+                torch.cuda.synchronize()
+                ctx.timing(False)
+                skern = {n: round(ms / cnt * 1e3, 2) for n, (ms, cnt) in ctx.timings().items() if cnt}
+            torch.cuda.synchronize()
+            q0 = time.perf_counter()
+            for k in range(args.steps):
+                sp[k % len(sp)].run()
+            torch.cuda.synchronize()
+            sfps = args.steps / (time.perf_counter() - q0)
+            A16, _ = ctx.indicator(*pool[0], grid_dim=dims, bbox=bbox, storage=sname)
+            dev_max = float((A16 - A32).abs().max()) / arange
+            dev_rms = float(((A16 - A32) ** 2).mean().sqrt()) / arange
+            stor[sname] = {"value": round(sfps, 2), "unit": "frames/s", "ms_per_step": round(1e3 / sfps, 4),
+                           "kernels_avg_us": skern,
+                           "indicator_dev_vs_f32_storage": {"max": float(f"{dev_max:.3g}"),
+                                                            "rms": float(f"{dev_rms:.3g}"),
+                                                            "of": "the indicator's range"}}
+            del sp, A16
+        del A32
+        result["storage"] = stor
 
     if args.batch > 0:
         result["batched"] = bench_batch(args, fvr, synth, torch, np, dev)

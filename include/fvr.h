@@ -61,7 +61,9 @@ typedef enum {
     FVR_E_UNSUPPORTED = -2, /* a grid dim not of the form 2^a 3^b 5^c, or > 512 */
     FVR_E_NOMEM = -3,       /* device allocation failed */
     FVR_E_CAPACITY = -4,    /* output arrays too small; required counts written */
-    FVR_E_DEVICE = -5       /* a HIP runtime error */
+    FVR_E_DEVICE = -5,      /* a HIP runtime error */
+    FVR_E_RANGE = -6        /* a 16-bit spectrum value overflowed (FVR_STORAGE_FP16
+                               with normals far from unit length): use float32 storage */
 } fvr_status;
 
 /* Largest point count of one frame: (2^31 - 1) / 3, so that every
@@ -92,6 +94,23 @@ typedef struct {
  * and V is the mean of the normals that land in a voxel (0 where none do);
  * weights are ignored (still validated). */
 #define FVR_SPLAT_NEAREST 1u
+/* fvr_frame.options: reduced-precision storage of the spectra between the
+ * transform passes - two bfloat16 (FVR_STORAGE_BF16) or two IEEE half
+ * (FVR_STORAGE_FP16) values per complex bin instead of complex64, half the
+ * bytes - with every pass computing in float32.  Each forward pass stores
+ * its output times 1/N_axis (the inverse's 1/n split over the passes), and
+ * the angular frequencies of the derivative and the solve are taken in
+ * units of 1/h_x (h_x the voxel size along x; A is scaled back at the end),
+ * so the stored magnitudes do not depend on the bbox's length unit: for
+ * unit normals they stay some 2^16 below FP16's largest value.  A value
+ * that overflows anyway makes the call fail with FVR_E_RANGE.  V never
+ * leaves the chip and A stays float32.  Dims must be in
+ * {16, 32, 64, 128, 256} (FVR_E_UNSUPPORTED otherwise).  The indicator then
+ * carries the rounding of 8-bit (bf16) or 11-bit (fp16) significands: its
+ * error against an FP64 evaluation is reported with the benchmarks, and lies
+ * outside the float32 tolerance. */
+#define FVR_STORAGE_BF16 2u
+#define FVR_STORAGE_FP16 4u
 
 typedef struct {
     float *vertices;            /* out: capacity x 3 */

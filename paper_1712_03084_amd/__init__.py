@@ -31,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfvr.so")
 
 STATUS = {0: "FVR_OK", -1: "FVR_E_INVALID", -2: "FVR_E_UNSUPPORTED", -3: "FVR_E_NOMEM",
-          -4: "FVR_E_CAPACITY", -5: "FVR_E_DEVICE"}
+          -4: "FVR_E_CAPACITY", -5: "FVR_E_DEVICE", -6: "FVR_E_RANGE"}
 FVR_FLAG_OPEN_SURFACE = 1
 
 
@@ -98,6 +98,8 @@ FVR_SPLAT_NEAREST = 1
 # splat variants of Sec. III-B: the weighted Gaussian splat of eqs. (1)-(2),
 # and the non-weighted one (each normal to its nearest voxel, mean per voxel)
 SPLATS = {"gaussian": 0, "nearest": FVR_SPLAT_NEAREST}
+# spectrum storage between the transform passes (computation is float32)
+STORAGES = {"f32": 0, "bf16": 2, "fp16": 4}
 
 Mesh = namedtuple("Mesh", "vertices triangles level n_rejected open_surface normals", defaults=(None,))
 
@@ -204,16 +206,18 @@ def check_grid(dims, bbox) -> int:
     return int(lib.fvr_check_grid(d, b))
 
 
-def check_frame(n_points, grid_dim, bbox, points_ptr=1, normals_ptr=1, weights_ptr=0) -> int:
+def check_frame(n_points, grid_dim, bbox, points_ptr=1, normals_ptr=1, weights_ptr=0, options=0) -> int:
     """Host-only validation of a frame's host-side fields (point count,
-    required pointers, grid, bbox) as ``fvr_reconstruct`` does before any
-    launch; the pointers are not dereferenced.  Returns the fvr_status code."""
+    required pointers, grid, bbox, option bits) as ``fvr_reconstruct`` does
+    before any launch; the pointers are not dereferenced.  Returns the
+    fvr_status code."""
     lib = load_library()
     f = _Frame()
     f.points, f.normals, f.weights = points_ptr or None, normals_ptr or None, weights_ptr or None
     f.n_points = int(n_points)
     f.dims = (ctypes.c_int32 * 3)(*[int(x) for x in grid_dim])
     f.bbox = (ctypes.c_float * 6)(*[float(x) for x in bbox])
+    f.options = int(options)
     return int(lib.fvr_check_frame(ctypes.byref(f)))
 
 
@@ -314,7 +318,7 @@ class Context:
             _check(self.lib, self.lib.fvr_set_stream(self.handle, ctypes.c_void_p(s)), self.handle)
             self._cur_stream = s
 
-    def _frame(self, points, normals, weights, grid_dim, bbox, splat="gaussian"):
+    def _frame(self, points, normals, weights, grid_dim, bbox, splat="gaussian", storage="f32"):
         points = _dev_f32(points, "points", self.device, 3)
         normals = _dev_f32(normals, "normals", self.device, 3)
         if normals.shape[0] != points.shape[0]:
@@ -334,7 +338,9 @@ class Context:
         f.bbox[:] = [float(x) for x in _flat_bbox(bbox)]
         if splat not in SPLATS:
             raise ValueError(f"splat must be one of {sorted(SPLATS)}")
-        f.options = SPLATS[splat]
+        if storage not in STORAGES:
+            raise ValueError(f"storage must be one of {sorted(STORAGES)}")
+        f.options = SPLATS[splat] | STORAGES[storage]
         return f, (points, normals, weights)
 
     def _run_mesh(self, call, dims, out, vcap, tcap, want_normals=False):
@@ -367,13 +373,15 @@ class Context:
     # -- API ----------------------------------------------------------------
     def reconstruct(self, points, normals, weights=None, grid_dim=(128, 128, 128),
                     bbox=((-1, -1, -1), (1, 1, 1)), out=None, vertex_capacity=None,
-                    triangle_capacity=None, vertex_normals=False, splat="gaussian") -> Mesh:
+                    triangle_capacity=None, vertex_normals=False, splat="gaussian",
+                    storage="f32") -> Mesh:
         """Sec. III-B end to end: returns Mesh(vertices [V,3] f32, triangles
         [T,3] i32, level, n_rejected, open_surface, normals [V,3] f32 or
         None).  ``out`` = (verts, tris[, normals]) preallocated buffers, used
         without retry; ``vertex_normals`` asks for normals when out is None;
-        ``splat`` is "gaussian" (eqs. (1)-(2)) or "nearest"."""
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
+        ``splat`` is "gaussian" (eqs. (1)-(2)) or "nearest"; ``storage`` the
+        spectra's storage between passes ("f32", "bf16", "fp16")."""
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat, storage)
         self._stream()
         dims = tuple(f.dims)
         return self._run_mesh(lambda m: self.lib.fvr_reconstruct(self.handle, ctypes.byref(f),
@@ -435,14 +443,14 @@ class Context:
 
     def prepare(self, points, normals, weights=None, grid_dim=(128, 128, 128),
                 bbox=((-1, -1, -1), (1, 1, 1)), out=None, vertex_capacity=None,
-                triangle_capacity=None, splat="gaussian") -> "PreparedFrame":
+                triangle_capacity=None, splat="gaussian", storage="f32") -> "PreparedFrame":
         """A frame for repeated reconstruction: the tensors are checked and
         the call's arguments marshalled once.  ``run()`` then enqueues the
         same work as ``reconstruct`` on the stream that was current here,
         reading the tensors' contents at each call (a serving loop refills
         the same input and output buffers between runs).  The output
         buffers are ``out`` or allocated once; a capacity shortfall raises."""
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat, storage)
         self._stream()
         torch = _torch()
         if out is None:
@@ -454,10 +462,10 @@ class Context:
         return PreparedFrame(self, f, keep, out, self._cur_stream)
 
     def indicator(self, points, normals, weights=None, grid_dim=(128, 128, 128),
-                  bbox=((-1, -1, -1), (1, 1, 1)), splat="gaussian"):
+                  bbox=((-1, -1, -1), (1, 1, 1)), splat="gaussian", storage="f32"):
         """Steps up to the iso-level: returns (A [Nz, Ny, Nx] f32 tensor, L)."""
         torch = _torch()
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat, storage)
         self._stream()
         nx, ny, nz = tuple(f.dims)
         A = torch.empty((nz, ny, nx), dtype=torch.float32, device=f"cuda:{self.device}")

@@ -35,6 +35,9 @@ def _flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument",
+            "-Wall", "-Wextra", "-Wno-unused-parameter",
+            "-Werror=infinite-recursion", "-Werror=return-type", "-Werror=uninitialized",
+            "-Werror=unused-variable",
             "-I", INCLUDE, "-I", CSRC]
 
 
@@ -48,6 +51,9 @@ def _compile(src: str) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    warn = [ln for ln in r.stderr.splitlines() if "warning:" in ln and "packed-fp32" not in ln]
+    if warn:
+        print("\n".join(warn), file=sys.stderr)
     return obj
 
 

@@ -116,6 +116,8 @@ struct fvr_ctx {
 
 namespace {
 
+const char *const kRangeMsg = "a 16-bit spectrum value overflowed: use float32 storage";
+
 fvr_status fail(fvr_ctx *c, fvr_status s, const std::string &msg) {
     if (c) c->err = msg;
     g_error = msg;
@@ -263,6 +265,31 @@ Grid make_grid(const int32_t dims[3], const float bbox[6]) {
     g.Hp = (g.H + 15) / 16 * 16;
     g.ty = g.tz = 1;  // splat tiling, filled in from the plan where it matters
     g.tiles_y = dims[1];
+    g.spec_st = kSpecF32;
+    g.fscale[0] = g.fscale[1] = g.fscale[2] = 1.0f;
+    g.iscale = 1.0f / ((float)dims[0] * (float)dims[1] * (float)dims[2]);
+    return g;
+}
+
+// The grid of a frame, with its spectrum storage.  The reduced storages
+// store each forward pass's output times 1/N_axis (powers of two: exact
+// scalings), and take the angular frequencies in units of 1/h_x: the
+// derivative multiplies by h_x w and the solve divides by h_x^2 |w|^2, so
+// the spectrum holds A / h_x and the last inverse pass multiplies by h_x.
+// Without that, the solve's 1/|w|^2 would carry a factor h^2 (the square of
+// the bbox's length unit) into every stored value, and FP16 would keep
+// most of them as subnormals.
+Grid frame_grid(const fvr_frame *f) {
+    Grid g = make_grid(f->dims, f->bbox);
+    if (f->options & (FVR_STORAGE_BF16 | FVR_STORAGE_FP16)) {
+        g.spec_st = (f->options & FVR_STORAGE_BF16) ? kSpecBF16 : kSpecF16;
+        const double hx = ((double)f->bbox[3] - (double)f->bbox[0]) / (double)f->dims[0];
+        for (int a = 0; a < 3; ++a) {
+            g.fscale[a] = 1.0f / (float)f->dims[a];
+            g.wstep[a] = (float)(2.0 * M_PI * hx / ((double)f->bbox[a + 3] - (double)f->bbox[a]));
+        }
+        g.iscale = (float)hx;
+    }
     return g;
 }
 
@@ -381,8 +408,19 @@ fvr_status check_frame_fields(fvr_ctx *c, const fvr_frame *f) {
     if (f->n_points > FVR_MAX_POINTS) return fail(c, FVR_E_INVALID, "n_points above FVR_MAX_POINTS");
     if (f->n_points > 0 && (!f->points || !f->normals))
         return fail(c, FVR_E_INVALID, "points or normals is NULL");
-    if (f->options & ~FVR_SPLAT_NEAREST) return fail(c, FVR_E_INVALID, "unknown frame option bits");
-    return check_grid(c, f->dims, f->bbox);
+    if (f->options & ~(FVR_SPLAT_NEAREST | FVR_STORAGE_BF16 | FVR_STORAGE_FP16))
+        return fail(c, FVR_E_INVALID, "unknown frame option bits");
+    if ((f->options & FVR_STORAGE_BF16) && (f->options & FVR_STORAGE_FP16))
+        return fail(c, FVR_E_INVALID, "FVR_STORAGE_BF16 and FVR_STORAGE_FP16 together");
+    fvr_status r = check_grid(c, f->dims, f->bbox);
+    if (r != FVR_OK) return r;
+    if (f->options & (FVR_STORAGE_BF16 | FVR_STORAGE_FP16))
+        for (int a = 0; a < 3; ++a) {
+            const int n = f->dims[a];
+            if (n != 16 && n != 32 && n != 64 && n != 128 && n != 256)
+                return fail(c, FVR_E_UNSUPPORTED, "16-bit spectrum storage needs dims in {16, 32, 64, 128, 256}");
+        }
+    return FVR_OK;
 }
 
 fvr_status check_frame(fvr_ctx *c, const fvr_frame *f) {
@@ -413,7 +451,7 @@ fvr_status field_bufs(fvr_ctx *c, const Grid &g, const Plan *p, int m) {
     GET(c, c->key, sizeof(int32_t) * (size_t)m, "keys");
     GET(c, c->rank, sizeof(int32_t) * (size_t)m, "ranks");
     GET(c, c->rec, sizeof(float4) * 2 * (size_t)m, "records");
-    GET(c, c->spec, sizeof(float2) * 3 * nspec, "spectra");
+    GET(c, c->spec, spec_elem_bytes(g.spec_st) * 3 * nspec, "spectra");
     GET(c, c->occ, (size_t)ntiles, "tile occupancy");
     GET(c, c->tiles, sizeof(int32_t) * (size_t)ntiles, "tile list");
     GET(c, c->tile_pend, sizeof(int2) * (size_t)ntiles, "tile costs");
@@ -495,19 +533,19 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
               "bin_scatter"); }
     { Timed t(c, K_SPLAT_FFT_X);
       HIP_TRY(c, launch_splat_fft_x(P<float4>(c->rec), P<int32_t>(c->bin_off), g, p->sc, p->ax[0],
-                                    st, P<int32_t>(c->tiles), P<float2>(c->spec), v_out, s), "splat_fft_x"); }
+                                    st, P<int32_t>(c->tiles), P<void>(c->spec), v_out, s), "splat_fft_x"); }
     if (splat_only) return FVR_OK;
-    float2 *sp = P<float2>(c->spec);
+    void *sp = P<void>(c->spec);
     { Timed t(c, K_FFT_Y_FWD);
       HIP_TRY(c, launch_fft_y_fwd(sp, P<uint8_t>(c->occ), P<uint8_t>(c->zocc), st, g, p->ax[1], s), "fft_y_fwd"); }
     { Timed t(c, K_FFT_Z_SOLVE);
       HIP_TRY(c, launch_fft_z_solve(sp, P<uint8_t>(c->zocc), g, p->ax[2], s), "fft_z_solve"); }
     if (fft_yx_fused(g)) {
         Timed t(c, K_FFT_YX_INV);
-        HIP_TRY(c, launch_fft_yx_inv(sp, field, P<float2>(c->rowmm), g, p->ax[1], s), "fft_yx_inv");
+        HIP_TRY(c, launch_fft_yx_inv(sp, field, P<float2>(c->rowmm), st, g, p->ax[1], s), "fft_yx_inv");
     } else {
         { Timed t(c, K_FFT_Y_INV); HIP_TRY(c, launch_fft_y_inv(sp, g, p->ax[1], s), "fft_y_inv"); }
-        { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, g, p->ax[0], s), "fft_x_c2r"); }
+        { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, st, g, p->ax[0], s), "fft_x_c2r"); }
     }
     return FVR_OK;
 }
@@ -579,6 +617,7 @@ fvr_status enqueue_mc(fvr_ctx *c, const Grid &g, const float *field, const float
 fvr_status finish_mesh(fvr_ctx *c, const DevStatus &hs, fvr_mesh *mesh, bool check_invalid) {
     if (check_invalid && (hs.flags & kFlagInvalid))
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
+    if (hs.flags & kFlagRange) return fail(c, FVR_E_RANGE, kRangeMsg);
     mesh->n_vertices = hs.mc_total[0];
     mesh->n_triangles = hs.mc_total[1];
     mesh->n_rejected = hs.rejected;
@@ -605,7 +644,7 @@ fvr_status run_mc(fvr_ctx *c, const Grid &g, const float *field, const float2 *r
 // the final status block goes to host_dst.
 fvr_status enqueue_reconstruct(fvr_ctx *c, const fvr_frame *f, Plan *p, const fvr_mesh *mesh,
                                DevStatus *host_dst) {
-    const Grid g = make_grid(f->dims, f->bbox);
+    const Grid g = frame_grid(f);
     fvr_status r;
     GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
     if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
@@ -635,7 +674,7 @@ size_t ctx_bytes(fvr_ctx *c) {
 
 // Every scratch buffer of one frame, requested before anything is enqueued.
 fvr_status frame_bufs(fvr_ctx *c, const fvr_frame *f, const Plan *p, const fvr_mesh *mesh) {
-    const Grid g = make_grid(f->dims, f->bbox);
+    const Grid g = frame_grid(f);
     const int m = (int)f->n_points;
     GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
     fvr_status r;
@@ -732,7 +771,6 @@ fvr_status fvr_reconstruct_noalloc(fvr_ctx *c, const fvr_frame *f, fvr_mesh *mes
     Plan plan;
     if ((r = build_plan(c, f->dims, plan)) != FVR_OK) return r;
     plan_geometry(&plan, f);
-    const Grid g = make_grid(f->dims, f->bbox);
     // arena mode for this call: every scratch buffer is a slice of the static
     // array; timing events (created on first use) are off
     struct ArenaCall {
@@ -768,7 +806,7 @@ fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, doubl
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     Plan *p;
     if ((r = get_plan(c, f, &p)) != FVR_OK) return r;
-    const Grid g = make_grid(f->dims, f->bbox);
+    const Grid g = frame_grid(f);
     // the transform writes into the context's field first: on invalid input
     // the caller's buffer stays untouched
     GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
@@ -779,6 +817,7 @@ fvr_status fvr_indicator(fvr_ctx *c, const fvr_frame *f, float *field_out, doubl
     if ((r = sync(c)) != FVR_OK) return r;
     if (c->host_status->flags & kFlagInvalid)
         return fail(c, FVR_E_INVALID, "non-finite point, normal or weight, or a negative weight");
+    if (c->host_status->flags & kFlagRange) return fail(c, FVR_E_RANGE, kRangeMsg);
     HIP_TRY(c, hipMemcpyAsync(field_out, P<float>(c->field), sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2],
                               hipMemcpyDeviceToDevice, c->stream), "field copy");
     if ((r = sync(c)) != FVR_OK) return r;
@@ -813,7 +852,7 @@ fvr_status fvr_debug_splat(fvr_ctx *c, const fvr_frame *f, float *v_out) {
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     Plan *p;
     if ((r = get_plan(c, f, &p)) != FVR_OK) return r;
-    const Grid g = make_grid(f->dims, f->bbox);
+    const Grid g = frame_grid(f);
     // the splat writes V only on tiles that some point reaches
     HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(v_out), 3 * (int64_t)g.n[0] * g.n[1] * g.n[2], 0,
                                c->stream), "clear v_out");
@@ -1693,6 +1732,7 @@ const char *fvr_status_string(fvr_status s) {
         case FVR_E_NOMEM: return "out of device memory";
         case FVR_E_CAPACITY: return "output capacity too small";
         case FVR_E_DEVICE: return "device error";
+        case FVR_E_RANGE: return "16-bit spectrum overflow";
     }
     return "unknown status";
 }

@@ -45,7 +45,55 @@ struct Grid {
     float bmax[3];
     float h[3];        // (bmax - bmin) / N, float32
     float wstep[3];    // 2 pi / extent: angular frequency of wavenumber 1
+    // Spectrum storage: kSpecF32 (complex64), kSpecBF16 or kSpecF16 (two
+    // 16-bit floats per bin).  The reduced forms split the 1/n of the
+    // inverse over the forward passes (each stores its output times
+    // 1/N_axis), which keeps FP16 clear of overflow.
+    int spec_st;
+    float fscale[3];   // factor on the stored output of the x, y and z forward passes
+    float iscale;      // factor on A after the inverse (1/n for complex64, else 1)
 };
+constexpr int kSpecF32 = 0, kSpecBF16 = 1, kSpecF16 = 2;
+inline size_t spec_elem_bytes(int st) { return st == kSpecF32 ? 8 : 4;}
+
+// Load and store of one spectrum bin of storage `ST` at element index i.
+#if defined(__HIPCC__)
+template <int ST>
+__device__ __forceinline__ float2 spec_unpack(unsigned u) {
+    if constexpr (ST == kSpecBF16) {
+        return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+    } else {
+        const _Float16 lo = __builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
+        const _Float16 hi = __builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
+        return make_float2((float)lo, (float)hi);
+    }
+}
+// round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+    const unsigned b = __float_as_uint(x);
+    return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+template <int ST>
+__device__ __forceinline__ unsigned spec_pack(float2 v) {
+    if constexpr (ST == kSpecBF16) {
+        return bf16_bits(v.x) | (bf16_bits(v.y) << 16);
+    } else {
+        const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)v.x);
+        const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)v.y);
+        return lo | (hi << 16);
+    }
+}
+template <int ST>
+__device__ __forceinline__ float2 spec_ld(const void *base, size_t i) {
+    if constexpr (ST == kSpecF32) return static_cast<const float2 *>(base)[i];
+    else return spec_unpack<ST>(static_cast<const unsigned *>(base)[i]);
+}
+template <int ST>
+__device__ __forceinline__ void spec_st(void *base, size_t i, float2 v) {
+    if constexpr (ST == kSpecF32) static_cast<float2 *>(base)[i] = v;
+    else static_cast<unsigned *>(base)[i] = spec_pack<ST>(v);
+}
+#endif
 
 // Splat-specific constants.  Gaussian weights are evaluated per axis as
 // exp2(e1[a] * d^2) with d the point-to-centre offset in voxels of axis a:
@@ -62,7 +110,7 @@ struct SplatConsts {
 
 // Device-side status block, read back once per frame.
 struct DevStatus {
-    uint32_t flags;       // bit 0: invalid input value; bit 1: open surface
+    uint32_t flags;       // bit 0: invalid input value; bit 1: open surface; bit 2: 16-bit spectrum overflow
     uint32_t rejected;    // points outside the bbox
     int32_t mc_total[3];  // vertices, triangles, active cells
     int32_t n_used;       // points that entered the level average
@@ -77,6 +125,7 @@ struct DevStatus {
 };
 constexpr uint32_t kFlagInvalid = 1u;
 constexpr uint32_t kFlagOpen = 2u;
+constexpr uint32_t kFlagRange = 4u;
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (each enqueues on `s` and returns the launch error)
@@ -137,7 +186,7 @@ hipError_t launch_tile_list(const int32_t *bin_count, int32_t *bin_off, int nbin
                             int32_t *list, const uint2 *blk_max, int m, DevStatus *st, hipStream_t s);
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
-                              const int32_t *list, float2 *spec, float *v_out, hipStream_t s);
+                              const int32_t *list, void *spec, float *v_out, hipStream_t s);
 int splat_blocks();
 // Voxels of one channel plane of a splat tile (tile rows x Nx), at most.
 int splat_max_plane();
@@ -147,23 +196,25 @@ size_t splat_lds_bytes(const Grid &g, const SplatConsts &sc);
 // derivative terms: plane0 <- F_y(plane0) + j w_y F_y(plane1); plane2 <- F_y(plane2).
 // Rows of unoccupied tiles are read as zero; a z plane with no occupied tile
 // is neither read nor written and gets zocc[z] = 0 (1 otherwise).
-hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, DevStatus *st,
+hipError_t launch_fft_y_fwd(void *spec, const uint8_t *occ, uint8_t *zocc, DevStatus *st,
                             const Grid &g, const FftAxis &ax, hipStream_t s);
 // Forward z transform of planes 0 and 2, the spectral solve, inverse z:
 // plane0 <- F_z^-1[(F_z plane0 + j w_z F_z plane2) / |w|^2], DC -> 0.
 // Planes with zocc[z] = 0 are read as zero.
-hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, const FftAxis &az,
+hipError_t launch_fft_z_solve(void *spec, const uint8_t *zocc, const Grid &g, const FftAxis &az,
                               hipStream_t s);
 // Inverse y transform of plane 0.
-hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
+hipError_t launch_fft_y_inv(void *spec, const Grid &g, const FftAxis &ay, hipStream_t s);
 // Both inverse passes below in one kernel (one block per z plane; the plane
 // does not go back to HBM between them), for Nx = Ny = 256: fft_yx_fused(g).
 // rowmm[z Ny + y] receives (min, max) of A over the row.
 bool fft_yx_fused(const Grid &g);
-hipError_t launch_fft_yx_inv(const float2 *spec, float *A, float2 *rowmm, const Grid &g,
+hipError_t launch_fft_yx_inv(const void *spec, float *A, float2 *rowmm, DevStatus *st, const Grid &g,
                              const FftAxis &ay, hipStream_t s);
-// Inverse real FFT along x of plane 0, scaled by 1/n -> A (Nz, Ny, Nx).
-hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const FftAxis &ax,
+// Inverse real FFT along x of plane 0, scaled by g.iscale -> A (Nz, Ny, Nx).
+// With a 16-bit spectrum storage both inverse kernels set kFlagRange in st
+// when they write a non-finite value (an overflowed store upstream).
+hipError_t launch_fft_x_c2r(const void *spec, float *A, DevStatus *st, const Grid &g, const FftAxis &ax,
                             hipStream_t s);
 
 // Iso-level: per-block double partial sums of trilinear A at accepted points,

@@ -298,18 +298,33 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
 // (Word 3 of the resource: the raw 32-bit-element format of gfx9-family GPUs.)
 constexpr unsigned kOob = 0xFFFFFFF0u;  // an offset past any spectrum allocation
 
+// One spectrum plane behind a buffer resource, storage ST (kB bytes per bin).
+template <int ST>
 struct SpecBuf {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    static constexpr unsigned kB = ST == kSpecF32 ? 8u : 4u;
     __amdgpu_buffer_rsrc_t r;
-    __device__ __forceinline__ SpecBuf(const float2 *base, unsigned bytes)
-        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base), (short)0, (int)bytes, 0x00020000)) {}
+    __device__ __forceinline__ SpecBuf(const void *base, unsigned bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000)) {}
     __device__ __forceinline__ float2 load(unsigned off) const {
-        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        if constexpr (ST == kSpecF32)
+            return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        else
+            return spec_unpack<ST>(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     }
     __device__ __forceinline__ void store(unsigned off, float2 v) const {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+        if constexpr (ST == kSpecF32)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(spec_pack<ST>(v), r, off, 0, 0);
     }
 };
+
+// byte address of plane p of a spectrum array with bins of kB bytes
+template <int ST>
+__device__ __forceinline__ const char *plane_base(const void *spec, size_t plane, int p) {
+    return static_cast<const char *>(spec) + (size_t)p * plane * SpecBuf<ST>::kB;
+}
 
 template <int N1, int N2>
 struct Pencil {
@@ -378,9 +393,9 @@ struct Pencil {
     }
 };
 
-template <int N1, int N2>
+template <int N1, int N2, int ST>
 __global__ void __launch_bounds__(16 * N2)
-pen_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
+pen_y_fwd_kernel(void *__restrict__ spec, const uint8_t *__restrict__ occ,
                  uint8_t *__restrict__ zocc, DevStatus *__restrict__ st, Grid g,
                  const float2 *__restrict__ twg) {
     using Pn = Pencil<N1, N2>;
@@ -415,10 +430,13 @@ pen_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
     // byte offsets: rows of tiles that no point reaches (and idle lanes) get
     // an offset past the range and read as zero
     // one resource per plane, so the same offsets serve all three
-    const unsigned plb = (unsigned)(plane * sizeof(float2));
-    const SpecBuf s0(spec, plb), s1(spec + plane, plb), s2(spec + 2 * plane, plb);
-    const unsigned o0 = (unsigned)(((size_t)z * N * Hp + k0 + c) * sizeof(float2));
-    const unsigned rowb = (unsigned)Hp * sizeof(float2);
+    using SB = SpecBuf<ST>;
+    const unsigned plb = (unsigned)(plane * SB::kB);
+    const SB s0(spec, plb), s1(plane_base<ST>(spec, plane, 1), plb), s2(plane_base<ST>(spec, plane, 2), plb);
+    const unsigned o0 = (unsigned)(((size_t)z * N * Hp + k0 + c) * SB::kB);
+    const unsigned rowb = (unsigned)Hp * SB::kB;
+    // the reduced storages keep their share of the inverse's 1/n here
+    const float sy = ST == kSpecF32 ? 1.0f : g.fscale[1];
     unsigned ro[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
@@ -439,18 +457,24 @@ pen_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
     for (int i = 0; i < N1; ++i) {
         const int r = Pn::out_row(t, i);
         const float w = deriv_w(r, N, g.wstep[1]);
-        s0.store(col ? so + (unsigned)r * rowb : kOob, make_float2(a[i].x - w * b[i].y, a[i].y + w * b[i].x));
+        float2 v = make_float2(a[i].x - w * b[i].y, a[i].y + w * b[i].x);
+        if (ST != kSpecF32) v = make_float2(v.x * sy, v.y * sy);
+        s0.store(col ? so + (unsigned)r * rowb : kOob, v);
     }
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) b[n1] = s2.load(ro[n1]);
     Pn::template run<-1>(b, ex, tw, c, t);
 #pragma unroll
-    for (int i = 0; i < N1; ++i) s2.store(col ? so + (unsigned)Pn::out_row(t, i) * rowb : kOob, b[i]);
+    for (int i = 0; i < N1; ++i) {
+        float2 v = b[i];
+        if (ST != kSpecF32) v = make_float2(v.x * sy, v.y * sy);
+        s2.store(col ? so + (unsigned)Pn::out_row(t, i) * rowb : kOob, v);
+    }
 }
 
-template <int N1, int N2>
+template <int N1, int N2, int ST>
 __global__ void __launch_bounds__(16 * N2)
-pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, Grid g,
+pen_z_solve_kernel(void *__restrict__ spec, const uint8_t *__restrict__ zocc, Grid g,
                    const float2 *__restrict__ twg) {
     using Pn = Pencil<N1, N2>;
     constexpr int N = Pn::N;  // = Nz
@@ -466,15 +490,16 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
     // planes 0 and 2 through raw buffer resources: 32-bit byte offsets, and
     // z planes that stay zero (and idle lanes) read as zero without a load
     const size_t plane = (size_t)N * Ny * Hp;
-    const unsigned plb = (unsigned)(plane * sizeof(float2));
-    const SpecBuf s0(spec, plb), s2(spec + 2 * plane, plb);
-    const unsigned zsb = (unsigned)Ny * Hp * sizeof(float2);
+    using SB = SpecBuf<ST>;
+    const unsigned plb = (unsigned)(plane * SB::kB);
+    const SB s0(spec, plb), s2(plane_base<ST>(spec, plane, 2), plb);
+    const unsigned zsb = (unsigned)Ny * Hp * SB::kB;
     const int nch = nchunks(H);
     const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
     const int k0 = chunk * kChunk;
     const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
     const bool col = k0 + c < H;
-    const unsigned o0 = (unsigned)(((size_t)ky * Hp + k0 + c) * sizeof(float2));
+    const unsigned o0 = (unsigned)(((size_t)ky * Hp + k0 + c) * SB::kB);
     float2 a[N1], b[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
@@ -495,7 +520,8 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
         const float wzf = (float)kappa(kz, N) * g.wstep[2];
         const float w2 = wxy + wzf * wzf;
         // v_rcp_f32 (about 1 ulp) in place of a correctly rounded divide
-        const float inv = w2 > 0.f ? __builtin_amdgcn_rcpf(w2) : 0.0f;
+        float inv = w2 > 0.f ? __builtin_amdgcn_rcpf(w2) : 0.0f;
+        if (ST != kSpecF32) inv *= g.fscale[2];  // the z share of the inverse's 1/n
         const float wz = deriv_w(kz, N, g.wstep[2]);
         a[i] = make_float2((a[i].x - wz * b[i].y) * inv, (a[i].y + wz * b[i].x) * inv);
     }
@@ -505,9 +531,9 @@ pen_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
     for (int i = 0; i < N1; ++i) s0.store(col ? o0 + (unsigned)Pn::out_row(t, i) * zsb : kOob, a[i]);
 }
 
-template <int N1, int N2>
+template <int N1, int N2, int ST>
 __global__ void __launch_bounds__(16 * N2)
-pen_y_inv_kernel(float2 *__restrict__ spec, Grid g, const float2 *__restrict__ twg) {
+pen_y_inv_kernel(void *__restrict__ spec, Grid g, const float2 *__restrict__ twg) {
     using Pn = Pencil<N1, N2>;
     constexpr int N = Pn::N;  // = Ny
     __shared__ float2 ex[Pn::EX];
@@ -520,15 +546,15 @@ pen_y_inv_kernel(float2 *__restrict__ spec, Grid g, const float2 *__restrict__ t
     const int k0 = chunk * kChunk;
     const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
     const bool col = k0 + c < H;
-    float2 *p = spec + (size_t)z * N * Hp + k0 + c;
+    const size_t p = (size_t)z * N * Hp + k0 + c;
     float2 a[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1)
-        a[n1] = col ? p[(size_t)Pn::in_row(t, n1) * Hp] : make_float2(0.f, 0.f);
+        a[n1] = col ? spec_ld<ST>(spec, p + (size_t)Pn::in_row(t, n1) * Hp) : make_float2(0.f, 0.f);
     Pn::template run<+1>(a, ex, tw, c, t);
 #pragma unroll
     for (int i = 0; i < N1; ++i)
-        if (col) p[(size_t)Pn::out_row(t, i) * Hp] = a[i];
+        if (col) spec_st<ST>(spec, p + (size_t)Pn::out_row(t, i) * Hp, a[i]);
 }
 
 // Inverse real transform along x for pencil lengths: a block takes 32 real
@@ -538,9 +564,9 @@ pen_y_inv_kernel(float2 *__restrict__ spec, Grid g, const float2 *__restrict__ t
 // writes Re -> row a, Im -> row b.  Spectra are read once each (both Z[k] and
 // Z[N-k] come from the pair at k) and the real rows leave through LDS as
 // 16-byte stores.
-template <int N1, int N2>
+template <int N1, int N2, int ST>
 __global__ void __launch_bounds__(16 * N2)
-pen_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
+pen_x_c2r_kernel(const void *__restrict__ spec, float *__restrict__ A, DevStatus *__restrict__ st, Grid g,
                  const float2 *__restrict__ twg, float scale) {
     using Pn = Pencil<N1, N2>;
     constexpr int N = Pn::N;  // = Nx
@@ -559,8 +585,8 @@ pen_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
         const int ra = row0 + 2 * c;
         float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
         if (ra < nrows) {
-            a = spec[(size_t)ra * Hp + k];
-            b = spec[(size_t)(ra + 1) * Hp + k];
+            a = spec_ld<ST>(spec, (size_t)ra * Hp + k);
+            b = spec_ld<ST>(spec, (size_t)(ra + 1) * Hp + k);
         }
         if (k == 0 || k == N / 2) {
             a.y = 0.f;
@@ -577,12 +603,16 @@ pen_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
     __syncthreads();  // buf becomes the exchange buffer
     Pn::template run<+1>(x, buf, tw, c, t);
     float *ob = reinterpret_cast<float *>(buf);
+    bool bad = false;
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
         const int k = Pn::out_row(t, i);
         ob[(2 * c) * OP + k] = x[i].x * scale;
         ob[(2 * c + 1) * OP + k] = x[i].y * scale;
+        if constexpr (ST != kSpecF32) bad |= !__builtin_isfinite(x[i].x) || !__builtin_isfinite(x[i].y);
     }
+    if constexpr (ST != kSpecF32)
+        if (bad) atomicOr(&st->flags, kFlagRange);
     __syncthreads();
     constexpr int Q4 = N / 4;  // float4 per real row
     for (int i = threadIdx.x; i < 32 * Q4; i += Pn::THREADS) {
@@ -613,9 +643,10 @@ constexpr int kYxBuf = 4 * PenYx::EX;  // float2: four exchange buffers
 static_assert(kYxBuf >= (kYx / 2) * kYxYP, "half plane of y-inverse rows fits");
 static_assert(2 * kYxBuf >= (kYx / 2) * kYxOP, "half plane of output rows fits");
 
+template <int ST>
 __global__ void __launch_bounds__(kYxThreads)
-yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm,
-                 Grid g, const float2 *__restrict__ twg, float scale) {
+yx_inv256_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm,
+                 DevStatus *__restrict__ st, Grid g, const float2 *__restrict__ twg, float scale) {
     using Pn = PenYx;
     constexpr int N = kYx;
     extern __shared__ __attribute__((aligned(16))) float2 smem[];
@@ -626,11 +657,11 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 
     const int grp = threadIdx.x >> 8, lt = threadIdx.x & 255;
     const int c = lt & 15, t = lt >> 4;
     const int z = blockIdx.x, Hp = g.Hp;
-    const float2 *P = spec + (size_t)z * N * Hp;
+    const size_t P = (size_t)z * N * Hp;  // the plane's first bin
     float2 *ex = buf + grp * Pn::EX;
     if (threadIdx.x < N) {
         tw[threadIdx.x] = twg[threadIdx.x];
-        nyq[threadIdx.x] = P[(size_t)threadIdx.x * Hp + N / 2];
+        nyq[threadIdx.x] = spec_ld<ST>(spec, P + (size_t)threadIdx.x * Hp + N / 2);
     }
 
     // y-inverse of chunks grp and grp + 4 (columns 16 ch + c)
@@ -642,7 +673,7 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) a[h][n1] = P[(size_t)(16 * n1) * Hp + lo + 64u * h];
+        for (int n1 = 0; n1 < 16; ++n1) a[h][n1] = spec_ld<ST>(spec, P + (size_t)(16 * n1) * Hp + lo + 64u * h);
     __syncthreads();  // twiddles and the Nyquist column
     if (grp == 0 && c == 0) {
         // column 0 carries the Nyquist column in its imaginary part
@@ -702,6 +733,7 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 
         Pn::template run<+1, true>(x, ex, tw, c, t);
         // every group is past the exchange (run ends with a block barrier)
         float4 mm = make_float4(x[0].x, x[0].x, x[0].y, x[0].y);  // min, max of rows ra, rb
+        bool bad = false;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int k = Pn::out_row(t, i);
@@ -709,7 +741,10 @@ yx_inv256_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 
             O[rb * kYxOP + k] = x[i].y * scale;
             mm = make_float4(fminf(mm.x, x[i].x), fmaxf(mm.y, x[i].x), fminf(mm.z, x[i].y),
                              fmaxf(mm.w, x[i].y));
+            if constexpr (ST != kSpecF32) bad |= !__builtin_isfinite(x[i].x) || !__builtin_isfinite(x[i].y);
         }
+        if constexpr (ST != kSpecF32)
+            if (bad) atomicOr(&st->flags, kFlagRange);
         // lanes c, c + 16, c + 32, c + 48 of a wave hold the same row pair
 #pragma unroll
         for (int d = 16; d < 64; d <<= 1) {
@@ -768,6 +803,15 @@ static int pencil_code(int n) {
         default: KERNEL<16, 16><<<GRID, 256, 0, s>>> ARGS; break;                       \
     }
 
+#define FVR_PEN_SWITCH3(code, KERNEL, ST, ARGS, GRID)                                     \
+    switch (code) {                                                                       \
+        case 44: KERNEL<4, 4, ST><<<GRID, 64, 0, s>>> ARGS; break;                      \
+        case 84: KERNEL<8, 4, ST><<<GRID, 64, 0, s>>> ARGS; break;                      \
+        case 88: KERNEL<8, 8, ST><<<GRID, 128, 0, s>>> ARGS; break;                     \
+        case 168: KERNEL<16, 8, ST><<<GRID, 128, 0, s>>> ARGS; break;                   \
+        default: KERNEL<16, 16, ST><<<GRID, 256, 0, s>>> ARGS; break;                   \
+    }
+
 // Per-thread prefetch depth for a pencil length: len * kChunk / 2 / 256 16-byte loads.
 static int prefetch_depth(int len) {
     const int need = (len * (kChunk / 2) + kPassThreads - 1) / kPassThreads;
@@ -789,7 +833,8 @@ hipError_t fft_configure() {
                        (const void *)fft_z_solve_kernel<8>, (const void *)fft_z_solve_kernel<16>,
                        (const void *)fft_y_inv_kernel<2>,   (const void *)fft_y_inv_kernel<4>,
                        (const void *)fft_y_inv_kernel<8>,   (const void *)fft_y_inv_kernel<16>,
-                       (const void *)fft_x_c2r_kernel, (const void *)yx_inv256_kernel};
+                       (const void *)fft_x_c2r_kernel, (const void *)yx_inv256_kernel<kSpecF32>,
+                       (const void *)yx_inv256_kernel<kSpecBF16>, (const void *)yx_inv256_kernel<kSpecF16>};
     for (const void *f : k) {
         hipError_t e = raise_dynamic_lds(f);
         if (e != hipSuccess) return e;
@@ -800,64 +845,89 @@ hipError_t fft_configure() {
 // pencil buffers plus the twiddle table
 static size_t pass_lds(int n, int bufs) { return ((size_t)bufs * n * kChunk + n) * sizeof(float2); }
 
-hipError_t launch_fft_y_fwd(float2 *spec, const uint8_t *occ, uint8_t *zocc, DevStatus *st,
+// Pencil kernels instantiated for the spectrum storage of the grid.
+#define FVR_PEN_ST(code, KERNEL, ARGS, GRID)                                                  \
+    switch (g.spec_st) {                                                                      \
+        case kSpecBF16: { FVR_PEN_SWITCH3(code, KERNEL, kSpecBF16, ARGS, GRID) } break;       \
+        case kSpecF16: { FVR_PEN_SWITCH3(code, KERNEL, kSpecF16, ARGS, GRID) } break;         \
+        default: { FVR_PEN_SWITCH3(code, KERNEL, kSpecF32, ARGS, GRID) } break;               \
+    }
+
+hipError_t launch_fft_y_fwd(void *spec, const uint8_t *occ, uint8_t *zocc, DevStatus *st,
                             const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
     if (const int pc = pencil_code(g.n[1])) {
-        FVR_PEN_SWITCH(pc, pen_y_fwd_kernel, (spec, occ, zocc, st, g, ax.tw), dim3(nch * g.n[2]))
+        FVR_PEN_ST(pc, pen_y_fwd_kernel, (spec, occ, zocc, st, g, ax.tw), dim3(nch * g.n[2]))
         return hipGetLastError();
     }
-    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, (spec, occ, zocc, st, g, ax), dim3(nch * g.n[2]),
+    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;  // complex64 only on Stockham lengths
+    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, (static_cast<float2 *>(spec), occ, zocc, st, g, ax), dim3(nch * g.n[2]),
                   dim3(kPassThreads), pass_lds(g.n[1], 2), s)
     return hipGetLastError();
 }
 
-hipError_t launch_fft_z_solve(float2 *spec, const uint8_t *zocc, const Grid &g, const FftAxis &ax,
+hipError_t launch_fft_z_solve(void *spec, const uint8_t *zocc, const Grid &g, const FftAxis &ax,
                               hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
     if (const int pc = pencil_code(g.n[2])) {
-        FVR_PEN_SWITCH(pc, pen_z_solve_kernel, (spec, zocc, g, ax.tw), dim3(nch * g.n[1]))
+        FVR_PEN_ST(pc, pen_z_solve_kernel, (spec, zocc, g, ax.tw), dim3(nch * g.n[1]))
         return hipGetLastError();
     }
-    FVR_PF_SWITCH(g.n[2], fft_z_solve_kernel, (spec, zocc, g, ax), dim3(nch * g.n[1]),
+    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;
+    FVR_PF_SWITCH(g.n[2], fft_z_solve_kernel, (static_cast<float2 *>(spec), zocc, g, ax), dim3(nch * g.n[1]),
                   dim3(kPassThreads), pass_lds(g.n[2], 2), s)
     return hipGetLastError();
 }
 
-hipError_t launch_fft_y_inv(float2 *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
+hipError_t launch_fft_y_inv(void *spec, const Grid &g, const FftAxis &ax, hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
     if (const int pc = pencil_code(g.n[1])) {
-        FVR_PEN_SWITCH(pc, pen_y_inv_kernel, (spec, g, ax.tw), dim3(nch * g.n[2]))
+        FVR_PEN_ST(pc, pen_y_inv_kernel, (spec, g, ax.tw), dim3(nch * g.n[2]))
         return hipGetLastError();
     }
-    FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, (spec, g, ax), dim3(nch * g.n[2]), dim3(kPassThreads),
+    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;
+    FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, (static_cast<float2 *>(spec), g, ax), dim3(nch * g.n[2]), dim3(kPassThreads),
                   pass_lds(g.n[1], 1), s)
     return hipGetLastError();
 }
 
 bool fft_yx_fused(const Grid &g) { return g.n[0] == kYx && g.n[1] == kYx; }
 
-hipError_t launch_fft_yx_inv(const float2 *spec, float *A, float2 *rowmm, const Grid &g,
+hipError_t launch_fft_yx_inv(const void *spec, float *A, float2 *rowmm, DevStatus *st, const Grid &g,
                              const FftAxis &ay, hipStream_t s) {
     if (!fft_yx_fused(g)) return hipErrorInvalidValue;
-    const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
-    yx_inv256_kernel<<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, rowmm, g, ay.tw,
-                                                                            scale);
+    const float scale = g.spec_st == kSpecF32 ? 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]) : g.iscale;
+    switch (g.spec_st) {
+        case kSpecBF16:
+            yx_inv256_kernel<kSpecBF16><<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, rowmm, st, g,
+                                                                                           ay.tw, scale);
+            break;
+        case kSpecF16:
+            yx_inv256_kernel<kSpecF16><<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, rowmm, st, g,
+                                                                                          ay.tw, scale);
+            break;
+        default:
+            yx_inv256_kernel<kSpecF32><<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, rowmm, st, g,
+                                                                                          ay.tw, scale);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_fft_x_c2r(const float2 *spec, float *A, const Grid &g, const FftAxis &ax,
+hipError_t launch_fft_x_c2r(const void *spec, float *A, DevStatus *st, const Grid &g, const FftAxis &ax,
                             hipStream_t s) {
     const int nrows = g.n[1] * g.n[2];
     if (const int pc = pencil_code(g.n[0])) {
-        const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
-        FVR_PEN_SWITCH(pc, pen_x_c2r_kernel, (spec, A, g, ax.tw, scale), dim3((nrows + 31) / 32))
+        const float scale = g.spec_st == kSpecF32 ? 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2])
+                                                  : g.iscale;
+        FVR_PEN_ST(pc, pen_x_c2r_kernel, (spec, A, st, g, ax.tw, scale), dim3((nrows + 31) / 32))
         return hipGetLastError();
     }
+    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;
     const int blocks = (nrows + kC2rRows - 1) / kC2rRows;
     const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
     const size_t lds = ((size_t)(kC2rRows / 2) * g.n[0] + g.n[0]) * sizeof(float2);
-    fft_x_c2r_kernel<<<dim3(blocks), dim3(kPassThreads), lds, s>>>(spec, A, g, ax, scale);
+    fft_x_c2r_kernel<<<dim3(blocks), dim3(kPassThreads), lds, s>>>(static_cast<const float2 *>(spec), A, g, ax,
+                                                                  scale);
     return hipGetLastError();
 }
 

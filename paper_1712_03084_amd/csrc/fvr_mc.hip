@@ -358,7 +358,7 @@ level_partial_kernel(const float *__restrict__ pts, int m, const float *__restri
     scnt[threadIdx.x] = cnt;
     __syncthreads();
     for (int w = kLevelThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if ((int)threadIdx.x < w) {
             ssum[threadIdx.x] += ssum[threadIdx.x + w];
             scnt[threadIdx.x] += scnt[threadIdx.x + w];
         }
@@ -405,7 +405,7 @@ __device__ __forceinline__ void level_reduce(const double *__restrict__ psum, co
     scnt[threadIdx.x] = cnt;
     __syncthreads();
     for (int w = kLevelThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if ((int)threadIdx.x < w) {
             ssum[threadIdx.x] += ssum[threadIdx.x + w];
             scnt[threadIdx.x] += scnt[threadIdx.x + w];
         }

@@ -300,7 +300,7 @@ template <bool kNearest>
 __global__ void __launch_bounds__(kSplatThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ bin_off, Grid g,
                    SplatConsts sc, FftAxis ax, DevStatus *__restrict__ st,
-                   const int32_t *__restrict__ list, float2 *__restrict__ spec,
+                   const int32_t *__restrict__ list, void *__restrict__ spec,
                    float *__restrict__ v_out) {
     extern __shared__ unsigned long long acc[];
     __shared__ int b_start[kMaxBins], b_pre[kMaxBins + 1], b_rows[kMaxBins], b_ny[kMaxBins];
@@ -623,8 +623,24 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
         }
         const int ya = y0 + ra % TY, za = z0 + ra / TY;
         const int yb = y0 + (ra + 1) % TY, zb = z0 + (ra + 1) / TY;
-        if (ya < Ny && za < Nz) spec[c * pl + ((size_t)za * Ny + ya) * Hp + kx] = xa;
-        if (yb < Ny && zb < Nz) spec[c * pl + ((size_t)zb * Ny + yb) * Hp + kx] = xb;
+        const size_t ia = c * pl + ((size_t)za * Ny + ya) * Hp + kx;
+        const size_t ib = c * pl + ((size_t)zb * Ny + yb) * Hp + kx;
+        if (g.spec_st == kSpecF32) {
+            if (ya < Ny && za < Nz) spec_st<kSpecF32>(spec, ia, xa);
+            if (yb < Ny && zb < Nz) spec_st<kSpecF32>(spec, ib, xb);
+        } else {
+            // the reduced storages keep the x share of the inverse's 1/n
+            const float sx = g.fscale[0];
+            xa = make_float2(xa.x * sx, xa.y * sx);
+            xb = make_float2(xb.x * sx, xb.y * sx);
+            if (g.spec_st == kSpecBF16) {
+                if (ya < Ny && za < Nz) spec_st<kSpecBF16>(spec, ia, xa);
+                if (yb < Ny && zb < Nz) spec_st<kSpecBF16>(spec, ib, xb);
+            } else {
+                if (ya < Ny && za < Nz) spec_st<kSpecF16>(spec, ia, xa);
+                if (yb < Ny && zb < Nz) spec_st<kSpecF16>(spec, ib, xb);
+            }
+        }
     }
     __syncthreads();  // LDS is reused by the next tile
     }
@@ -824,7 +840,7 @@ int bin_scan_tiles(int nbins) { return scan_tiles(nbins); }
 
 hipError_t launch_splat_fft_x(const float4 *rec, const int32_t *bin_off, const Grid &g,
                               const SplatConsts &sc, const FftAxis &ax, DevStatus *st,
-                              const int32_t *list, float2 *spec, float *v_out, hipStream_t s) {
+                              const int32_t *list, void *spec, float *v_out, hipStream_t s) {
     const int tiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     const int blocks = tiles < g_splat_blocks ? tiles : g_splat_blocks;
     const size_t lds = splat_lds_bytes(g, sc);

@@ -68,10 +68,29 @@ def test_mc_table_identical_to_oracle_generator():
     assert np.array_equal(e_gpu, e_orc)
 
 
+def test_check_frame_option_bits():
+    """Spectrum storages: one at a time, and only on the pencil lengths."""
+    ok = (-1, -1, -1, 1, 1, 1)
+    bf16, fp16, nearest = 2, 4, 1
+    for opt in (0, bf16, fp16, nearest, nearest | bf16, nearest | fp16):
+        assert fvr.check_frame(10, (64, 64, 64), ok, options=opt) == 0
+    assert fvr.check_frame(10, (64, 64, 64), ok, options=bf16 | fp16) == -1
+    assert fvr.check_frame(10, (64, 64, 64), ok, options=8) == -1
+    for dims in ((48, 64, 64), (64, 96, 64), (64, 64, 512)):
+        assert fvr.check_frame(10, dims, ok) == 0
+        assert fvr.check_frame(10, dims, ok, options=bf16) == -2
+        assert fvr.check_frame(10, dims, ok, options=fp16) == -2
+    assert fvr.check_frame(10, (16, 256, 128), ok, options=fp16) == 0
+
+
 def test_status_strings_and_null_context():
     lib = fvr.load_library()
-    for s in (0, -1, -2, -3, -4, -5):
-        assert lib.fvr_status_string(s)
+    names = set()
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.fvr_status_string(s) and lib.fvr_status_string(s) != b"unknown status"
+        names.add(lib.fvr_status_string(s))
+    assert len(names) == 7
+    assert fvr.STATUS[-6] == "FVR_E_RANGE"
     assert lib.fvr_reconstruct(None, None, None) == -1
     assert lib.fvr_last_error(None)
 

@@ -1,0 +1,88 @@
+"""Reduced-precision spectrum storage (bf16 / fp16 between the transform
+passes, float32 arithmetic): the indicator's max-abs and RMS error and the
+mesh's Hausdorff distance against the FP64 oracle, stated per storage."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1712_03084_amd as fvr  # noqa: E402
+
+# error bars: max and RMS indicator error as fractions of the oracle
+# indicator's range, mesh Hausdorff distance in voxels.  A rounding model of
+# the stores (float64 transforms, each stored value rounded to the storage
+# type) predicts max / RMS of 5.1e-3 / 9.7e-4 (bf16) and 7.6e-4 / 1.2e-4
+# (fp16) on the 64^3 sphere and at most 2.1e-3 / 1.5e-4 (bf16) and
+# 2.7e-4 / 1.9e-5 (fp16) on the 128^3 and 256^3 body proxies: the bars are
+# about twice the worst of these.
+BARS = {"bf16": (1e-2, 2e-3, 1.0), "fp16": (1.5e-3, 2.5e-4, 0.25)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return fvr.Context(0)
+
+
+def _hausdorff(a, b):
+    from scipy.spatial import cKDTree
+    return float(max(cKDTree(b).query(a)[0].max(), cKDTree(a).query(b)[0].max()))
+
+
+@pytest.mark.parametrize("config", ["sphere64", "proxy128", "proxy256"])
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_reduced_storage_error_against_fp64(ctx, config, storage):
+    f = synth.config_frame(config)
+    d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (f.points, f.normals, f.weights)]
+    A, L = ctx.indicator(*d, grid_dim=f.dims, bbox=f.bbox, storage=storage)
+    mesh = ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox, storage=storage)
+    A32, _ = ctx.indicator(*d, grid_dim=f.dims, bbox=f.bbox)
+    r = oracle.reconstruct(f.points, f.normals, f.weights, f.dims, f.bbox)
+    Ao = r["A"]
+    rng_ = Ao.max() - Ao.min()
+    e = A.cpu().numpy().astype(np.float64) - Ao
+    emax, erms = np.abs(e).max() / rng_, np.sqrt(np.mean(e * e)) / rng_
+    e32 = np.abs(A32.cpu().numpy() - Ao).max() / rng_
+    h = (f.bbox[3] - f.bbox[0]) / f.dims[0]
+    hd = _hausdorff(mesh.vertices.cpu().numpy().astype(np.float64), r["verts"])
+    print(f"[{storage}] {config}: A max err {emax:.3g}, rms {erms:.3g} of range (f32 storage {e32:.3g}); "
+          f"L err {abs(L - r['level']) / rng_:.3g}; mesh Hausdorff {hd / h:.3g} voxels = {hd * 1e3:.3g} mm "
+          f"({mesh.vertices.shape[0]} vs {len(r['verts'])} vertices)", flush=True)
+    bmax, brms, bhd = BARS[storage]
+    assert emax <= bmax and erms <= brms and hd <= bhd * h
+
+
+def test_reduced_storage_needs_pencil_lengths(ctx):
+    f = synth.sphere_frame(seed=1, m=5000, grid=48)
+    d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (f.points, f.normals, f.weights)]
+    with pytest.raises(fvr.FvrError) as e:
+        ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox, storage="bf16")
+    assert e.value.status == -2
+    # f32 storage of the same frame is unaffected
+    assert ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox).vertices.shape[0] > 0
+
+
+def test_fp16_overflow_is_an_error_not_a_wrong_answer(ctx):
+    """Normals of length 1e9 drive the FP16 spectrum past its largest value:
+    the call fails with FVR_E_RANGE; bf16 (float32's exponent range) and
+    float32 storage take the same frame."""
+    f = synth.sphere_frame(seed=2, m=20000, grid=64)
+    pts = torch.from_numpy(np.ascontiguousarray(f.points)).cuda()
+    big = torch.from_numpy(np.ascontiguousarray(f.normals) * np.float32(1e9)).cuda()
+    with pytest.raises(fvr.FvrError) as e:
+        ctx.reconstruct(pts, big, None, grid_dim=f.dims, bbox=f.bbox, storage="fp16")
+    assert e.value.status == -6
+    with pytest.raises(fvr.FvrError) as e:
+        ctx.indicator(pts, big, None, grid_dim=f.dims, bbox=f.bbox, storage="fp16")
+    assert e.value.status == -6
+    ref = ctx.reconstruct(pts, big, None, grid_dim=f.dims, bbox=f.bbox)
+    m16 = ctx.reconstruct(pts, big, None, grid_dim=f.dims, bbox=f.bbox, storage="bf16")
+    assert ref.vertices.shape[0] > 0 and abs(m16.vertices.shape[0] - ref.vertices.shape[0]) <= 0.01 * ref.vertices.shape[0]
+    # the context is usable afterwards, and the flag does not stick
+    unit = torch.from_numpy(np.ascontiguousarray(f.normals)).cuda()
+    assert ctx.reconstruct(pts, unit, None, grid_dim=f.dims, bbox=f.bbox, storage="fp16").vertices.shape[0] > 0

@@ -259,7 +259,7 @@ typedef struct {
     int64_t n_points;
     int32_t dims[3];
     float bbox[6];
-    uint32_t options;                        /* FVR_SPLAT_* */
+    uint32_t options;                        /* FVR_SPLAT_*, FVR_STORAGE_* */
     uint32_t flags;                          /* FVR_REQUEST_* */
     float *vertices;                         /* host out: vertex_capacity x 3 */
     int32_t *triangles;                      /* host out: triangle_capacity x 3 */

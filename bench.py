@@ -243,6 +243,50 @@ def bench_batch(args, fvr, synth, torch, np, dev):
                                                   "tuned_us": v["us"]} for k, v in tuned.items()}}
 
 
+def bench_batch_headline(args, fvr, torch, np, dev, pool, dims, bbox):
+    """The headline workload's frames through the batch: n frames of the pool
+    per call, spread over S slots (frames of different slots overlap on the
+    device), one captured graph and one synchronisation per call."""
+    n = min(args.headline_batch, len(pool))
+    print(f"[bench] headline frames batched: {n} per call", file=sys.stderr, flush=True)
+    vcap = 200_000
+    outs = [(torch.empty((vcap, 3), dtype=torch.float32, device=dev),
+             torch.empty((2 * vcap, 3), dtype=torch.int32, device=dev)) for _ in range(n)]
+    devs = [tuple(pool[i]) + (dims, bbox) for i in range(n)]
+    reps = max(2, args.steps // n)
+    sweep, best = {}, None
+    for slots in [int(x) for x in args.headline_slots.split(",") if x]:
+        b = fvr.Batch(slots=slots, graph=True)
+        pb = b.prepare(devs, outs)
+        for _ in range(2):
+            pb.run()  # capture, then a replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pb.run()
+        fps = reps * n / (time.perf_counter() - t0)
+        sweep[slots] = round(fps, 2)
+        if best is None or fps > best[1]:
+            if best is not None:
+                best[2].close()
+            best = (slots, fps, b, pb)
+        else:
+            b.close()
+    slots, fps, b, pb = best
+    lat = []
+    for _ in range(max(20, args.latency_frames // n)):
+        ts = time.perf_counter()
+        pb.run()
+        lat.append(time.perf_counter() - ts)
+    b.close()
+    lat = np.asarray(lat) * 1e3
+    return {"workload": f"{n} frames of the headline pool per call", "frames": n, "unit": "frames/s",
+            "batched_value": round(fps, 2), "slots": slots, "slots_sweep": sweep,
+            "batch_p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "batch_p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "batch_latency_samples": len(lat)}
+
+
 def bench_serve(args, fvr, synth, np, captures):
     """Serving (config 5): three capture stations (128^3 with 4 views, 192^3
     and 256^3 with 6) emit frames at 30 Hz each with exponential
@@ -329,6 +373,11 @@ def main():
     ap.add_argument("--storages", default="bf16,fp16",
                     help="16-bit spectrum storages measured on the headline workload after it and "
                          "reported under 'storage' (empty: none)")
+    ap.add_argument("--headline-batch", type=int, default=16,
+                    help="frames of the headline pool per batched call, measured after the plain "
+                         "form and reported under 'batched_headline' (0: skip)")
+    ap.add_argument("--headline-slots", default="2,4,8",
+                    help="slot counts of the batched headline measurement; the fastest is reported")
     ap.add_argument("--batch", type=int, default=16,
                     help="frames of the batched workload (16 uneven frames on {96..192}^3 grids) "
                          "measured after the headline one, batched and plain (0: skip)")
@@ -586,6 +635,9 @@ def main():
             del sp, A16
         del A32
         result["storage"] = stor
+
+    if args.headline_batch > 0:
+        result["batched_headline"] = bench_batch_headline(args, fvr, torch, np, dev, pool, dims, bbox)
 
     if args.batch > 0:
         result["batched"] = bench_batch(args, fvr, synth, torch, np, dev)

@@ -465,7 +465,7 @@ fvr_status field_bufs(fvr_ctx *c, const Grid &g, const Plan *p, int m) {
     // sized for both scans of the frame before anything is enqueued
     const int scan_items = std::max(bin_scan_tiles(nbins), 3 * scan_partials(mc_blocks(g)));
     GET(c, c->scan_part, sizeof(int32_t) * (size_t)scan_items, "scan scratch");
-    if (fft_yx_fused(g)) GET(c, c->rowmm, sizeof(float2) * (size_t)g.n[1] * g.n[2], "row ranges");
+    GET(c, c->rowmm, sizeof(float2) * (size_t)g.n[1] * g.n[2], "row ranges");
     return FVR_OK;
 }
 
@@ -550,7 +550,7 @@ fvr_status run_field(fvr_ctx *c, const fvr_frame *f, Plan *p, const Grid &g0, fl
         HIP_TRY(c, launch_fft_yx_inv(sp, field, P<float2>(c->rowmm), st, g, p->ax[1], s), "fft_yx_inv");
     } else {
         { Timed t(c, K_FFT_Y_INV); HIP_TRY(c, launch_fft_y_inv(sp, g, p->ax[1], s), "fft_y_inv"); }
-        { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, st, g, p->ax[0], s), "fft_x_c2r"); }
+        { Timed t(c, K_FFT_X_C2R); HIP_TRY(c, launch_fft_x_c2r(sp, field, P<float2>(c->rowmm), st, g, p->ax[0], s), "fft_x_c2r"); }
     }
     return FVR_OK;
 }
@@ -653,14 +653,12 @@ fvr_status enqueue_reconstruct(fvr_ctx *c, const fvr_frame *f, Plan *p, const fv
     fvr_status r;
     GET(c, c->field, sizeof(float) * (size_t)g.n[0] * g.n[1] * g.n[2], "field");
     if ((r = run_field(c, f, p, g, P<float>(c->field), nullptr, false)) != FVR_OK) return r;
-    // the fused inverse pass left each row's range of A: blocks of cells
+    // the last inverse pass left each row's range of A: blocks of cells
     // entirely on one side of the level skip the field, and their
     // classification also finishes the level
-    const bool fused = fft_yx_fused(g);
     const int level_nb = level_blocks((int)f->n_points);
-    if ((r = run_level(c, f, g, P<float>(c->field), !fused || level_nb == 0)) != FVR_OK) return r;
-    return enqueue_mc(c, g, P<float>(c->field), fused ? P<float2>(c->rowmm) : nullptr, mesh, nullptr, true,
-                      fused ? level_nb : 0, host_dst);
+    if ((r = run_level(c, f, g, P<float>(c->field), level_nb == 0)) != FVR_OK) return r;
+    return enqueue_mc(c, g, P<float>(c->field), P<float2>(c->rowmm), mesh, nullptr, true, level_nb, host_dst);
 }
 
 // Every device buffer a context owns.
@@ -685,7 +683,7 @@ fvr_status frame_bufs(fvr_ctx *c, const fvr_frame *f, const Plan *p, const fvr_m
     fvr_status r;
     if ((r = field_bufs(c, g, p, m)) != FVR_OK) return r;
     if ((r = level_bufs(c, m)) != FVR_OK) return r;
-    return mc_bufs(c, g, mesh_caps(g, mesh, true), fft_yx_fused(g));
+    return mc_bufs(c, g, mesh_caps(g, mesh, true), true);
 }
 
 }  // namespace

@@ -211,11 +211,13 @@ hipError_t launch_fft_y_inv(void *spec, const Grid &g, const FftAxis &ay, hipStr
 bool fft_yx_fused(const Grid &g);
 hipError_t launch_fft_yx_inv(const void *spec, float *A, float2 *rowmm, DevStatus *st, const Grid &g,
                              const FftAxis &ay, hipStream_t s);
-// Inverse real FFT along x of plane 0, scaled by g.iscale -> A (Nz, Ny, Nx).
-// With a 16-bit spectrum storage both inverse kernels set kFlagRange in st
-// when they write a non-finite value (an overflowed store upstream).
-hipError_t launch_fft_x_c2r(const void *spec, float *A, DevStatus *st, const Grid &g, const FftAxis &ax,
-                            hipStream_t s);
+// Inverse real FFT along x of plane 0, scaled by g.iscale -> A (Nz, Ny, Nx);
+// rowmm[z Ny + y] receives (min, max) of A over the row, as the fused pass
+// writes it.  With a 16-bit spectrum storage both inverse kernels set
+// kFlagRange in st when they write a non-finite value (an overflowed store
+// upstream).
+hipError_t launch_fft_x_c2r(const void *spec, float *A, float2 *rowmm, DevStatus *st, const Grid &g,
+                            const FftAxis &ax, hipStream_t s);
 
 // Iso-level: per-block double partial sums of trilinear A at accepted points,
 // then (final) one block reduces them in a fixed order into st->level,

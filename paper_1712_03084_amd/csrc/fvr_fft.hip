@@ -221,8 +221,8 @@ fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
 // (Hermitian symmetry of a real row's spectrum); the imaginary parts of the
 // k = 0 and k = Nx/2 bins are dropped, as a real row's spectrum has none.
 __global__ void __launch_bounds__(kPassThreads)
-fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g, FftAxis ax,
-                 float scale) {
+fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm, Grid g,
+                 FftAxis ax, float scale) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
     const int Nx = g.n[0], Hp = g.Hp;
     const int nrows = g.n[1] * g.n[2];
@@ -272,6 +272,29 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, Grid g,
             const float2 z = lds[i];
             A[(size_t)ra * Nx + k] = z.x * scale;
             A[(size_t)(ra + 1) * Nx + k] = z.y * scale;
+        }
+    }
+    // (min, max) of each real row as stored, one wave per complex row
+    const int lane = threadIdx.x & 63;
+    for (int jr = threadIdx.x >> 6; jr < ncx; jr += blockDim.x >> 6) {
+        const int ra = row0 + 2 * jr;
+        if (ra >= nrows) break;  // uniform across the wave
+        float4 mm = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        for (int k = lane; k < Nx; k += 64) {
+            const float2 z = lds[jr * Nx + k];
+            const float va = z.x * scale, vb = z.y * scale;
+            mm = make_float4(fminf(mm.x, va), fmaxf(mm.y, va), fminf(mm.z, vb), fmaxf(mm.w, vb));
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            mm.x = fminf(mm.x, __shfl_xor(mm.x, d, 64));
+            mm.y = fmaxf(mm.y, __shfl_xor(mm.y, d, 64));
+            mm.z = fminf(mm.z, __shfl_xor(mm.z, d, 64));
+            mm.w = fmaxf(mm.w, __shfl_xor(mm.w, d, 64));
+        }
+        if (lane == 0) {
+            rowmm[ra] = make_float2(mm.x, mm.y);
+            rowmm[ra + 1] = make_float2(mm.z, mm.w);
         }
     }
 }
@@ -566,8 +589,8 @@ pen_y_inv_kernel(void *__restrict__ spec, Grid g, const float2 *__restrict__ twg
 // 16-byte stores.
 template <int N1, int N2, int ST>
 __global__ void __launch_bounds__(16 * N2)
-pen_x_c2r_kernel(const void *__restrict__ spec, float *__restrict__ A, DevStatus *__restrict__ st, Grid g,
-                 const float2 *__restrict__ twg, float scale) {
+pen_x_c2r_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm,
+                 DevStatus *__restrict__ st, Grid g, const float2 *__restrict__ twg, float scale) {
     using Pn = Pencil<N1, N2>;
     constexpr int N = Pn::N;  // = Nx
     constexpr int ZP = N + 1;       // LDS pitch of a packed complex row (float2)
@@ -615,11 +638,20 @@ pen_x_c2r_kernel(const void *__restrict__ spec, float *__restrict__ A, DevStatus
         if (bad) atomicOr(&st->flags, kFlagRange);
     __syncthreads();
     constexpr int Q4 = N / 4;  // float4 per real row
+    // a row's Q4 float4 lie on consecutive lanes of one wave (Q4 divides 64
+    // and the thread count): their (min, max) reduces over those lanes
+    static_assert(64 % Q4 == 0 && Pn::THREADS % 64 == 0, "rows within a wave");
     for (int i = threadIdx.x; i < 32 * Q4; i += Pn::THREADS) {
         const int r = i / Q4, q = i - r * Q4;
-        if (row0 + r < nrows)
-            *reinterpret_cast<float4 *>(A + (size_t)(row0 + r) * N + 4 * q) =
-                *reinterpret_cast<const float4 *>(ob + r * OP + 4 * q);
+        const float4 v = *reinterpret_cast<const float4 *>(ob + r * OP + 4 * q);
+        if (row0 + r < nrows) *reinterpret_cast<float4 *>(A + (size_t)(row0 + r) * N + 4 * q) = v;
+        float mn = fminf(fminf(v.x, v.y), fminf(v.z, v.w)), mx = fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w));
+#pragma unroll
+        for (int d = Q4 / 2; d > 0; d >>= 1) {
+            mn = fminf(mn, __shfl_xor(mn, d, 64));
+            mx = fmaxf(mx, __shfl_xor(mx, d, 64));
+        }
+        if (q == 0 && row0 + r < nrows) rowmm[row0 + r] = make_float2(mn, mx);
     }
 }
 
@@ -913,21 +945,21 @@ hipError_t launch_fft_yx_inv(const void *spec, float *A, float2 *rowmm, DevStatu
     return hipGetLastError();
 }
 
-hipError_t launch_fft_x_c2r(const void *spec, float *A, DevStatus *st, const Grid &g, const FftAxis &ax,
-                            hipStream_t s) {
+hipError_t launch_fft_x_c2r(const void *spec, float *A, float2 *rowmm, DevStatus *st, const Grid &g,
+                            const FftAxis &ax, hipStream_t s) {
     const int nrows = g.n[1] * g.n[2];
     if (const int pc = pencil_code(g.n[0])) {
         const float scale = g.spec_st == kSpecF32 ? 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2])
                                                   : g.iscale;
-        FVR_PEN_ST(pc, pen_x_c2r_kernel, (spec, A, st, g, ax.tw, scale), dim3((nrows + 31) / 32))
+        FVR_PEN_ST(pc, pen_x_c2r_kernel, (spec, A, rowmm, st, g, ax.tw, scale), dim3((nrows + 31) / 32))
         return hipGetLastError();
     }
     if (g.spec_st != kSpecF32) return hipErrorInvalidValue;
     const int blocks = (nrows + kC2rRows - 1) / kC2rRows;
     const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
     const size_t lds = ((size_t)(kC2rRows / 2) * g.n[0] + g.n[0]) * sizeof(float2);
-    fft_x_c2r_kernel<<<dim3(blocks), dim3(kPassThreads), lds, s>>>(static_cast<const float2 *>(spec), A, g, ax,
-                                                                  scale);
+    fft_x_c2r_kernel<<<dim3(blocks), dim3(kPassThreads), lds, s>>>(static_cast<const float2 *>(spec), A, rowmm, g,
+                                                                  ax, scale);
     return hipGetLastError();
 }
 

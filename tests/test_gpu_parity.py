@@ -331,6 +331,37 @@ def test_fused_inverse_on_a_256x256x96_grid(ctx):
     assert full.open_surface == mesh.open_surface
 
 
+@pytest.mark.parametrize("dims", [(128, 128, 128), (64, 64, 48), (96, 160, 192), (160, 96, 64)])
+def test_row_range_skip_after_unfused_inverse_passes(ctx, dims):
+    """Grids other than N_x = N_y = 256 run the inverse y and x passes apart
+    (register pencils on power-of-two lengths, mixed-radix passes on the
+    others); the x pass leaves the row ranges of A for the marching-cubes
+    block list: the mesh must equal the full classification of the same
+    field."""
+    half = tuple(0.5 * d / 64.0 for d in dims)
+    f = _random_frame(30 + dims[0] + dims[2], 80_000, dims, tuple(-h for h in half) + half)
+    print(f"[skip] random frame {dims}", flush=True)
+    dev = _frame_dev(f)
+    A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
+    mesh = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox)
+    full = ctx.extract(A, f.bbox, L)
+    assert mesh.vertices.shape[0] > 0
+    assert torch.equal(full.vertices, mesh.vertices) and torch.equal(full.triangles, mesh.triangles)
+    assert full.open_surface == mesh.open_surface and mesh.level == L
+
+
+def test_row_range_skip_on_an_open_surface_128(ctx):
+    """The open-surface flag from blocks settled by row ranges, on the
+    unfused inverse passes."""
+    f = synth.sphere_frame(seed=5, m=100_000, grid=128, half_extent=0.7)
+    dev = _frame_dev(f)
+    A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
+    mesh = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox)
+    full = ctx.extract(A, f.bbox, L)
+    assert mesh.open_surface and full.open_surface
+    assert torch.equal(full.vertices, mesh.vertices) and torch.equal(full.triangles, mesh.triangles)
+
+
 def test_empty_and_all_rejected(ctx):
     z = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
     mesh = ctx.reconstruct(z, z, None, grid_dim=(16, 16, 16), bbox=(-1, -1, -1, 1, 1, 1))

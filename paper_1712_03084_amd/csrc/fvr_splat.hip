@@ -277,6 +277,49 @@ bin_scatter_kernel(const float *__restrict__ pts, const float *__restrict__ nrm,
                                    ldexpf(wi * nrm[3 * i + 2], sn), __int_as_float(ix));
 }
 
+// Forward transform along x of the tile's ncx complex rows of length
+// N = 16 P in LDS (split complex: row j's real parts at S[2 N j + e], its
+// imaginary parts N floats later), for the register-pencil lengths.  Four
+// steps on N = P x 16: lane n2 of a row takes x[16 n1 + n2] over n1, a
+// length-P DFT, and the twiddles w_N^(n2 k1); the values go through the
+// exchange area X (pitch P + 1: both of its accesses are conflict-free);
+// lane k1 then takes a length-16 DFT over n2, giving X[k1 + P k2].  All
+// index arithmetic is shifts and masks; the transformed rows replace the
+// input in S.  Synchronises on entry and on return.
+template <int P>
+__device__ __forceinline__ void splat_rows_fft16(float *__restrict__ S, float2 *__restrict__ X, int ncx,
+                                                 const float2 *__restrict__ twl) {
+    constexpr int N = 16 * P;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ncx * 16; i += blockDim.x) {
+        const int j = i >> 4, n2 = i & 15;
+        const float *re = S + 2 * N * j, *im = re + N;
+        float2 v[P];
+#pragma unroll
+        for (int n1 = 0; n1 < P; ++n1) v[n1] = make_float2(re[16 * n1 + n2], im[16 * n1 + n2]);
+        if constexpr (P > 1) Dft<P>::run(v, -1);
+        float2 *x = X + (16 * j + n2) * (P + 1);
+        x[0] = v[0];
+#pragma unroll
+        for (int k1 = 1; k1 < P; ++k1) x[k1] = cmul(v[k1], twl[n2 * k1]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ncx * P; i += blockDim.x) {
+        const int j = i / P, k1 = i % P;
+        float2 v[16];
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) v[n2] = X[(16 * j + n2) * (P + 1) + k1];
+        Dft<16>::run(v, -1);
+        float *re = S + 2 * N * j, *im = re + N;
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) {
+            re[k1 + P * k2] = v[k2].x;
+            im[k1 + P * k2] = v[k2].y;
+        }
+    }
+    __syncthreads();
+}
+
 // Accumulation is in 64-bit fixed point with integer LDS atomics (gfx950's
 // LDS float atomics run ~30x slower than its integer ones, and integer sums
 // do not depend on the order of the additions).  The unit of a tile is
@@ -600,9 +643,20 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     // Real FFT along x: real rows (2j, 2j+1) of the flat (channel, row) order
     // - always the same channel since R is even - form complex row j.
     const int ncx = 3 * R / 2;
-    // at most 1.5 kSplatMaxPlane elements over kSplatThreads threads
-    fft_rows<false, (3 * kSplatMaxPlane / 2 + kSplatThreads - 1) / kSplatThreads>(RowsS{S, 2 * Nx, Nx}, ncx,
-                                                                                  ax, twl, -1);
+    // the exchange area of the pencil lengths follows the rows (it fits in the
+    // accumulator's space: 24 R Nx + 192 R bytes against 32 R (Nx + 5))
+    float2 *xa = reinterpret_cast<float2 *>(S + 3 * plane);
+    switch (Nx) {
+        case 256: splat_rows_fft16<16>(S, xa, ncx, twl); break;
+        case 128: splat_rows_fft16<8>(S, xa, ncx, twl); break;
+        case 64: splat_rows_fft16<4>(S, xa, ncx, twl); break;
+        case 32: splat_rows_fft16<2>(S, xa, ncx, twl); break;
+        case 16: splat_rows_fft16<1>(S, xa, ncx, twl); break;
+        default:
+            // at most 1.5 kSplatMaxPlane elements over kSplatThreads threads
+            fft_rows<false, (3 * kSplatMaxPlane / 2 + kSplatThreads - 1) / kSplatThreads>(RowsS{S, 2 * Nx, Nx},
+                                                                                          ncx, ax, twl, -1);
+    }
 
     // Unpack X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = (Z[k] - conj Z[N-k]) / 2i,
     // k = 0..Nx/2, and store; the x component is multiplied by j w_x.

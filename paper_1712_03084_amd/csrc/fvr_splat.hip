@@ -88,6 +88,14 @@ __device__ __forceinline__ int nearest_voxel(float x, float bmin, float h, int n
     return min(max(i, 0), n - 1);
 }
 
+// An int64 to float via double: hi 2^32 + lo is exact in double while |x| <
+// 2^53 and is then rounded once (a few instructions against the long
+// integer sequence of a direct int64 to float conversion).
+__device__ __forceinline__ float i64_to_float(long long x) {
+    const double hi = (double)(int)(x >> 32), lo = (double)(unsigned)(x & 0xffffffffll);
+    return (float)fma(hi, 4294967296.0, lo);
+}
+
 __device__ __forceinline__ bool finite3(float a, float b, float c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
@@ -609,10 +617,13 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
             const int row = l / Nx, la = l + 5 * row + 2;  // padded accumulator index
             const long long d = (long long)acc[3 * aplane + la];
             if (d > 0) {
-                const float inv = ratio / (float)d;
-                vv[t][0] = (float)(long long)acc[la] * inv;
-                vv[t][1] = (float)(long long)acc[aplane + la] * inv;
-                vv[t][2] = (float)(long long)acc[2 * aplane + la] * inv;
+                // the sums to float through double (two 32-bit conversions, a
+                // scale and an add; exact below 2^53, one rounding to float),
+                // and v_rcp_f32 (about 1 ulp) in place of a divide
+                const float inv = ratio * __builtin_amdgcn_rcpf(i64_to_float(d));
+                vv[t][0] = i64_to_float((long long)acc[la]) * inv;
+                vv[t][1] = i64_to_float((long long)acc[aplane + la]) * inv;
+                vv[t][2] = i64_to_float((long long)acc[2 * aplane + la]) * inv;
             }
         }
     }
@@ -660,39 +671,51 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
 
     // Unpack X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = (Z[k] - conj Z[N-k]) / 2i,
     // k = 0..Nx/2, and store; the x component is multiplied by j w_x.
-    const unsigned mH = div_magic(H);
-    for (int i = threadIdx.x; i < ncx * H; i += blockDim.x) {
-        const int jr = udiv(i, H, mH), kx = i - jr * H;
-        const float *re = S + 2 * jr * Nx, *im = re + Nx;
-        const int km = kx == 0 ? 0 : Nx - kx;
-        const float zr = re[kx], zi = im[kx];
-        const float mr = re[km], mi = im[km];
-        float2 xa = make_float2(0.5f * (zr + mr), 0.5f * (zi - mi));
-        float2 xb = make_float2(0.5f * (zi + mi), 0.5f * (mr - zr));
+    // Work in wave-sized chunks of one complex row: chunk q of row jr holds
+    // kx = 64 q + lane (kx < Nx/2; dims are even), and lane 0 of chunk 0 also
+    // the Nyquist bin kx = Nx/2.  The row's channel and tile rows are
+    // wave-uniform: readfirstlane makes them scalar.
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int half = Nx / 2, nkc = (half + 63) >> 6;
+    for (int it = threadIdx.x >> 6; it < ncx * nkc; it += nw) {
+        const int itu = __builtin_amdgcn_readfirstlane(it);
+        const int jr = itu / nkc, q = itu - jr * nkc;
         const int ra = (2 * jr) % R, c = (2 * jr) / R;
-        if (c == 0) {
-            const float wx = deriv_w(kx, Nx, g.wstep[0]);
-            xa = make_float2(-wx * xa.y, wx * xa.x);
-            xb = make_float2(-wx * xb.y, wx * xb.x);
-        }
         const int ya = y0 + ra % TY, za = z0 + ra / TY;
         const int yb = y0 + (ra + 1) % TY, zb = z0 + (ra + 1) / TY;
-        const size_t ia = c * pl + ((size_t)za * Ny + ya) * Hp + kx;
-        const size_t ib = c * pl + ((size_t)zb * Ny + yb) * Hp + kx;
-        if (g.spec_st == kSpecF32) {
-            if (ya < Ny && za < Nz) spec_st<kSpecF32>(spec, ia, xa);
-            if (yb < Ny && zb < Nz) spec_st<kSpecF32>(spec, ib, xb);
-        } else {
-            // the reduced storages keep the x share of the inverse's 1/n
-            const float sx = g.fscale[0];
-            xa = make_float2(xa.x * sx, xa.y * sx);
-            xb = make_float2(xb.x * sx, xb.y * sx);
-            if (g.spec_st == kSpecBF16) {
-                if (ya < Ny && za < Nz) spec_st<kSpecBF16>(spec, ia, xa);
-                if (yb < Ny && zb < Nz) spec_st<kSpecBF16>(spec, ib, xb);
+        const bool oka = ya < Ny && za < Nz, okb = yb < Ny && zb < Nz;
+        const size_t ba = c * pl + ((size_t)za * Ny + ya) * Hp, bb = c * pl + ((size_t)zb * Ny + yb) * Hp;
+        const float *re = S + 2 * jr * Nx, *im = re + Nx;
+        const int k0 = 64 * q + lane;
+        const int nk = (q == 0 && lane == 0) ? 2 : (k0 < half ? 1 : 0);
+        for (int u = 0; u < nk; ++u) {
+            const int kx = u ? half : k0;
+            const int km = kx == 0 ? 0 : Nx - kx;
+            const float zr = re[kx], zi = im[kx];
+            const float mr = re[km], mi = im[km];
+            float2 xa = make_float2(0.5f * (zr + mr), 0.5f * (zi - mi));
+            float2 xb = make_float2(0.5f * (zi + mi), 0.5f * (mr - zr));
+            if (c == 0) {
+                const float wx = deriv_w(kx, Nx, g.wstep[0]);
+                xa = make_float2(-wx * xa.y, wx * xa.x);
+                xb = make_float2(-wx * xb.y, wx * xb.x);
+            }
+            const size_t ia = ba + kx, ib = bb + kx;
+            if (g.spec_st == kSpecF32) {
+                if (oka) spec_st<kSpecF32>(spec, ia, xa);
+                if (okb) spec_st<kSpecF32>(spec, ib, xb);
             } else {
-                if (ya < Ny && za < Nz) spec_st<kSpecF16>(spec, ia, xa);
-                if (yb < Ny && zb < Nz) spec_st<kSpecF16>(spec, ib, xb);
+                // the reduced storages keep the x share of the inverse's 1/n
+                const float sx = g.fscale[0];
+                xa = make_float2(xa.x * sx, xa.y * sx);
+                xb = make_float2(xb.x * sx, xb.y * sx);
+                if (g.spec_st == kSpecBF16) {
+                    if (oka) spec_st<kSpecBF16>(spec, ia, xa);
+                    if (okb) spec_st<kSpecBF16>(spec, ib, xb);
+                } else {
+                    if (oka) spec_st<kSpecF16>(spec, ia, xa);
+                    if (okb) spec_st<kSpecF16>(spec, ib, xb);
+                }
             }
         }
     }

@@ -671,51 +671,39 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
 
     // Unpack X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = (Z[k] - conj Z[N-k]) / 2i,
     // k = 0..Nx/2, and store; the x component is multiplied by j w_x.
-    // Work in wave-sized chunks of one complex row: chunk q of row jr holds
-    // kx = 64 q + lane (kx < Nx/2; dims are even), and lane 0 of chunk 0 also
-    // the Nyquist bin kx = Nx/2.  The row's channel and tile rows are
-    // wave-uniform: readfirstlane makes them scalar.
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    const int half = Nx / 2, nkc = (half + 63) >> 6;
-    for (int it = threadIdx.x >> 6; it < ncx * nkc; it += nw) {
-        const int itu = __builtin_amdgcn_readfirstlane(it);
-        const int jr = itu / nkc, q = itu - jr * nkc;
+    const unsigned mH = div_magic(H);
+    for (int i = threadIdx.x; i < ncx * H; i += blockDim.x) {
+        const int jr = udiv(i, H, mH), kx = i - jr * H;
+        const float *re = S + 2 * jr * Nx, *im = re + Nx;
+        const int km = kx == 0 ? 0 : Nx - kx;
+        const float zr = re[kx], zi = im[kx];
+        const float mr = re[km], mi = im[km];
+        float2 xa = make_float2(0.5f * (zr + mr), 0.5f * (zi - mi));
+        float2 xb = make_float2(0.5f * (zi + mi), 0.5f * (mr - zr));
         const int ra = (2 * jr) % R, c = (2 * jr) / R;
+        if (c == 0) {
+            const float wx = deriv_w(kx, Nx, g.wstep[0]);
+            xa = make_float2(-wx * xa.y, wx * xa.x);
+            xb = make_float2(-wx * xb.y, wx * xb.x);
+        }
         const int ya = y0 + ra % TY, za = z0 + ra / TY;
         const int yb = y0 + (ra + 1) % TY, zb = z0 + (ra + 1) / TY;
-        const bool oka = ya < Ny && za < Nz, okb = yb < Ny && zb < Nz;
-        const size_t ba = c * pl + ((size_t)za * Ny + ya) * Hp, bb = c * pl + ((size_t)zb * Ny + yb) * Hp;
-        const float *re = S + 2 * jr * Nx, *im = re + Nx;
-        const int k0 = 64 * q + lane;
-        const int nk = (q == 0 && lane == 0) ? 2 : (k0 < half ? 1 : 0);
-        for (int u = 0; u < nk; ++u) {
-            const int kx = u ? half : k0;
-            const int km = kx == 0 ? 0 : Nx - kx;
-            const float zr = re[kx], zi = im[kx];
-            const float mr = re[km], mi = im[km];
-            float2 xa = make_float2(0.5f * (zr + mr), 0.5f * (zi - mi));
-            float2 xb = make_float2(0.5f * (zi + mi), 0.5f * (mr - zr));
-            if (c == 0) {
-                const float wx = deriv_w(kx, Nx, g.wstep[0]);
-                xa = make_float2(-wx * xa.y, wx * xa.x);
-                xb = make_float2(-wx * xb.y, wx * xb.x);
-            }
-            const size_t ia = ba + kx, ib = bb + kx;
-            if (g.spec_st == kSpecF32) {
-                if (oka) spec_st<kSpecF32>(spec, ia, xa);
-                if (okb) spec_st<kSpecF32>(spec, ib, xb);
+        const size_t ia = c * pl + ((size_t)za * Ny + ya) * Hp + kx;
+        const size_t ib = c * pl + ((size_t)zb * Ny + yb) * Hp + kx;
+        if (g.spec_st == kSpecF32) {
+            if (ya < Ny && za < Nz) spec_st<kSpecF32>(spec, ia, xa);
+            if (yb < Ny && zb < Nz) spec_st<kSpecF32>(spec, ib, xb);
+        } else {
+            // the reduced storages keep the x share of the inverse's 1/n
+            const float sx = g.fscale[0];
+            xa = make_float2(xa.x * sx, xa.y * sx);
+            xb = make_float2(xb.x * sx, xb.y * sx);
+            if (g.spec_st == kSpecBF16) {
+                if (ya < Ny && za < Nz) spec_st<kSpecBF16>(spec, ia, xa);
+                if (yb < Ny && zb < Nz) spec_st<kSpecBF16>(spec, ib, xb);
             } else {
-                // the reduced storages keep the x share of the inverse's 1/n
-                const float sx = g.fscale[0];
-                xa = make_float2(xa.x * sx, xa.y * sx);
-                xb = make_float2(xb.x * sx, xb.y * sx);
-                if (g.spec_st == kSpecBF16) {
-                    if (oka) spec_st<kSpecBF16>(spec, ia, xa);
-                    if (okb) spec_st<kSpecBF16>(spec, ib, xb);
-                } else {
-                    if (oka) spec_st<kSpecF16>(spec, ia, xa);
-                    if (okb) spec_st<kSpecF16>(spec, ib, xb);
-                }
+                if (ya < Ny && za < Nz) spec_st<kSpecF16>(spec, ia, xa);
+                if (yb < Ny && zb < Nz) spec_st<kSpecF16>(spec, ib, xb);
             }
         }
     }
@@ -768,7 +756,9 @@ hipError_t launch_bin_scatter(const float *pts, const float *nrm, const float *w
     return hipGetLastError();
 }
 
-// One thread per splat tile: the point-rows that fall into it (each point of
+constexpr int kTileLanes = 8;  // lanes per tile in tile_list
+
+// Per splat tile (kTileLanes lanes): the point-rows that fall into it (each point of
 // bin (iy, iz) adds one item row per tile row within its footprint rows
 // iy - 1 .. iy + 2, iz - 1 .. iz + 2).  Busy tiles get occ = 1 and an entry
 // (tile, cost) in `pend`, in no particular order.  Block b < nscan also sums
@@ -778,7 +768,10 @@ tile_list_kernel(const int32_t *__restrict__ bin_count, int nbins, int nscan,
                  int32_t *__restrict__ partial, Grid g, SplatConsts sc, int ntiles,
                  uint8_t *__restrict__ occ, int2 *__restrict__ pend, DevStatus *st) {
     if ((int)blockIdx.x < nscan) scan_tile_sum<1>(bin_count, nbins, blockIdx.x, partial);
-    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    // kTileLanes lanes per tile, lane r on the tile's origin rows iz_lo + r,
+    // iz_lo + r + kTileLanes, ...; their sums meet by shuffles
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tile = gt / kTileLanes, r = gt % kTileLanes;
     long long cost = 0;
     if (tile < ntiles) {
         const int Ny = g.n[1], Nz = g.n[2];
@@ -789,7 +782,7 @@ tile_list_kernel(const int32_t *__restrict__ bin_count, int nbins, int nscan,
         const int iz_lo = max(z0 - hi, -1), iz_hi = min(z0 + sc.tz - 1 - lo, Nz - 1);
         const int iy_lo = max(y0 - hi, -1), iy_hi = min(y0 + sc.ty - 1 - lo, Ny - 1);
         // the loads of a bin row are independent: unrolled, they are in flight together
-        for (int iz = iz_lo; iz <= iz_hi; ++iz) {
+        for (int iz = iz_lo + r; iz <= iz_hi; iz += kTileLanes) {
             const int nz = min(iz + hi, z1) - max(iz + lo, z0) + 1;
             const int row = (iz + 1) * (Ny + 1) + 1;
             long long sum = 0;
@@ -798,9 +791,11 @@ tile_list_kernel(const int32_t *__restrict__ bin_count, int nbins, int nscan,
                 sum += (long long)bin_count[row + iy] * max(min(iy + hi, y1) - max(iy + lo, y0) + 1, 0);
             cost += max(nz, 0) * sum;
         }
-        occ[tile] = cost > 0 ? 1 : 0;
     }
-    const bool busy = cost > 0;
+#pragma unroll
+    for (int d = kTileLanes / 2; d > 0; d >>= 1) cost += __shfl_xor(cost, d, kTileLanes);
+    if (tile < ntiles && r == 0) occ[tile] = cost > 0 ? 1 : 0;
+    const bool busy = tile < ntiles && r == 0 && cost > 0;
     // one list append per wave
     const unsigned long long b = __ballot(busy);
     const int lane = threadIdx.x & 63;
@@ -903,7 +898,7 @@ hipError_t launch_tile_list(const int32_t *bin_count, int32_t *bin_off, int nbin
                             int32_t *list, const uint2 *blk_max, int m, DevStatus *st, hipStream_t s) {
     const int ntiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     const int nscan = scan_tiles(nbins);
-    const int blocks = std::max((ntiles + 255) / 256, nscan);
+    const int blocks = std::max((ntiles * kTileLanes + 255) / 256, nscan);
     tile_list_kernel<<<dim3(blocks), dim3(256), 0, s>>>(bin_count, nbins, nscan, partial, g, sc, ntiles,
                                                        occ, pend, st);
     hipError_t e = hipGetLastError();

@@ -40,10 +40,12 @@ LOG2E = 1.4426950408889634
 
 
 def _tile_shape(nx):
-    r = 64
+    """The kernel's default splat tile: 2 x 2 rows up to N_x = 128, 2 x 4
+    above, within 2048 voxels per channel plane."""
+    r = 4 if nx <= 128 else 8
     while r > 4 and r * nx > 2048:
         r //= 2
-    tz = 8 if r >= 32 else 4 if r >= 8 else 2
+    tz = 4 if r >= 8 else 2
     return r // tz, tz
 
 

@@ -815,6 +815,131 @@ yx_inv256_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *_
 
 size_t yx_inv256_lds() { return (size_t)(kYxBuf + 2 * kYx) * sizeof(float2) + 256 * sizeof(float4); }
 
+// Both inverse passes for Nx = Ny = 128: two 512-thread blocks per z plane,
+// block (z, h) writing rows y = 64 h .. 64 h + 63 of A (two blocks per plane
+// keep the whole chip busy at 128 planes; each runs the plane's y inverse,
+// a few MB of extra reads at 128^3).  Four groups of 128 threads run the
+// 16 x 8 register pencil along y on column chunks kx = 16 q + c (kx < 64);
+// the kx = 0 and kx = 64 columns share one transform (Z = X_0 + i X_64, as in
+// the 256 kernel).  The half's y-inverse rows go to LDS, pairs of real rows
+// are packed as complex rows and transformed along x with the same pencil,
+// and the rows leave through LDS as 16-byte stores with their (min, max).
+constexpr int kYh = 128;
+constexpr int kYhThreads = 512;
+using PenYh = Pencil<16, 8>;
+constexpr int kYhYP = kYh / 2 + 1;     // LDS pitch of a y-inverse row (complex)
+constexpr int kYhOP = kYh + 4;         // LDS pitch of a real output row (float)
+constexpr int kYhBuf = 4 * PenYh::EX;  // float2: four exchange buffers
+static_assert(kYhBuf >= (kYh / 2) * kYhYP, "half plane of y-inverse rows fits");
+static_assert(2 * kYhBuf >= (kYh / 2) * kYhOP, "half plane of output rows fits");
+static_assert(PenYh::THREADS * 4 == kYhThreads, "four groups");
+
+template <int ST>
+__global__ void __launch_bounds__(kYhThreads)
+yx_inv128_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm,
+                 DevStatus *__restrict__ st, Grid g, const float2 *__restrict__ twg, float scale) {
+    using Pn = PenYh;
+    constexpr int N = kYh;
+    extern __shared__ __attribute__((aligned(16))) float2 smem[];
+    float2 *buf = smem;           // exchange buffers / y-inverse rows / output rows
+    float2 *tw = smem + kYhBuf;   // w_128^m (the same table serves x and y)
+    float2 *nyq = tw + N;         // the Nyquist column kx = 64
+    const int grp = threadIdx.x >> 7, lt = threadIdx.x & 127;
+    const int c = lt & 15, t = lt >> 4;
+    const int z = blockIdx.x >> 1, h = blockIdx.x & 1, Hp = g.Hp;
+    const size_t P = (size_t)z * N * Hp;  // the plane's first bin
+    float2 *ex = buf + grp * Pn::EX;
+    if (threadIdx.x < N) {
+        tw[threadIdx.x] = twg[threadIdx.x];
+        nyq[threadIdx.x] = spec_ld<ST>(spec, P + (size_t)threadIdx.x * Hp + N / 2);
+    }
+    const int kx = 16 * grp + c;
+    float2 a[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) a[n1] = spec_ld<ST>(spec, P + (size_t)Pn::in_row(t, n1) * Hp + kx);
+    __syncthreads();  // twiddles and the Nyquist column
+    if (kx == 0) {
+        // column 0 carries the Nyquist column in its imaginary part
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const float2 w = nyq[Pn::in_row(t, n1)];
+            a[n1] = make_float2(a[n1].x - w.y, a[n1].y + w.x);
+        }
+    }
+    Pn::template run<+1>(a, ex, tw, c, t);
+    // this half's y-inverse rows to LDS (the exchange buffers are free)
+    float2 *Y = buf;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = Pn::out_row(t, i);
+        if ((r >> 6) == h) {
+            const int rr = r & 63;
+            if (kx == 0) {
+                Y[rr * kYhYP] = make_float2(a[i].x, 0.f);
+                Y[rr * kYhYP + N / 2] = make_float2(a[i].y, 0.f);
+            } else {
+                Y[rr * kYhYP + kx] = a[i];
+            }
+        }
+    }
+    __syncthreads();
+    // groups 0 and 1 pack real rows (2p, 2p + 1), p = 16 grp + c, of the half
+    // as Z[k] = X_a[k] + i X_b[k] over the full length; groups 2 and 3 run the
+    // transform on zeros (its barriers are the block's)
+    const int p = 16 * grp + c, ra = 2 * p, rb = ra + 1;
+    float2 x[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+        x[n1] = make_float2(0.f, 0.f);
+        if (p < 32) {
+            const int k = Pn::in_row(t, n1);
+            const int kk = k <= N / 2 ? k : N - k;
+            float2 xa = Y[ra * kYhYP + kk], xb = Y[rb * kYhYP + kk];
+            if (kk == 0 || kk == N / 2) {
+                xa.y = 0.f;
+                xb.y = 0.f;
+            }
+            x[n1] = k <= N / 2 ? make_float2(xa.x - xb.y, xa.y + xb.x) : make_float2(xa.x + xb.y, xb.x - xa.y);
+        }
+    }
+    __syncthreads();  // the rows are read: buf becomes the exchange buffers
+    Pn::template run<+1>(x, ex, tw, c, t);
+    float *O = reinterpret_cast<float *>(buf);
+    bool bad = false;
+    if (p < 32) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int k = Pn::out_row(t, i);
+            O[ra * kYhOP + k] = x[i].x * scale;
+            O[rb * kYhOP + k] = x[i].y * scale;
+            if constexpr (ST != kSpecF32) bad |= !__builtin_isfinite(x[i].x) || !__builtin_isfinite(x[i].y);
+        }
+    }
+    if constexpr (ST != kSpecF32)
+        if (bad) atomicOr(&st->flags, kFlagRange);
+    __syncthreads();
+    // 64 rows of 32 float4: 32 lanes per row, two rows per wave; each row's
+    // (min, max) reduces over its lanes
+    constexpr int Q4 = N / 4;
+    static_assert((64 * Q4) % kYhThreads == 0 && Q4 == 32, "whole rows per wave");
+    float *dst = A + ((size_t)z * N + 64 * h) * N;
+#pragma unroll
+    for (int i = threadIdx.x; i < 64 * Q4; i += kYhThreads) {
+        const int r = i / Q4, q = i - r * Q4;
+        const float4 v = *reinterpret_cast<const float4 *>(O + r * kYhOP + 4 * q);
+        *reinterpret_cast<float4 *>(dst + (size_t)r * N + 4 * q) = v;
+        float mn = fminf(fminf(v.x, v.y), fminf(v.z, v.w)), mx = fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w));
+#pragma unroll
+        for (int d = 16; d > 0; d >>= 1) {
+            mn = fminf(mn, __shfl_xor(mn, d, 32));
+            mx = fmaxf(mx, __shfl_xor(mx, d, 32));
+        }
+        if (q == 0) rowmm[(size_t)z * N + 64 * h + r] = make_float2(mn, mx);
+    }
+}
+
+size_t yx_inv128_lds() { return (size_t)(kYhBuf + 2 * kYh) * sizeof(float2); }
+
 static int pencil_code(int n) {
     switch (n) {
         case 16: return 44;
@@ -866,7 +991,9 @@ hipError_t fft_configure() {
                        (const void *)fft_y_inv_kernel<2>,   (const void *)fft_y_inv_kernel<4>,
                        (const void *)fft_y_inv_kernel<8>,   (const void *)fft_y_inv_kernel<16>,
                        (const void *)fft_x_c2r_kernel, (const void *)yx_inv256_kernel<kSpecF32>,
-                       (const void *)yx_inv256_kernel<kSpecBF16>, (const void *)yx_inv256_kernel<kSpecF16>};
+                       (const void *)yx_inv256_kernel<kSpecBF16>, (const void *)yx_inv256_kernel<kSpecF16>,
+                       (const void *)yx_inv128_kernel<kSpecF32>, (const void *)yx_inv128_kernel<kSpecBF16>,
+                       (const void *)yx_inv128_kernel<kSpecF16>};
     for (const void *f : k) {
         hipError_t e = raise_dynamic_lds(f);
         if (e != hipSuccess) return e;
@@ -923,12 +1050,28 @@ hipError_t launch_fft_y_inv(void *spec, const Grid &g, const FftAxis &ax, hipStr
     return hipGetLastError();
 }
 
-bool fft_yx_fused(const Grid &g) { return g.n[0] == kYx && g.n[1] == kYx; }
+bool fft_yx_fused(const Grid &g) {
+    return (g.n[0] == kYx && g.n[1] == kYx) || (g.n[0] == kYh && g.n[1] == kYh);
+}
 
 hipError_t launch_fft_yx_inv(const void *spec, float *A, float2 *rowmm, DevStatus *st, const Grid &g,
                              const FftAxis &ay, hipStream_t s) {
     if (!fft_yx_fused(g)) return hipErrorInvalidValue;
     const float scale = g.spec_st == kSpecF32 ? 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]) : g.iscale;
+    if (g.n[0] == kYh) {
+        const dim3 grid(2 * g.n[2]), blk(kYhThreads);
+        switch (g.spec_st) {
+            case kSpecBF16:
+                yx_inv128_kernel<kSpecBF16><<<grid, blk, yx_inv128_lds(), s>>>(spec, A, rowmm, st, g, ay.tw, scale);
+                break;
+            case kSpecF16:
+                yx_inv128_kernel<kSpecF16><<<grid, blk, yx_inv128_lds(), s>>>(spec, A, rowmm, st, g, ay.tw, scale);
+                break;
+            default:
+                yx_inv128_kernel<kSpecF32><<<grid, blk, yx_inv128_lds(), s>>>(spec, A, rowmm, st, g, ay.tw, scale);
+        }
+        return hipGetLastError();
+    }
     switch (g.spec_st) {
         case kSpecBF16:
             yx_inv256_kernel<kSpecBF16><<<dim3(g.n[2]), dim3(kYxThreads), yx_inv256_lds(), s>>>(spec, A, rowmm, st, g,

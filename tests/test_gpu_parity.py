@@ -308,12 +308,14 @@ def test_row_range_skip_on_an_open_surface_256(ctx):
     assert torch.equal(full.vertices, mesh.vertices) and torch.equal(full.triangles, mesh.triangles)
 
 
-def test_fused_inverse_on_a_256x256x96_grid(ctx):
-    """N_x = N_y = 256 takes the fused inverse y/x pass and the marching-cubes
-    block list whatever N_z is: indicator against the oracle, mesh against the
-    full classification of the same field."""
-    f = _random_frame(21, 60_000, (256, 256, 96), (-1.0, -1.0, -0.375, 1.0, 1.0, 0.375))
-    print("[fused] random frame 256x256x96", flush=True)
+@pytest.mark.parametrize("dims", [(256, 256, 96), (128, 128, 48), (128, 128, 16)])
+def test_fused_inverse_passes(ctx, dims):
+    """N_x = N_y = 256 and N_x = N_y = 128 take the fused inverse y/x pass
+    whatever N_z is: indicator against the oracle, mesh against the full
+    classification of the same field."""
+    half = tuple(d / dims[0] for d in dims)
+    f = _random_frame(21 + dims[2], 60_000, dims, tuple(-x for x in half) + half)
+    print(f"[fused] random frame {dims}", flush=True)
     dev = _frame_dev(f)
     A, L = ctx.indicator(*dev, grid_dim=f.dims, bbox=f.bbox)
     Vo, _, _, _ = oracle.splat(f.points, f.normals, f.weights, f.dims, f.bbox)

@@ -307,13 +307,6 @@ def bench_serve(args, fvr, synth, np, captures):
             pool.append(tuple(torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
                               for a in (f.points, f.normals, f.weights)))
         pools.append((name, dims, base.bbox, pool, base.n_points))
-    srv = fvr.Server(slots=args.serve_slots, hbm_budget=int(args.serve_budget_gib * (1 << 30)))
-    # warm the slots up: every station's shape once per slot, so the
-    # measured stream runs on grown scratch
-    for _ in range(args.serve_slots):
-        for name, dims, bbox, pool, _m in pools:
-            srv.submit(*pool[0], dims, bbox)
-    srv.drain()
     rng = np.random.default_rng(5000)
     arrivals = []
     for si in range(len(pools)):
@@ -324,15 +317,39 @@ def bench_serve(args, fvr, synth, np, captures):
                 break
             arrivals.append((t, si, int(rng.integers(0, args.serve_pool))))
     arrivals.sort()
-    print(f"[bench] serving: {len(arrivals)} requests over {args.serve_seconds} s", file=sys.stderr, flush=True)
+    storages = [x for x in args.serve_storages.split(",") if x]
+    out = None
+    for storage in storages:
+        r = _serve_stream(args, fvr, np, pools, arrivals, storage)
+        if out is None:
+            out = r
+            out["storage"] = storage
+            out["other_storages"] = {}
+        else:
+            out["other_storages"][storage] = {k: r[k] for k in ("completed", "value", "p50_ms", "p99_ms",
+                                                                 "stations", "max_in_flight", "device_bytes")}
+    return out
+
+
+def _serve_stream(args, fvr, np, pools, arrivals, storage):
+    """One pass of the arrival stream through a fresh server, every request
+    with the given spectrum storage."""
+    srv = fvr.Server(slots=args.serve_slots, hbm_budget=int(args.serve_budget_gib * (1 << 30)))
+    # warm the slots up: every station's shape once per slot, so the
+    # measured stream runs on grown scratch
+    for _ in range(args.serve_slots):
+        for name, dims, bbox, pool, _m in pools:
+            srv.submit(*pool[0], dims, bbox, storage=storage)
+    srv.drain()
+    print(f"[bench] serving ({storage} spectra): {len(arrivals)} requests over {args.serve_seconds} s",
+          file=sys.stderr, flush=True)
     results = []
     t0 = time.perf_counter()
-    base_ms = None
     for t, si, j in arrivals:
         while time.perf_counter() - t0 < t:
             results += srv.poll()
         name, dims, bbox, pool, _m = pools[si]
-        srv.submit(*pool[j], dims, bbox, user=si)
+        srv.submit(*pool[j], dims, bbox, user=si, storage=storage)
     results += srv.drain()
     elapsed = time.perf_counter() - t0
     info = srv.info()
@@ -389,6 +406,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=16, help="frames per station pool")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-storages", default="f32,bf16",
+                    help="spectrum storages of the serving passes (the same arrival stream each); the "
+                         "first is reported under 'serving', the others under its 'other_storages'")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="measure the batched workload on the default plans")
     ap.add_argument("--tune-cache", default=None, help="JSON file the autotuner's choices are added to")

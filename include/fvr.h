@@ -104,8 +104,8 @@ typedef struct {
  * so the stored magnitudes do not depend on the bbox's length unit: for
  * unit normals they stay some 2^16 below FP16's largest value.  A value
  * that overflows anyway makes the call fail with FVR_E_RANGE.  V never
- * leaves the chip and A stays float32.  Dims must be in
- * {16, 32, 64, 128, 256} (FVR_E_UNSUPPORTED otherwise).  The indicator then
+ * leaves the chip and A stays float32.  Every supported grid takes either
+ * storage.  The indicator then
  * carries the rounding of 8-bit (bf16) or 11-bit (fp16) significands: its
  * error against an FP64 evaluation is reported with the benchmarks, and lies
  * outside the float32 tolerance. */

@@ -425,7 +425,7 @@ class Context:
         return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
 
     def reconstruct_noalloc(self, points, normals, weights=None, grid_dim=(128, 128, 128),
-                            bbox=((-1, -1, -1), (1, 1, 1)), out=None, splat="gaussian") -> Mesh:
+                            bbox=((-1, -1, -1), (1, 1, 1)), out=None, splat="gaussian", storage="f32") -> Mesh:
         """``reconstruct`` through ``fvr_reconstruct_noalloc``: the library
         allocates no device memory in the call (its scratch is the device's
         static array of FVR_NOALLOC_SCRATCH_BYTES).  ``out`` = (verts, tris)
@@ -433,7 +433,7 @@ class Context:
         scratch raises FvrError."""
         if out is None:
             raise ValueError("reconstruct_noalloc needs preallocated out=(vertices, triangles)")
-        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat)
+        f, keep = self._frame(points, normals, weights, grid_dim, bbox, splat, storage)
         self._stream()
         m = _Mesh()
         _fill_mesh(m, out)
@@ -706,8 +706,12 @@ class Server:
 
     def submit(self, points, normals, weights=None, grid_dim=(128, 128, 128), bbox=((-1, -1, -1), (1, 1, 1)),
                splat="gaussian", vertex_capacity=None, triangle_capacity=None, vertex_normals=False,
-               user=None) -> int:
+               user=None, storage="f32") -> int:
         import numpy as np
+        if splat not in SPLATS:
+            raise ValueError(f"splat must be one of {sorted(SPLATS)}")
+        if storage not in STORAGES:
+            raise ValueError(f"storage must be one of {sorted(STORAGES)}")
         p, pp, pin_p = self._host(points, "points", 3)
         n, pn, pin_n = self._host(normals, "normals", 3)
         keep = [p, n]
@@ -727,7 +731,7 @@ class Server:
         q.n_points = int(p.shape[0])
         q.dims[:] = [nx, ny, nz]
         q.bbox[:] = [float(x) for x in _flat_bbox(bbox)]
-        q.options = SPLATS[splat]
+        q.options = SPLATS[splat] | STORAGES[storage]
         q.flags = 1 if (pin_p and pin_n and pin_w) else 0
         q.vertices, q.triangles = verts.ctypes.data, tris.ctypes.data
         q.normals_out = nrm.ctypes.data if nrm is not None else None

@@ -419,12 +419,6 @@ fvr_status check_frame_fields(fvr_ctx *c, const fvr_frame *f) {
         return fail(c, FVR_E_INVALID, "FVR_STORAGE_BF16 and FVR_STORAGE_FP16 together");
     fvr_status r = check_grid(c, f->dims, f->bbox);
     if (r != FVR_OK) return r;
-    if (f->options & (FVR_STORAGE_BF16 | FVR_STORAGE_FP16))
-        for (int a = 0; a < 3; ++a) {
-            const int n = f->dims[a];
-            if (n != 16 && n != 32 && n != 64 && n != 128 && n != 256)
-                return fail(c, FVR_E_UNSUPPORTED, "16-bit spectrum storage needs dims in {16, 32, 64, 128, 256}");
-        }
     return FVR_OK;
 }
 

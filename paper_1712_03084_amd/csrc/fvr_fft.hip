@@ -1,7 +1,8 @@
 // Strided FFT passes of the spectral integration (Sec. III-B) on gfx950.
 //
 // Spectra are three half-spectrum planes of shape (Nz, Ny, H), H = Nx/2 + 1,
-// complex64, kx fastest.  The forward x transform (with the x derivative
+// kx fastest, each bin complex64 or two packed 16-bit floats (bf16 / fp16;
+// every pass computes in float32).  The forward x transform (with the x derivative
 // factor) is fused into the splat kernel; these passes finish the transform
 // along y and z, apply the integration filter, and invert:
 //
@@ -10,8 +11,8 @@
 //   fft_z_solve P0 <- F_z^-1 [ (F_z P0 + j w_z F_z P2) / |w|^2 ],  DC -> 0
 //   fft_y_inv   P0 <- F_y^-1 P0
 //   fft_x_c2r   A  <- F_x^-1 P0 / (Nx Ny Nz)          (real output)
-//   fft_yx_inv  both of the above in one kernel, one block per z plane
-//               (Nx = Ny = 256), with each row's range of A as a by-product
+//   fft_yx_inv  both of the above in one kernel per z plane (Nx = Ny = 256
+//               or 128), with each row's range of A as a by-product
 //
 // By linearity this equals the paper's per-component transform, filter and
 // inverse followed by the sum of the X, Y and Z components.
@@ -33,77 +34,94 @@ constexpr int kBatch = 8;      // 16-byte global loads kept in flight per thread
 __device__ __forceinline__ int nchunks(int H) { return (H + kChunk - 1) / kChunk; }
 
 // Pencil tiles.  A tile is [len][kChunk] complex values of one spectrum
-// plane, element (t, c) at src[t * stride + kx0 + c] (zero for kx0 + c >= H);
-// rows are 128-byte aligned (stride and kx0 are multiples of 16), so a thread
-// moves two complex values per 16-byte access.  prefetch() issues all of a
-// thread's loads of one tile (PF = len * kChunk / 2 / kPassThreads of them)
-// into registers; commit() writes them to LDS.  Issuing the loads of two or
-// three tiles before the first commit keeps one memory round trip per block.
-template <int PF>
-__device__ __forceinline__ void prefetch(float4 (&v)[PF], const float2 *__restrict__ src,
-                                         size_t stride, int len, int kx0, int H) {
+// plane, element (t, c) at bin t * stride + kx0 + c of src (zero for
+// kx0 + c >= H); rows start on 64-byte boundaries (stride and kx0 are
+// multiples of 16), so a thread moves two adjacent bins per access: 16 bytes
+// of complex64 or 8 bytes of two packed 16-bit complex values.  prefetch()
+// issues all of a thread's loads of one tile (PF = len * kChunk / 2 /
+// kPassThreads of them) into registers, as stored; commit() widens them to
+// float32 in LDS.  Issuing the loads of two or three tiles before the first
+// commit keeps one memory round trip per block.  Rows t with keep[t] == 0
+// (keep non-null) are known to be zero and are not read.
+template <int ST> struct PairOf { typedef uint2 T; };
+template <> struct PairOf<kSpecF32> { typedef float4 T; };
+template <int ST> using PairT = typename PairOf<ST>::T;
+template <int ST> constexpr size_t kBinBytes = ST == kSpecF32 ? 8 : 4;
+
+// address of bin i of a spectrum array of storage ST
+template <int ST>
+__device__ __forceinline__ char *bin_at(void *spec, size_t i) {
+    return static_cast<char *>(spec) + i * kBinBytes<ST>;
+}
+
+template <int ST, int PF>
+__device__ __forceinline__ void prefetch(PairT<ST> (&v)[PF], const char *__restrict__ src, size_t stride, int len,
+                                         int kx0, int H, const uint8_t *keep) {
     const int tot2 = len * (kChunk / 2);
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const int i = u * kPassThreads + threadIdx.x;
         const int t = i / (kChunk / 2), c = 2 * (i % (kChunk / 2));
-        v[u] = (i < tot2 && kx0 + c < H) ? *reinterpret_cast<const float4 *>(src + t * stride + kx0 + c)
-                                         : make_float4(0.f, 0.f, 0.f, 0.f);
-        if (kx0 + c + 1 >= H) {  // the pair's second column is row padding
-            v[u].z = 0.f;
-            v[u].w = 0.f;
+        PairT<ST> w = {};
+        if (i < tot2 && kx0 + c < H && (!keep || keep[t]))
+            w = *reinterpret_cast<const PairT<ST> *>(src + (t * stride + kx0 + c) * kBinBytes<ST>);
+        if (kx0 + c + 1 >= H) {  // the pair's second bin is row padding
+            if constexpr (ST == kSpecF32) {
+                w.z = 0.f;
+                w.w = 0.f;
+            } else {
+                w.y = 0u;
+            }
         }
+        v[u] = w;
     }
 }
 
-// prefetch() for a tile whose rows t with keep[t] == 0 are known to be zero:
-// those rows are not read.
-template <int PF>
-__device__ __forceinline__ void prefetch_rows(float4 (&v)[PF], const float2 *__restrict__ src,
-                                              size_t stride, int len, int kx0, int H,
-                                              const uint8_t *keep) {
+template <int ST, int PF>
+__device__ __forceinline__ void commit(float2 *dst, const PairT<ST> (&v)[PF], int len) {
     const int tot2 = len * (kChunk / 2);
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const int i = u * kPassThreads + threadIdx.x;
-        const int t = i / (kChunk / 2), c = 2 * (i % (kChunk / 2));
-        v[u] = (i < tot2 && kx0 + c < H && keep[t])
-                   ? *reinterpret_cast<const float4 *>(src + t * stride + kx0 + c)
-                   : make_float4(0.f, 0.f, 0.f, 0.f);
-        if (kx0 + c + 1 >= H) {
-            v[u].z = 0.f;
-            v[u].w = 0.f;
+        if (i >= tot2) continue;
+        if constexpr (ST == kSpecF32) {
+            reinterpret_cast<float4 *>(dst)[i] = v[u];
+        } else {
+            const float2 a = spec_unpack<ST>(v[u].x), b = spec_unpack<ST>(v[u].y);
+            reinterpret_cast<float4 *>(dst)[i] = make_float4(a.x, a.y, b.x, b.y);
         }
     }
 }
 
-template <int PF>
-__device__ __forceinline__ void commit(float2 *dst, const float4 (&v)[PF], int len) {
-    const int tot2 = len * (kChunk / 2);
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-        const int i = u * kPassThreads + threadIdx.x;
-        if (i < tot2) reinterpret_cast<float4 *>(dst)[i] = v[u];
-    }
-}
-
-__device__ __forceinline__ void store_pencils(float2 *__restrict__ dstg, const float2 *src,
-                                              size_t stride, int len, int kx0, int H) {
+// Writes a tile back; the 16-bit storages store it times `scale`.
+template <int ST>
+__device__ __forceinline__ void store_pencils(char *__restrict__ dstg, const float2 *src, size_t stride, int len,
+                                              int kx0, int H, float scale) {
     const int tot2 = len * (kChunk / 2);
     for (int i = threadIdx.x; i < tot2; i += kPassThreads) {
         const int t = i / (kChunk / 2), c = 2 * (i % (kChunk / 2));
         const float4 v = reinterpret_cast<const float4 *>(src)[i];
-        if (kx0 + c + 1 < H)
-            *reinterpret_cast<float4 *>(dstg + t * stride + kx0 + c) = v;
-        else if (kx0 + c < H)
-            dstg[t * stride + kx0 + c] = make_float2(v.x, v.y);
+        char *d = dstg + (t * stride + kx0 + c) * kBinBytes<ST>;
+        if constexpr (ST == kSpecF32) {
+            if (kx0 + c + 1 < H)
+                *reinterpret_cast<float4 *>(d) = v;
+            else if (kx0 + c < H)
+                *reinterpret_cast<float2 *>(d) = make_float2(v.x, v.y);
+        } else {
+            const unsigned pa = spec_pack<ST>(make_float2(v.x * scale, v.y * scale));
+            const unsigned pb = spec_pack<ST>(make_float2(v.z * scale, v.w * scale));
+            if (kx0 + c + 1 < H)
+                *reinterpret_cast<uint2 *>(d) = make_uint2(pa, pb);
+            else if (kx0 + c < H)
+                *reinterpret_cast<unsigned *>(d) = pa;
+        }
     }
 }
 
-template <int PF>
+template <int ST, int PF>
 __global__ void __launch_bounds__(kPassThreads)
-fft_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
-                 uint8_t *__restrict__ zocc, DevStatus *__restrict__ st, Grid g, FftAxis ay) {
+fft_y_fwd_kernel(void *__restrict__ spec, const uint8_t *__restrict__ occ, uint8_t *__restrict__ zocc,
+                 DevStatus *__restrict__ st, Grid g, FftAxis ay) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
     __shared__ uint8_t keep[kMaxDim];
     __shared__ int any;
@@ -130,13 +148,14 @@ fft_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
     float2 *A = lds, *B = lds + Ny * kChunk, *tw = lds + 2 * Ny * kChunk;
     const int tot = Ny * kChunk;
     const size_t zoff = (size_t)z * Ny * Hp;
-    float4 va[PF], vb[PF], vc[PF];
-    prefetch_rows<PF>(va, spec + zoff, Hp, Ny, k0, H, keep);
-    prefetch_rows<PF>(vb, spec + plane + zoff, Hp, Ny, k0, H, keep);
+    const float sy = ST == kSpecF32 ? 1.0f : g.fscale[1];  // the y share of the inverse's 1/n
+    PairT<ST> va[PF], vb[PF], vc[PF];
+    prefetch<ST, PF>(va, bin_at<ST>(spec, zoff), Hp, Ny, k0, H, keep);
+    prefetch<ST, PF>(vb, bin_at<ST>(spec, plane + zoff), Hp, Ny, k0, H, keep);
     load_twiddles(tw, ay);
-    commit<PF>(A, va, Ny);
-    commit<PF>(B, vb, Ny);
-    prefetch_rows<PF>(vc, spec + 2 * plane + zoff, Hp, Ny, k0, H, keep);  // in flight during the transforms
+    commit<ST, PF>(A, va, Ny);
+    commit<ST, PF>(B, vb, Ny);
+    prefetch<ST, PF>(vc, bin_at<ST>(spec, 2 * plane + zoff), Hp, Ny, k0, H, keep);  // in flight during the transforms
     __syncthreads();
     fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, ay, tw, -1);
     fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, tw, -1);
@@ -147,16 +166,16 @@ fft_y_fwd_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ occ,
         A[i] = make_float2(A[i].x - w * b.y, A[i].y + w * b.x);
     }
     __syncthreads();
-    store_pencils(spec + zoff, A, Hp, Ny, k0, H);
-    commit<PF>(B, vc, Ny);
+    store_pencils<ST>(bin_at<ST>(spec, zoff), A, Hp, Ny, k0, H, sy);
+    commit<ST, PF>(B, vc, Ny);
     __syncthreads();
     fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, ay, tw, -1);
-    store_pencils(spec + 2 * plane + zoff, B, Hp, Ny, k0, H);
+    store_pencils<ST>(bin_at<ST>(spec, 2 * plane + zoff), B, Hp, Ny, k0, H, sy);
 }
 
-template <int PF>
+template <int ST, int PF>
 __global__ void __launch_bounds__(kPassThreads)
-fft_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, Grid g, FftAxis az) {
+fft_z_solve_kernel(void *__restrict__ spec, const uint8_t *__restrict__ zocc, Grid g, FftAxis az) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
     __shared__ uint8_t keep[kMaxDim];
     const int Ny = g.n[1], Nz = g.n[2], H = g.H, Hp = g.Hp;
@@ -170,22 +189,23 @@ fft_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
     float2 *A = lds, *B = lds + Nz * kChunk, *tw = lds + 2 * Nz * kChunk;
     const int tot = Nz * kChunk;
     const size_t yoff = (size_t)ky * Hp;
-    float4 va[PF], vb[PF];
-    prefetch_rows<PF>(va, spec + yoff, zstride, Nz, k0, H, keep);
-    prefetch_rows<PF>(vb, spec + 2 * plane + yoff, zstride, Nz, k0, H, keep);
+    PairT<ST> va[PF], vb[PF];
+    prefetch<ST, PF>(va, bin_at<ST>(spec, yoff), zstride, Nz, k0, H, keep);
+    prefetch<ST, PF>(vb, bin_at<ST>(spec, 2 * plane + yoff), zstride, Nz, k0, H, keep);
     load_twiddles(tw, az);
-    commit<PF>(A, va, Nz);
-    commit<PF>(B, vb, Nz);
+    commit<ST, PF>(A, va, Nz);
+    commit<ST, PF>(B, vb, Nz);
     __syncthreads();
     fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, tw, -1);
     fft_rows<true>(RowsC{B, 1, kChunk}, kChunk, az, tw, -1);
     const float wy = (float)kappa(ky, Ny) * g.wstep[1];
+    const float sz = ST == kSpecF32 ? 1.0f : g.fscale[2];  // the z share of the inverse's 1/n
     for (int i = threadIdx.x; i < tot; i += blockDim.x) {
         const int kz = i / kChunk, c = i % kChunk, kx = k0 + c;
         const float wx = (float)kappa(kx, g.n[0]) * g.wstep[0];
         const float wzf = (float)kappa(kz, Nz) * g.wstep[2];
         const float w2 = wx * wx + wy * wy + wzf * wzf;
-        const float inv = w2 > 0.f ? 1.0f / w2 : 0.0f;
+        const float inv = w2 > 0.f ? sz / w2 : 0.0f;
         const float wz = deriv_w(kz, Nz, g.wstep[2]);
         const float2 b = B[i];
         const float2 a = A[i];
@@ -193,12 +213,12 @@ fft_z_solve_kernel(float2 *__restrict__ spec, const uint8_t *__restrict__ zocc, 
     }
     __syncthreads();
     fft_rows<true>(RowsC{A, 1, kChunk}, kChunk, az, tw, +1);
-    store_pencils(spec + yoff, A, zstride, Nz, k0, H);
+    store_pencils<ST>(bin_at<ST>(spec, yoff), A, zstride, Nz, k0, H, 1.0f);
 }
 
-template <int PF>
+template <int ST, int PF>
 __global__ void __launch_bounds__(kPassThreads)
-fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
+fft_y_inv_kernel(void *__restrict__ spec, Grid g, FftAxis ay) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
     const int Ny = g.n[1], H = g.H, Hp = g.Hp;
     const int nch = nchunks(H);
@@ -206,13 +226,13 @@ fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
     const int k0 = chunk * kChunk;
     const size_t zoff = (size_t)z * Ny * Hp;
     float2 *tw = lds + Ny * kChunk;
-    float4 va[PF];
-    prefetch<PF>(va, spec + zoff, Hp, Ny, k0, H);
+    PairT<ST> va[PF];
+    prefetch<ST, PF>(va, bin_at<ST>(spec, zoff), Hp, Ny, k0, H, nullptr);
     load_twiddles(tw, ay);
-    commit<PF>(lds, va, Ny);
+    commit<ST, PF>(lds, va, Ny);
     __syncthreads();
     fft_rows<true>(RowsC{lds, 1, kChunk}, kChunk, ay, tw, +1);
-    store_pencils(spec + zoff, lds, Hp, Ny, k0, H);
+    store_pencils<ST>(bin_at<ST>(spec, zoff), lds, Hp, Ny, k0, H, 1.0f);
 }
 
 // Inverse real transform along x.  Two real rows a, b (consecutive linear
@@ -220,9 +240,12 @@ fft_y_inv_kernel(float2 *__restrict__ spec, Grid g, FftAxis ay) {
 // Z[k] = X_a[k] + i X_b[k], with X[k] for k > Nx/2 taken as conj(X[Nx-k])
 // (Hermitian symmetry of a real row's spectrum); the imaginary parts of the
 // k = 0 and k = Nx/2 bins are dropped, as a real row's spectrum has none.
+// A 16-bit storage that overflowed leaves a non-finite value in A: the pass
+// flags it (kFlagRange).
+template <int ST>
 __global__ void __launch_bounds__(kPassThreads)
-fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm, Grid g,
-                 FftAxis ax, float scale) {
+fft_x_c2r_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *__restrict__ rowmm,
+                 DevStatus *__restrict__ st, Grid g, FftAxis ax, float scale) {
     extern __shared__ __attribute__((aligned(16))) float2 lds[];
     const int Nx = g.n[0], Hp = g.Hp;
     const int nrows = g.n[1] * g.n[2];
@@ -242,8 +265,8 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 
             xa[u] = xb[u] = make_float2(0.f, 0.f);
             if (i < tot && ra < nrows) {
                 const int kk = k > Nx / 2 ? Nx - k : k;
-                xa[u] = spec[(size_t)ra * Hp + kk];
-                xb[u] = spec[(size_t)(ra + 1) * Hp + kk];
+                xa[u] = spec_ld<ST>(spec, (size_t)ra * Hp + kk);
+                xb[u] = spec_ld<ST>(spec, (size_t)(ra + 1) * Hp + kk);
             }
         }
 #pragma unroll
@@ -265,6 +288,7 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 
     }
     __syncthreads();
     fft_rows<false>(RowsC{lds, Nx, 1}, ncx, ax, tw, +1);
+    bool bad = false;
     for (int i = threadIdx.x; i < tot; i += blockDim.x) {
         const int jr = udiv(i, Nx, mN), k = i - jr * Nx;
         const int ra = row0 + 2 * jr;
@@ -272,8 +296,11 @@ fft_x_c2r_kernel(const float2 *__restrict__ spec, float *__restrict__ A, float2 
             const float2 z = lds[i];
             A[(size_t)ra * Nx + k] = z.x * scale;
             A[(size_t)(ra + 1) * Nx + k] = z.y * scale;
+            if constexpr (ST != kSpecF32) bad |= !__builtin_isfinite(z.x) || !__builtin_isfinite(z.y);
         }
     }
+    if constexpr (ST != kSpecF32)
+        if (bad) atomicOr(&st->flags, kFlagRange);
     // (min, max) of each real row as stored, one wave per complex row
     const int lane = threadIdx.x & 63;
     for (int jr = threadIdx.x >> 6; jr < ncx; jr += blockDim.x >> 6) {
@@ -975,27 +1002,48 @@ static int prefetch_depth(int len) {
     return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
 }
 
-#define FVR_PF_SWITCH(len, KERNEL, ARGS, ...)                                             \
+#define FVR_PF_SWITCH(len, KERNEL, ST, ARGS, ...)                                         \
     switch (prefetch_depth(len)) {                                                        \
-        case 2: KERNEL<2><<<__VA_ARGS__>>> ARGS; break;                                  \
-        case 4: KERNEL<4><<<__VA_ARGS__>>> ARGS; break;                                  \
-        case 8: KERNEL<8><<<__VA_ARGS__>>> ARGS; break;                                  \
-        default: KERNEL<16><<<__VA_ARGS__>>> ARGS; break;                                \
+        case 2: KERNEL<ST, 2><<<__VA_ARGS__>>> ARGS; break;                              \
+        case 4: KERNEL<ST, 4><<<__VA_ARGS__>>> ARGS; break;                              \
+        case 8: KERNEL<ST, 8><<<__VA_ARGS__>>> ARGS; break;                              \
+        default: KERNEL<ST, 16><<<__VA_ARGS__>>> ARGS; break;                            \
+    }
+// Stockham kernels instantiated for the spectrum storage of the grid.
+#define FVR_PF_ST(len, KERNEL, ARGS, ...)                                                 \
+    switch (g.spec_st) {                                                                  \
+        case kSpecBF16: { FVR_PF_SWITCH(len, KERNEL, kSpecBF16, ARGS, __VA_ARGS__) } break; \
+        case kSpecF16: { FVR_PF_SWITCH(len, KERNEL, kSpecF16, ARGS, __VA_ARGS__) } break;   \
+        default: { FVR_PF_SWITCH(len, KERNEL, kSpecF32, ARGS, __VA_ARGS__) } break;         \
     }
 
+template <int ST>
+static hipError_t configure_stockham() {
+    const void *k[] = {(const void *)fft_y_fwd_kernel<ST, 2>,   (const void *)fft_y_fwd_kernel<ST, 4>,
+                       (const void *)fft_y_fwd_kernel<ST, 8>,   (const void *)fft_y_fwd_kernel<ST, 16>,
+                       (const void *)fft_z_solve_kernel<ST, 2>, (const void *)fft_z_solve_kernel<ST, 4>,
+                       (const void *)fft_z_solve_kernel<ST, 8>, (const void *)fft_z_solve_kernel<ST, 16>,
+                       (const void *)fft_y_inv_kernel<ST, 2>,   (const void *)fft_y_inv_kernel<ST, 4>,
+                       (const void *)fft_y_inv_kernel<ST, 8>,   (const void *)fft_y_inv_kernel<ST, 16>,
+                       (const void *)fft_x_c2r_kernel<ST>};
+    for (const void *f : k) {
+        hipError_t e = raise_dynamic_lds(f);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t fft_configure() {
-    const void *k[] = {(const void *)fft_y_fwd_kernel<2>,   (const void *)fft_y_fwd_kernel<4>,
-                       (const void *)fft_y_fwd_kernel<8>,   (const void *)fft_y_fwd_kernel<16>,
-                       (const void *)fft_z_solve_kernel<2>, (const void *)fft_z_solve_kernel<4>,
-                       (const void *)fft_z_solve_kernel<8>, (const void *)fft_z_solve_kernel<16>,
-                       (const void *)fft_y_inv_kernel<2>,   (const void *)fft_y_inv_kernel<4>,
-                       (const void *)fft_y_inv_kernel<8>,   (const void *)fft_y_inv_kernel<16>,
-                       (const void *)fft_x_c2r_kernel, (const void *)yx_inv256_kernel<kSpecF32>,
+    hipError_t e = configure_stockham<kSpecF32>();
+    if (e == hipSuccess) e = configure_stockham<kSpecBF16>();
+    if (e == hipSuccess) e = configure_stockham<kSpecF16>();
+    if (e != hipSuccess) return e;
+    const void *k[] = {(const void *)yx_inv256_kernel<kSpecF32>,
                        (const void *)yx_inv256_kernel<kSpecBF16>, (const void *)yx_inv256_kernel<kSpecF16>,
                        (const void *)yx_inv128_kernel<kSpecF32>, (const void *)yx_inv128_kernel<kSpecBF16>,
                        (const void *)yx_inv128_kernel<kSpecF16>};
     for (const void *f : k) {
-        hipError_t e = raise_dynamic_lds(f);
+        e = raise_dynamic_lds(f);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1019,9 +1067,8 @@ hipError_t launch_fft_y_fwd(void *spec, const uint8_t *occ, uint8_t *zocc, DevSt
         FVR_PEN_ST(pc, pen_y_fwd_kernel, (spec, occ, zocc, st, g, ax.tw), dim3(nch * g.n[2]))
         return hipGetLastError();
     }
-    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;  // complex64 only on Stockham lengths
-    FVR_PF_SWITCH(g.n[1], fft_y_fwd_kernel, (static_cast<float2 *>(spec), occ, zocc, st, g, ax), dim3(nch * g.n[2]),
-                  dim3(kPassThreads), pass_lds(g.n[1], 2), s)
+    FVR_PF_ST(g.n[1], fft_y_fwd_kernel, (spec, occ, zocc, st, g, ax), dim3(nch * g.n[2]), dim3(kPassThreads),
+              pass_lds(g.n[1], 2), s)
     return hipGetLastError();
 }
 
@@ -1032,9 +1079,8 @@ hipError_t launch_fft_z_solve(void *spec, const uint8_t *zocc, const Grid &g, co
         FVR_PEN_ST(pc, pen_z_solve_kernel, (spec, zocc, g, ax.tw), dim3(nch * g.n[1]))
         return hipGetLastError();
     }
-    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;
-    FVR_PF_SWITCH(g.n[2], fft_z_solve_kernel, (static_cast<float2 *>(spec), zocc, g, ax), dim3(nch * g.n[1]),
-                  dim3(kPassThreads), pass_lds(g.n[2], 2), s)
+    FVR_PF_ST(g.n[2], fft_z_solve_kernel, (spec, zocc, g, ax), dim3(nch * g.n[1]), dim3(kPassThreads),
+              pass_lds(g.n[2], 2), s)
     return hipGetLastError();
 }
 
@@ -1044,9 +1090,8 @@ hipError_t launch_fft_y_inv(void *spec, const Grid &g, const FftAxis &ax, hipStr
         FVR_PEN_ST(pc, pen_y_inv_kernel, (spec, g, ax.tw), dim3(nch * g.n[2]))
         return hipGetLastError();
     }
-    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;
-    FVR_PF_SWITCH(g.n[1], fft_y_inv_kernel, (static_cast<float2 *>(spec), g, ax), dim3(nch * g.n[2]), dim3(kPassThreads),
-                  pass_lds(g.n[1], 1), s)
+    FVR_PF_ST(g.n[1], fft_y_inv_kernel, (spec, g, ax), dim3(nch * g.n[2]), dim3(kPassThreads), pass_lds(g.n[1], 1),
+              s)
     return hipGetLastError();
 }
 
@@ -1091,18 +1136,23 @@ hipError_t launch_fft_yx_inv(const void *spec, float *A, float2 *rowmm, DevStatu
 hipError_t launch_fft_x_c2r(const void *spec, float *A, float2 *rowmm, DevStatus *st, const Grid &g,
                             const FftAxis &ax, hipStream_t s) {
     const int nrows = g.n[1] * g.n[2];
+    const float scale = g.spec_st == kSpecF32 ? 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]) : g.iscale;
     if (const int pc = pencil_code(g.n[0])) {
-        const float scale = g.spec_st == kSpecF32 ? 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2])
-                                                  : g.iscale;
         FVR_PEN_ST(pc, pen_x_c2r_kernel, (spec, A, rowmm, st, g, ax.tw, scale), dim3((nrows + 31) / 32))
         return hipGetLastError();
     }
-    if (g.spec_st != kSpecF32) return hipErrorInvalidValue;
-    const int blocks = (nrows + kC2rRows - 1) / kC2rRows;
-    const float scale = 1.0f / ((float)g.n[0] * (float)g.n[1] * (float)g.n[2]);
+    const dim3 grid((nrows + kC2rRows - 1) / kC2rRows), blk(kPassThreads);
     const size_t lds = ((size_t)(kC2rRows / 2) * g.n[0] + g.n[0]) * sizeof(float2);
-    fft_x_c2r_kernel<<<dim3(blocks), dim3(kPassThreads), lds, s>>>(static_cast<const float2 *>(spec), A, rowmm, g,
-                                                                  ax, scale);
+    switch (g.spec_st) {
+        case kSpecBF16:
+            fft_x_c2r_kernel<kSpecBF16><<<grid, blk, lds, s>>>(spec, A, rowmm, st, g, ax, scale);
+            break;
+        case kSpecF16:
+            fft_x_c2r_kernel<kSpecF16><<<grid, blk, lds, s>>>(spec, A, rowmm, st, g, ax, scale);
+            break;
+        default:
+            fft_x_c2r_kernel<kSpecF32><<<grid, blk, lds, s>>>(spec, A, rowmm, st, g, ax, scale);
+    }
     return hipGetLastError();
 }
 

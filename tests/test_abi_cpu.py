@@ -69,18 +69,19 @@ def test_mc_table_identical_to_oracle_generator():
 
 
 def test_check_frame_option_bits():
-    """Spectrum storages: one at a time, and only on the pencil lengths."""
+    """Spectrum storages: one at a time, on any supported grid."""
     ok = (-1, -1, -1, 1, 1, 1)
     bf16, fp16, nearest = 2, 4, 1
     for opt in (0, bf16, fp16, nearest, nearest | bf16, nearest | fp16):
         assert fvr.check_frame(10, (64, 64, 64), ok, options=opt) == 0
     assert fvr.check_frame(10, (64, 64, 64), ok, options=bf16 | fp16) == -1
     assert fvr.check_frame(10, (64, 64, 64), ok, options=8) == -1
-    for dims in ((48, 64, 64), (64, 96, 64), (64, 64, 512)):
-        assert fvr.check_frame(10, dims, ok) == 0
-        assert fvr.check_frame(10, dims, ok, options=bf16) == -2
-        assert fvr.check_frame(10, dims, ok, options=fp16) == -2
-    assert fvr.check_frame(10, (16, 256, 128), ok, options=fp16) == 0
+    for dims in ((48, 64, 64), (64, 96, 64), (64, 64, 512), (16, 256, 128)):
+        for opt in (0, bf16, fp16):
+            assert fvr.check_frame(10, dims, ok, options=opt) == 0
+    for dims in ((56, 64, 64), (64, 64, 1024)):  # unsupported lengths stay unsupported
+        for opt in (0, bf16, fp16):
+            assert fvr.check_frame(10, dims, ok, options=opt) == -2
 
 
 def test_status_strings_and_null_context():

@@ -34,10 +34,19 @@ def _hausdorff(a, b):
     return float(max(cKDTree(b).query(a)[0].max(), cKDTree(a).query(b)[0].max()))
 
 
-@pytest.mark.parametrize("config", ["sphere64", "proxy128", "proxy256"])
+def _frame(config):
+    # sphere48 and proxy192 take the mixed-radix passes on every axis
+    if config == "sphere48":
+        return synth.sphere_frame(seed=3, m=40_000, grid=48)
+    if config == "proxy192":
+        return synth.human_proxy_frame(seed=1000, views=6, m=550_000, grid=192)
+    return synth.config_frame(config)
+
+
+@pytest.mark.parametrize("config", ["sphere64", "proxy128", "proxy256", "sphere48", "proxy192"])
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])
 def test_reduced_storage_error_against_fp64(ctx, config, storage):
-    f = synth.config_frame(config)
+    f = _frame(config)
     d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (f.points, f.normals, f.weights)]
     A, L = ctx.indicator(*d, grid_dim=f.dims, bbox=f.bbox, storage=storage)
     mesh = ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox, storage=storage)
@@ -57,21 +66,12 @@ def test_reduced_storage_error_against_fp64(ctx, config, storage):
     assert emax <= bmax and erms <= brms and hd <= bhd * h
 
 
-def test_reduced_storage_needs_pencil_lengths(ctx):
-    f = synth.sphere_frame(seed=1, m=5000, grid=48)
-    d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (f.points, f.normals, f.weights)]
-    with pytest.raises(fvr.FvrError) as e:
-        ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox, storage="bf16")
-    assert e.value.status == -2
-    # f32 storage of the same frame is unaffected
-    assert ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox).vertices.shape[0] > 0
-
-
-def test_fp16_overflow_is_an_error_not_a_wrong_answer(ctx):
+@pytest.mark.parametrize("grid", [64, 48])
+def test_fp16_overflow_is_an_error_not_a_wrong_answer(ctx, grid):
     """Normals of length 1e9 drive the FP16 spectrum past its largest value:
     the call fails with FVR_E_RANGE; bf16 (float32's exponent range) and
-    float32 storage take the same frame."""
-    f = synth.sphere_frame(seed=2, m=20000, grid=64)
+    float32 storage take the same frame.  48^3 runs the mixed-radix passes."""
+    f = synth.sphere_frame(seed=2, m=20000, grid=grid)
     pts = torch.from_numpy(np.ascontiguousarray(f.points)).cuda()
     big = torch.from_numpy(np.ascontiguousarray(f.normals) * np.float32(1e9)).cuda()
     with pytest.raises(fvr.FvrError) as e:

@@ -37,9 +37,9 @@ def mix():
     return frames
 
 
-def _reference(ctx, f, splat):
+def _reference(ctx, f, splat, storage="f32"):
     d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (f.points, f.normals, f.weights)]
-    m = ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox, splat=splat, vertex_normals=True)
+    m = ctx.reconstruct(*d, grid_dim=f.dims, bbox=f.bbox, splat=splat, vertex_normals=True, storage=storage)
     return m.vertices.cpu().numpy(), m.triangles.cpu().numpy(), m.normals.cpu().numpy(), m.level
 
 
@@ -66,6 +66,26 @@ def test_each_result_equals_its_frame_alone(ctx, mix):
     assert len(results) == 2 * len(mix) and info["max_in_flight"] >= 2
     for r in results:
         _check(r, refs[r["user"]])
+    srv.close()
+
+
+def test_16bit_storage_requests_among_float32_ones(ctx, mix):
+    """Requests with bf16 / fp16 spectra (192^3 on the mixed-radix passes)
+    interleaved with float32 ones on the same slots: each equals its frame
+    reconstructed alone with the same storage."""
+    cases = [(mix[1], "bf16"), (mix[3], "bf16"), (mix[0], "f32"), (mix[4], "fp16"), (mix[3], "f32"),
+             (mix[5], "fp16")]
+    refs = [_reference(ctx, f, sp, storage) for (f, sp), storage in cases]
+    srv = fvr.Server(slots=3, hbm_budget=64 << 30)
+    for i, ((f, sp), storage) in enumerate(cases):
+        srv.submit(f.points, f.normals, f.weights, f.dims, f.bbox, splat=sp, vertex_normals=True, user=i,
+                   storage=storage)
+    results = srv.drain()
+    assert len(results) == len(cases)
+    for r in results:
+        _check(r, refs[r["user"]])
+    with pytest.raises(ValueError):
+        srv.submit(mix[0][0].points, mix[0][0].normals, None, (64, 64, 64), mix[0][0].bbox, storage="fp8")
     srv.close()
 
 

@@ -69,6 +69,22 @@ def test_noalloc_matches_reconstruct_over_consecutive_calls(ctx):
         _same(again, ref)
 
 
+def test_noalloc_with_16bit_spectrum_storage(ctx):
+    """The storage option bits pass through: the 16-bit spectra (half the
+    bytes) are carved from the same static array."""
+    out = _out(200_000, 400_000)
+    for name, make, storage in [
+            ("proxy128, bf16", lambda: synth.config_frame("proxy128"), "bf16"),
+            ("sphere 48^3 (mixed-radix passes), fp16", lambda: synth.sphere_frame(seed=6, m=30_000, grid=48),
+             "fp16")]:
+        print(f"[noalloc] {name}", flush=True)
+        f = make()
+        dev = _frame_dev(f)
+        got = ctx.reconstruct_noalloc(*dev, grid_dim=f.dims, bbox=f.bbox, out=out, storage=storage)
+        ref = ctx.reconstruct(*dev, grid_dim=f.dims, bbox=f.bbox, storage=storage)
+        _same(got, ref)
+
+
 def test_noalloc_refuses_a_frame_beyond_the_static_scratch(ctx):
     f = synth.sphere_frame(seed=1, m=20_000, grid=256)
     dev = _frame_dev(f)

@@ -712,7 +712,6 @@ yx_inv256_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *_
     float2 *buf = smem;            // exchange buffers / y-inverse rows / output rows
     float2 *tw = smem + kYxBuf;    // w_256^m (the same table serves x and y)
     float2 *nyq = tw + N;          // the Nyquist column kx = 128
-    float4 *mmr = reinterpret_cast<float4 *>(nyq + N);  // per-wave row ranges [group][wave][c]
     const int grp = threadIdx.x >> 8, lt = threadIdx.x & 255;
     const int c = lt & 15, t = lt >> 4;
     const int z = blockIdx.x, Hp = g.Hp;
@@ -751,7 +750,8 @@ yx_inv256_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *_
     float *O = reinterpret_cast<float *>(buf);
     // out_row(t, i) = t + 16 i: row y lies in half y / 128 = i / 8, at
     // y - 128 half = out_row(t, i mod 8).  The loop body handles a[.][0..7];
-    // the second half's values move down at its end.
+    // the second half's values move down at its end.  Column 0 keeps the
+    // pair (x_0, x_128) of the two real columns as one complex value.
     static_assert(Pn::Q == 1, "output row t + 16 i");
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) {
@@ -761,29 +761,28 @@ yx_inv256_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *_
             const int kx = 16 * (grp + 4 * h) + c;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const int r = Pn::out_row(t, i);
-                if (kx == 0) {
-                    buf[r * kYxYP] = make_float2(a[h][i].x, 0.f);
-                    buf[r * kYxYP + N / 2] = make_float2(a[h][i].y, 0.f);
-                } else {
-                    buf[r * kYxYP + kx] = a[h][i];
-                }
+                buf[Pn::out_row(t, i) * kYxYP + kx] = a[h][i];
                 a[h][i] = a[h][i + 8];
             }
         }
         __syncthreads();
         // group grp packs real rows (2p, 2p + 1), p = 16 grp + c, as
-        // Z[k] = X_a[k] + i X_b[k] over the full length (X[N-k] = conj X[k])
+        // Z[k] = X_a[k] + i X_b[k] over the full length (X[N-k] = conj X[k]);
+        // bins 0 and N/2 of a real row are real, both read from column 0
         const int ra = 2 * (16 * grp + c), rb = ra + 1;
         float2 x[16];
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) {
             const int k = Pn::in_row(t, n1);
             const int kk = k <= N / 2 ? k : N - k;
-            float2 xa = buf[ra * kYxYP + kk], xb = buf[rb * kYxYP + kk];
-            if (kk == 0 || kk == N / 2) {
+            const int col = kk == N / 2 ? 0 : kk;
+            float2 xa = buf[ra * kYxYP + col], xb = buf[rb * kYxYP + col];
+            if (kk == 0) {
                 xa.y = 0.f;
                 xb.y = 0.f;
+            } else if (kk == N / 2) {
+                xa = make_float2(xa.y, 0.f);
+                xb = make_float2(xb.y, 0.f);
             }
             x[n1] = k <= N / 2 ? make_float2(xa.x - xb.y, xa.y + xb.x)
                                : make_float2(xa.x + xb.y, xb.x - xa.y);
@@ -791,56 +790,48 @@ yx_inv256_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *_
         __syncthreads();  // the rows are read: buf becomes the exchange buffers
         Pn::template run<+1, true>(x, ex, tw, c, t);
         // every group is past the exchange (run ends with a block barrier)
-        float4 mm = make_float4(x[0].x, x[0].x, x[0].y, x[0].y);  // min, max of rows ra, rb
-        bool bad = false;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int k = Pn::out_row(t, i);
             O[ra * kYxOP + k] = x[i].x * scale;
             O[rb * kYxOP + k] = x[i].y * scale;
-            mm = make_float4(fminf(mm.x, x[i].x), fmaxf(mm.y, x[i].x), fminf(mm.z, x[i].y),
-                             fmaxf(mm.w, x[i].y));
-            if constexpr (ST != kSpecF32) bad |= !__builtin_isfinite(x[i].x) || !__builtin_isfinite(x[i].y);
+        }
+        __syncthreads();
+        // 128 rows of 64 float4, 16 lanes per row (4 float4 each): the row's
+        // (min, max) as stored reduces over its 16 lanes
+        constexpr int Q4 = N / 4;
+        static_assert(kYxThreads / 16 * 2 == 128 && Q4 == 64, "two row passes of 64 rows");
+        float *dst = A + ((size_t)z * N + 128 * half) * N;
+        const int l16 = threadIdx.x & 15;
+        bool bad = false;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int r = (threadIdx.x >> 4) + 64 * v;
+            float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+            for (int u = 0; u < Q4 / 16; ++u) {
+                const int q = l16 + 16 * u;
+                const float4 e = *reinterpret_cast<const float4 *>(O + r * kYxOP + 4 * q);
+                *reinterpret_cast<float4 *>(dst + (unsigned)(r * N + 4 * q)) = e;
+                mn = fminf(mn, fminf(fminf(e.x, e.y), fminf(e.z, e.w)));
+                mx = fmaxf(mx, fmaxf(fmaxf(e.x, e.y), fmaxf(e.z, e.w)));
+                if constexpr (ST != kSpecF32)
+                    bad |= !__builtin_isfinite(e.x) || !__builtin_isfinite(e.y) || !__builtin_isfinite(e.z) ||
+                           !__builtin_isfinite(e.w);
+            }
+#pragma unroll
+            for (int d = 8; d > 0; d >>= 1) {
+                mn = fminf(mn, __shfl_xor(mn, d, 16));
+                mx = fmaxf(mx, __shfl_xor(mx, d, 16));
+            }
+            if (l16 == 0) rowmm[(size_t)z * N + 128 * half + r] = make_float2(mn, mx);
         }
         if constexpr (ST != kSpecF32)
             if (bad) atomicOr(&st->flags, kFlagRange);
-        // lanes c, c + 16, c + 32, c + 48 of a wave hold the same row pair
-#pragma unroll
-        for (int d = 16; d < 64; d <<= 1) {
-            mm.x = fminf(mm.x, __shfl_xor(mm.x, d, 64));
-            mm.y = fmaxf(mm.y, __shfl_xor(mm.y, d, 64));
-            mm.z = fminf(mm.z, __shfl_xor(mm.z, d, 64));
-            mm.w = fmaxf(mm.w, __shfl_xor(mm.w, d, 64));
-        }
-        if ((lt & 63) < 16) mmr[(grp * 4 + (lt >> 6)) * 16 + c] = mm;
-        __syncthreads();
-        constexpr int Q4 = N / 4;  // float4 per real row: one wave per row
-        static_assert(Q4 == 64, "a wave stores one row");
-        float *dst = A + ((size_t)z * N + 128 * half) * N;
-#pragma unroll
-        for (int u = 0; u < 128 * Q4 / kYxThreads; ++u) {
-            const int i = u * kYxThreads + threadIdx.x;
-            const int r = i / Q4, q = i - r * Q4;
-            *reinterpret_cast<float4 *>(dst + (unsigned)(r * N + 4 * q)) =
-                *reinterpret_cast<const float4 *>(O + r * kYxOP + 4 * q);
-        }
-        if (threadIdx.x < 128) {
-            // real row r = 2 (16 q + c) + b of this half: its range over the
-            // four waves of group q (A = x scale, scale > 0: the order holds)
-            const int r = threadIdx.x, q = r >> 5, cc = (r & 31) >> 1, b = r & 1;
-            float mn = INFINITY, mx = -INFINITY;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const float4 e = mmr[(q * 4 + w) * 16 + cc];
-                mn = fminf(mn, b ? e.z : e.x);
-                mx = fmaxf(mx, b ? e.w : e.y);
-            }
-            rowmm[(size_t)z * N + 128 * half + r] = make_float2(mn * scale, mx * scale);
-        }
     }
 }
 
-size_t yx_inv256_lds() { return (size_t)(kYxBuf + 2 * kYx) * sizeof(float2) + 256 * sizeof(float4); }
+size_t yx_inv256_lds() { return (size_t)(kYxBuf + 2 * kYx) * sizeof(float2); }
 
 // Both inverse passes for Nx = Ny = 128: two 512-thread blocks per z plane,
 // block (z, h) writing rows y = 64 h .. 64 h + 63 of A (two blocks per plane

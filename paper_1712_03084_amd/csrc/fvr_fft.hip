@@ -522,10 +522,24 @@ pen_y_fwd_kernel(void *__restrict__ spec, const uint8_t *__restrict__ occ,
     }
 }
 
+// Chunks of 16 columns leave the last column alone when H = 16 m + 1 (Nx a
+// multiple of 32): a block for it would transform 15 columns of zeros.  The
+// z pass then gives that column (kx = Nx/2) of kNyqLines ky lines to each of
+// its first `nyqb` blocks, line kNyqLines b + c in the place of column c,
+// and the other blocks the m full chunks of every line.  Each column gets
+// the same arithmetic either way.  (The column's loads are 8 bytes per
+// 128-byte line, so a few lines per block spread them over many CUs.  For
+// the y pass, whose lines would be whole z planes apart, the chunk layout
+// measured faster.)
+constexpr int kNyqLines = 4;
+static int nyquist_blocks(int H, int lines) {
+    return (H > kChunk && (H - 1) % kChunk == 0) ? (lines + kNyqLines - 1) / kNyqLines : 0;
+}
+
 template <int N1, int N2, int ST>
 __global__ void __launch_bounds__(16 * N2)
 pen_z_solve_kernel(void *__restrict__ spec, const uint8_t *__restrict__ zocc, Grid g,
-                   const float2 *__restrict__ twg) {
+                   const float2 *__restrict__ twg, int nyqb) {
     using Pn = Pencil<N1, N2>;
     constexpr int N = Pn::N;  // = Nz
     __shared__ float2 ex[Pn::EX];
@@ -544,12 +558,23 @@ pen_z_solve_kernel(void *__restrict__ spec, const uint8_t *__restrict__ zocc, Gr
     const unsigned plb = (unsigned)(plane * SB::kB);
     const SB s0(spec, plb), s2(plane_base<ST>(spec, plane, 2), plb);
     const unsigned zsb = (unsigned)Ny * Hp * SB::kB;
-    const int nch = nchunks(H);
-    const int chunk = blockIdx.x % nch, ky = blockIdx.x / nch;
-    const int k0 = chunk * kChunk;
     const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
-    const bool col = k0 + c < H;
-    const unsigned o0 = (unsigned)(((size_t)ky * Hp + k0 + c) * SB::kB);
+    int kx, ky;  // this thread's column
+    bool col;
+    if ((int)blockIdx.x < nyqb) {
+        // column Nx/2 of line ky = kNyqLines b + c
+        kx = H - 1;
+        ky = kNyqLines * (int)blockIdx.x + c;
+        col = c < kNyqLines && ky < Ny;
+        if (!col) ky = 0;
+    } else {
+        const int b = (int)blockIdx.x - nyqb;
+        const int nch = nyqb ? (H - 1) / kChunk : nchunks(H);
+        kx = (b % nch) * kChunk + c;
+        ky = b / nch;
+        col = kx < H;
+    }
+    const unsigned o0 = (unsigned)(((size_t)ky * Hp + kx) * SB::kB);
     float2 a[N1], b[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
@@ -561,7 +586,7 @@ pen_z_solve_kernel(void *__restrict__ spec, const uint8_t *__restrict__ zocc, Gr
     Pn::template run<-1>(a, ex, tw, c, t);
     Pn::template run<-1>(b, ex, tw, c, t);
     // (F_z P0 + j w_z F_z P2) / |w|^2, zero at the DC bin
-    const float wx = (float)kappa(k0 + c, g.n[0]) * g.wstep[0];
+    const float wx = (float)kappa(kx, g.n[0]) * g.wstep[0];
     const float wy = (float)kappa(ky, Ny) * g.wstep[1];
     const float wxy = wx * wx + wy * wy;
 #pragma unroll
@@ -802,11 +827,15 @@ yx_inv256_kernel(const void *__restrict__ spec, float *__restrict__ A, float2 *_
         constexpr int Q4 = N / 4;
         static_assert(kYxThreads / 16 * 2 == 128 && Q4 == 64, "two row passes of 64 rows");
         float *dst = A + ((size_t)z * N + 128 * half) * N;
-        const int l16 = threadIdx.x & 15;
+        // the lane from the exec mask and the wave index as a scalar: no
+        // thread index needs to stay live into this loop
+        const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int l16 = lane & 15;
         bool bad = false;
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-            const int r = (threadIdx.x >> 4) + 64 * v;
+            const int r = 4 * wave + (lane >> 4) + 64 * v;
             float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
             for (int u = 0; u < Q4 / 16; ++u) {
@@ -1067,7 +1096,9 @@ hipError_t launch_fft_z_solve(void *spec, const uint8_t *zocc, const Grid &g, co
                               hipStream_t s) {
     const int nch = (g.H + kChunk - 1) / kChunk;
     if (const int pc = pencil_code(g.n[2])) {
-        FVR_PEN_ST(pc, pen_z_solve_kernel, (spec, zocc, g, ax.tw), dim3(nch * g.n[1]))
+        const int nyqb = nyquist_blocks(g.H, g.n[1]);
+        const int blocks = nyqb ? nyqb + (g.H - 1) / kChunk * g.n[1] : nch * g.n[1];
+        FVR_PEN_ST(pc, pen_z_solve_kernel, (spec, zocc, g, ax.tw, nyqb), dim3(blocks))
         return hipGetLastError();
     }
     FVR_PF_ST(g.n[2], fft_z_solve_kernel, (spec, zocc, g, ax), dim3(nch * g.n[1]), dim3(kPassThreads),

@@ -103,6 +103,9 @@ def test_splat_parity(ctx, name, spec):
 INDICATOR_CASES = SPLAT_CASES + [
     ("paper_r6_shape", ((64, 128, 64), (-0.6, -1.2, -0.6, 0.6, 1.2, 0.6))),
     ("radix_96_160_192", ((96, 160, 192), (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0))),
+    # the z pass's column kx = Nx/2 in blocks of 4 ky lines, the last of
+    # 30 lines with two masked
+    ("nyquist_lines_z", ((64, 30, 32), (-0.4, -0.19, -0.2, 0.4, 0.19, 0.2))),
 ]
 
 

@@ -85,7 +85,8 @@ typedef struct {
     int64_t n_points;     /* 0 <= M <= FVR_MAX_POINTS, else FVR_E_INVALID */
     int32_t dims[3];      /* Nx, Ny, Nz: each even, 8..512, 2^a 3^b 5^c */
     float bbox[6];        /* xmin, ymin, zmin, xmax, ymax, zmax (max > min) */
-    uint32_t options;     /* FVR_SPLAT_* bits; 0: the weighted splat of eqs. (1)-(2) */
+    uint32_t options;     /* FVR_SPLAT_*, FVR_STORAGE_* bits; 0: the weighted splat of
+                             eqs. (1)-(2) with complex64 spectra */
 } fvr_frame;
 
 /* fvr_frame.options: the non-weighted splat of Sec. III-B ("simplest

@@ -62,8 +62,12 @@ typedef enum {
     FVR_E_NOMEM = -3,       /* device allocation failed */
     FVR_E_CAPACITY = -4,    /* output arrays too small; required counts written */
     FVR_E_DEVICE = -5,      /* a HIP runtime error */
-    FVR_E_RANGE = -6        /* a 16-bit spectrum value overflowed (FVR_STORAGE_FP16
+    FVR_E_RANGE = -6,       /* a 16-bit spectrum value overflowed (FVR_STORAGE_FP16
                                with normals far from unit length): use float32 storage */
+    /* not a status: widens the type to every int32 value, so that a value
+       from a newer or older library (fvr_status_string says "unknown
+       status") is a valid fvr_status in C++ too */
+    FVR_STATUS_MAX_ENUM = 0x7fffffff
 } fvr_status;
 
 /* Largest point count of one frame: (2^31 - 1) / 3, so that every

@@ -1730,6 +1730,7 @@ const char *fvr_status_string(fvr_status s) {
         case FVR_E_CAPACITY: return "output capacity too small";
         case FVR_E_DEVICE: return "device error";
         case FVR_E_RANGE: return "16-bit spectrum overflow";
+        default: break;
     }
     return "unknown status";
 }

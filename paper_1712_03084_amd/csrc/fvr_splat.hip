@@ -830,12 +830,20 @@ tile_order_kernel(const int32_t *__restrict__ bin_count, int32_t *__restrict__ b
     }
     __shared__ int hist[kTileClasses], cursor[kTileClasses];
     __shared__ unsigned wmax[kScanBlock / 64], wnmax[kScanBlock / 64];
-    // the frame's largest W and W |N_c| (fixed-point units of the splat).
     // Loads go out kBatch at a time with clamped indices (a duplicate does not
-    // change a maximum), so each batch costs one memory round trip.
+    // change a maximum or a count that the index check excludes), so each
+    // batch costs one memory round trip.  The first batch of busy tiles goes
+    // out with the block maxima, and when it holds them all (the usual case)
+    // the scatter below reuses it.
     constexpr int kBatch = 8;
+    constexpr int kOne = kBatch * kScanBlock;
+    const int n = st->n_busy;
+    int2 e0[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) e0[u] = pend[max(min(u * kScanBlock + (int)threadIdx.x, n - 1), 0)];
+    // the frame's largest W and W |N_c| (fixed-point units of the splat)
     unsigned mw = 0, mn = 0;
-    for (int b0 = 0; b0 < nblk; b0 += kBatch * kScanBlock) {
+    for (int b0 = 0; b0 < nblk; b0 += kOne) {
         uint2 v[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) v[u] = blk_max[min(b0 + u * kScanBlock + (int)threadIdx.x, nblk - 1)];
@@ -854,10 +862,12 @@ tile_order_kernel(const int32_t *__restrict__ bin_count, int32_t *__restrict__ b
         wmax[threadIdx.x >> 6] = mw;
         wnmax[threadIdx.x >> 6] = mn;
     }
-    const int n = st->n_busy;
     if (threadIdx.x < kTileClasses) hist[threadIdx.x] = 0;
     __syncthreads();
-    for (int b0 = 0; b0 < n; b0 += kBatch * kScanBlock) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+        if (u * kScanBlock + (int)threadIdx.x < n) atomicAdd(&hist[tile_class(e0[u].y)], 1);
+    for (int b0 = kOne; b0 < n; b0 += kOne) {
         int2 e[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) e[u] = pend[min(b0 + u * kScanBlock + (int)threadIdx.x, n - 1)];
@@ -874,7 +884,10 @@ tile_order_kernel(const int32_t *__restrict__ bin_count, int32_t *__restrict__ b
         cursor[c] = above;
     }
     __syncthreads();
-    for (int b0 = 0; b0 < n; b0 += kBatch * kScanBlock) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+        if (u * kScanBlock + (int)threadIdx.x < n) list[atomicAdd(&cursor[tile_class(e0[u].y)], 1)] = e0[u].x;
+    for (int b0 = kOne; b0 < n; b0 += kOne) {
         int2 e[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) e[u] = pend[min(b0 + u * kScanBlock + (int)threadIdx.x, n - 1)];

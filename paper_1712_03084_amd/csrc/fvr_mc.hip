@@ -616,10 +616,14 @@ mc_count_kernel(const float *__restrict__ A, const float *__restrict__ level_f32
     const float L = *level_f32;
     const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
     const int nblk = list ? st->mc_active : (int)gridDim.x;
+    // this block's first list entry, loaded together with the list length
+    // (the list has room for every block, so the entry exists; it is used
+    // only when it is below the length)
+    const unsigned first = list ? (unsigned)list[blockIdx.x] : (unsigned)blockIdx.x;
     if ((int)blockIdx.x >= nblk) return;
     mc_count_table(s_ntri);
     for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
-    const unsigned blk = list ? (unsigned)list[it] : (unsigned)it;
+    const unsigned blk = it == (int)blockIdx.x ? first : (list ? (unsigned)list[it] : (unsigned)it);
     uint32_t code4 = 0;  // the 4 point codes, byte i for point l0 + i
     const unsigned l0u = blk * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
     const size_t l0 = l0u;
@@ -771,26 +775,31 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
         const uint32_t *src = reinterpret_cast<const uint32_t *>(st);
         for (int i = threadIdx.x; i < (int)(sizeof(DevStatus) / 4); i += blockDim.x) host_status[i] = src[i];
     }
+    // this block's first list entry, loaded together with the status (the
+    // list has room for every block; the entry is used only below the length)
+    const unsigned first = list ? (unsigned)list[blockIdx.x] : (unsigned)blockIdx.x;
     if (!mesh_fits(st, caps)) return;
     // the blocks in `list` (persistent blocks stride over it), or block
     // blockIdx.x when list is null
     const int nblk = list ? st->mc_active : (int)gridDim.x;
+    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
     bool have_table = false;
     for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
-    const unsigned blk = list ? (unsigned)list[it] : (unsigned)it;
-    // a block without vertices and active cells has nothing to write (and
-    // mc_count stored no codes for it)
-    if (blk_counts[3 * blk] == 0 && blk_counts[3 * blk + 2] == 0) continue;
-    // the block's global offsets, loaded before anything waits on the codes
+    const unsigned blk = it == (int)blockIdx.x ? first : (list ? (unsigned)list[it] : (unsigned)it);
+    // the block's totals, offsets and codes in one round of loads.  A block
+    // without vertices and active cells has nothing to write (and mc_count
+    // stored no codes for it: the codes loaded then are stale and unused).
+    const int bv = blk_counts[3 * blk], ba = blk_counts[3 * blk + 2];
     int vbase = blk_off[3 * blk + 0], tbase = blk_off[3 * blk + 1], abase = blk_off[3 * blk + 2];
+    const unsigned l0u = blk * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
+    const size_t l0 = l0u;
+    const uint32_t code_ld = l0 < n ? codes[l0u / 4] : 0u;
+    if (bv == 0 && ba == 0) continue;
     if (!have_table) {
         mc_count_table(s_ntri);
         have_table = true;
     }
     const float L = *level_f32;
-    const size_t n = (size_t)g.n[0] * g.n[1] * g.n[2];
-    const unsigned l0u = blk * (unsigned)kMcPerBlock + threadIdx.x * (unsigned)kMcPpt;
-    const size_t l0 = l0u;
     int eb[kMcPpt], cs[kMcPpt];
     int cnt[3] = {0, 0, 0};
     int qx = 0, qy = 0, qz = 0;
@@ -800,7 +809,7 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
         qx = (int)(l0u - ru * (unsigned)g.n[0]);
         qz = (int)(ru / (unsigned)g.n[1]);
         qy = (int)(ru - (unsigned)qz * (unsigned)g.n[1]);
-        code4 = codes[l0u / 4];
+        code4 = code_ld;
     }
     {
         int x = qx, y = qy, z = qz;

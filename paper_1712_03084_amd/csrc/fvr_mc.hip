@@ -966,8 +966,10 @@ hipError_t launch_mc_generate(const float *A, const float *level_f32, const int3
 
 hipError_t launch_mc_triangles(const int4 *cells, const int32_t *vidx, const Grid &g, int32_t *tris,
                                const DevStatus *st, MeshCaps caps, hipStream_t s) {
+    // a grid-stride loop over the active cells: blocks beyond the count only
+    // read the status and exit, so the grid stays moderate
     const long long want = (caps.cells + 255) / 256;
-    const int blocks = (int)std::max(1LL, std::min(want, 4096LL));
+    const int blocks = (int)std::max(1LL, std::min(want, 1024LL));
     mc_triangles_kernel<<<dim3(blocks), dim3(256), 0, s>>>(cells, vidx, g, tris, st, caps);
     return hipGetLastError();
 }

@@ -381,9 +381,14 @@ splat_fft_x_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ b
     const int eD = unit_exp(__uint_as_float(st->wmax_bits));
     const float k1 = exp2f(2.0f * sc.e1[0]), k2 = exp2f(2.0f * sc.e2[0]);
 
-    // Persistent blocks (one per CU) claim the busy tiles from a ticket counter.
+    // Persistent blocks claim the busy tiles from a ticket counter; block b
+    // starts with tile b of the list without a counter round trip, and the
+    // counter hands out the tickets from gridDim.x on.
+    bool first_tile = true;
     for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&st->tile_ticket, 1);
+    if (threadIdx.x == 0)
+        s_tile = first_tile ? (int)blockIdx.x : (int)gridDim.x + (int)atomicAdd(&st->tile_ticket, 1);
+    first_tile = false;
     __syncthreads();
     const int ticket = s_tile;
     if (ticket >= nbusy) break;

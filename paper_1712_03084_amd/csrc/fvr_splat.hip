@@ -768,7 +768,9 @@ constexpr int kTileLanes = 8;  // lanes per tile in tile_list
 // iy - 1 .. iy + 2, iz - 1 .. iz + 2).  Busy tiles get occ = 1 and an entry
 // (tile, cost) in `pend`, in no particular order.  Block b < nscan also sums
 // scan tile b of the bin counts into partial[b] (first half of the bin scan).
-__global__ void __launch_bounds__(256)
+constexpr int kTileListThreads = 256;
+
+__global__ void __launch_bounds__(kTileListThreads)
 tile_list_kernel(const int32_t *__restrict__ bin_count, int nbins, int nscan,
                  int32_t *__restrict__ partial, Grid g, SplatConsts sc, int ntiles,
                  uint8_t *__restrict__ occ, int2 *__restrict__ pend, DevStatus *st) {
@@ -801,14 +803,24 @@ tile_list_kernel(const int32_t *__restrict__ bin_count, int nbins, int nscan,
     for (int d = kTileLanes / 2; d > 0; d >>= 1) cost += __shfl_xor(cost, d, kTileLanes);
     if (tile < ntiles && r == 0) occ[tile] = cost > 0 ? 1 : 0;
     const bool busy = tile < ntiles && r == 0 && cost > 0;
-    // one list append per wave
+    // one list append per block (every block appends to the one counter:
+    // fewer atomics queue on it than with one per wave)
+    __shared__ int wcnt[kTileListThreads / 64], bbase;
     const unsigned long long b = __ballot(busy);
-    const int lane = threadIdx.x & 63;
-    int base = 0;
-    if (lane == 0 && b) base = atomicAdd(&st->n_busy, __popcll(b));
-    base = __shfl(base, 0, 64);
-    if (busy)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) wcnt[wid] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < kTileListThreads / 64; ++w) tot += wcnt[w];
+        bbase = tot ? atomicAdd(&st->n_busy, tot) : 0;
+    }
+    __syncthreads();
+    if (busy) {
+        int base = bbase;
+        for (int w = 0; w < wid; ++w) base += wcnt[w];
         pend[base + __popcll(b & ((1ull << lane) - 1ull))] = make_int2(tile, (int)min(cost, 0x7fffffffLL));
+    }
 }
 
 // Busy tiles in decreasing cost (64 logarithmic cost classes, a counting
@@ -916,8 +928,8 @@ hipError_t launch_tile_list(const int32_t *bin_count, int32_t *bin_off, int nbin
                             int32_t *list, const uint2 *blk_max, int m, DevStatus *st, hipStream_t s) {
     const int ntiles = sc.tiles_y * ((g.n[2] + sc.tz - 1) / sc.tz);
     const int nscan = scan_tiles(nbins);
-    const int blocks = std::max((ntiles * kTileLanes + 255) / 256, nscan);
-    tile_list_kernel<<<dim3(blocks), dim3(256), 0, s>>>(bin_count, nbins, nscan, partial, g, sc, ntiles,
+    const int blocks = std::max((ntiles * kTileLanes + kTileListThreads - 1) / kTileListThreads, nscan);
+    tile_list_kernel<<<dim3(blocks), dim3(kTileListThreads), 0, s>>>(bin_count, nbins, nscan, partial, g, sc, ntiles,
                                                        occ, pend, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

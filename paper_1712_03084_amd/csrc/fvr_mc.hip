@@ -598,11 +598,25 @@ mc_classify_kernel(float *__restrict__ level_f32, const double *__restrict__ psu
         }
     }
     if (__ballot(inside) && lane == 0) atomicOr(&st->flags, kFlagOpen);
+    // one list append per block: every block appends to the one counter at
+    // about the same time, and fewer returning atomics queue on it than with
+    // one per wave
+    __shared__ int wcnt[kLevelThreads / 64], bbase;
     const unsigned long long m = __ballot(active);
-    int base = 0;
-    if (lane == 0 && m) base = atomicAdd(&st->mc_active, __popcll(m));
-    base = __shfl(base, 0, 64);
-    if (active) list[base + __popcll(m & ((1ull << lane) - 1ull))] = b;
+    const int wid = threadIdx.x >> 6;
+    if (lane == 0) wcnt[wid] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < kLevelThreads / 64; ++w) tot += wcnt[w];
+        bbase = tot ? atomicAdd(&st->mc_active, tot) : 0;
+    }
+    __syncthreads();
+    if (active) {
+        int base = bbase;
+        for (int w = 0; w < wid; ++w) base += wcnt[w];
+        list[base + __popcll(m & ((1ull << lane) - 1ull))] = b;
+    }
 }
 
 // Classification of the blocks in `list` (st->mc_active of them; persistent

@@ -133,6 +133,7 @@ scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int 
 // scan over all nb blocks in the same block.
 constexpr int kListThreads = 1024;
 constexpr int kListCap = 4096;
+static_assert(kListCap % kListThreads == 0, "whole entries per thread");
 
 __global__ void __launch_bounds__(kListThreads)
 mc_list_scan_kernel(const int32_t *__restrict__ list, const int32_t *__restrict__ cnt, int nb,
@@ -146,12 +147,24 @@ mc_list_scan_kernel(const int32_t *__restrict__ list, const int32_t *__restrict_
     const int n = st->mc_active;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (n <= kListCap) {
+        // this thread's entries i = threadIdx.x + kListThreads u and their
+        // totals, loaded once: the totals' loads are in flight while the
+        // bitmap is built and ranked
+        constexpr int kPer = kListCap / kListThreads;
+        int4 e[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = (int)threadIdx.x + kListThreads * u;
+            e[u].x = i < n ? list[i] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (e[u].x >= 0) e[u] = make_int4(e[u].x, cnt[3 * e[u].x], cnt[3 * e[u].x + 1], cnt[3 * e[u].x + 2]);
         for (int w = threadIdx.x; w < nw; w += kListThreads) bits[w] = 0u;
         __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kListThreads) {
-            const int b = list[i];
-            atomicOr(&bits[b >> 5], 1u << (b & 31));
-        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (e[u].x >= 0) atomicOr(&bits[e[u].x >> 5], 1u << (e[u].x & 31));
         __syncthreads();
         // exclusive scan of the words' popcounts: thread t owns words [t S, (t+1) S)
         const int S = (nw + kListThreads - 1) / kListThreads;
@@ -168,11 +181,12 @@ mc_list_scan_kernel(const int32_t *__restrict__ list, const int32_t *__restrict_
             run += __popc(bits[w]);
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kListThreads) {
-            const int b = list[i];
-            const int r = wbase[b >> 5] + __popc(bits[b >> 5] & ((1u << (b & 31)) - 1u));
-            srt[r] = make_int4(b, cnt[3 * b], cnt[3 * b + 1], cnt[3 * b + 2]);
-        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (e[u].x >= 0) {
+                const int b = e[u].x;
+                srt[wbase[b >> 5] + __popc(bits[b >> 5] & ((1u << (b & 31)) - 1u))] = e[u];
+            }
         __syncthreads();
         // exclusive scan of the listed totals in block order
         const int T = (n + kListThreads - 1) / kListThreads;

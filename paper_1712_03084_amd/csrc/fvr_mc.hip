@@ -796,6 +796,7 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
                    uint32_t *__restrict__ host_status) {
     __shared__ int red[12];
     __shared__ uint8_t s_ntri[256];
+    __shared__ uint2 elist[3 * kMcPerBlock];  // the block's crossing edges, by vertex rank
     // The status block is final here (the mesh kernels only read it): block 0
     // copies it to the host (as status_publish_kernel does), and the stores'
     // latency hides behind the mesh work instead of costing a launch.
@@ -874,41 +875,22 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
             cnt[2] += c > 0;
         }
     }
+    const int vblk = vbase;  // the block's first vertex
     block_excl_scan3(cnt, red);
-    vbase += cnt[0];
     tbase += cnt[1];
     abase += cnt[2];
+    // this thread's crossing edges into the block's edge list, at their
+    // vertex ranks within the block (order: linear index, axis)
+    int k = cnt[0];
     int x = qx, y = qy, z = qz;
     for (int i = 0; i < kMcPpt; ++i) {
         const size_t l = l0 + i;
         if (l >= n) break;
-        if (eb[i]) {
-            const float px = fmaf((float)x + 0.5f, g.h[0], g.bmin[0]);
-            const float py = fmaf((float)y + 0.5f, g.h[1], g.bmin[1]);
-            const float pz = fmaf((float)z + 0.5f, g.h[2], g.bmin[2]);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (!((eb[i] >> a) & 1)) continue;
-                const size_t step = a == 0 ? 1 : a == 1 ? (size_t)g.n[0] : (size_t)g.n[0] * g.n[1];
-                const float a0 = A[l], a1 = A[l + step];
-                const float t = (L - a0) / (a1 - a0);
-                float p[3] = {px, py, pz};
-                p[a] += t * g.h[a];
-                verts[3 * (size_t)vbase + 0] = p[0];
-                verts[3 * (size_t)vbase + 1] = p[1];
-                verts[3 * (size_t)vbase + 2] = p[2];
-                if (nrms) {
-                    const int q0[3] = {x, y, z};
-                    float nv[3];
-                    edge_normal(A, g, l, q0, a, step, a0, a1, t, nv);
-                    nrms[3 * (size_t)vbase + 0] = nv[0];
-                    nrms[3 * (size_t)vbase + 1] = nv[1];
-                    nrms[3 * (size_t)vbase + 2] = nv[2];
-                }
-                vidx[3 * l + a] = vbase;
-                ++vbase;
-            }
-        }
+        for (int a = 0; a < 3; ++a)
+            if ((eb[i] >> a) & 1)
+                elist[k++] = make_uint2((unsigned)l, (unsigned)x | ((unsigned)y << 10) | ((unsigned)z << 20) |
+                                                         ((unsigned)a << 30));
         if (cs[i] >= 0) {
             const int c = (int)s_ntri[cs[i]];
             if (c > 0) {
@@ -924,6 +906,34 @@ mc_generate_kernel(const float *__restrict__ A, const float *__restrict__ level_
                 ++z;
             }
         }
+    }
+    __syncthreads();
+    // one vertex per thread (a listed block has a few dozen): the position
+    // on its edge, its normal, and its id at the edge's slot
+    for (int e = threadIdx.x; e < bv; e += blockDim.x) {
+        const uint2 en = elist[e];
+        const size_t l = en.x;
+        const int ex = (int)(en.y & 1023u), ey = (int)((en.y >> 10) & 1023u), ez = (int)((en.y >> 20) & 1023u);
+        const int a = (int)(en.y >> 30);
+        const int vid = vblk + e;
+        const size_t step = a == 0 ? 1 : a == 1 ? (size_t)g.n[0] : (size_t)g.n[0] * g.n[1];
+        const float a0 = A[l], a1 = A[l + step];
+        const float t = (L - a0) / (a1 - a0);
+        float p[3] = {fmaf((float)ex + 0.5f, g.h[0], g.bmin[0]), fmaf((float)ey + 0.5f, g.h[1], g.bmin[1]),
+                      fmaf((float)ez + 0.5f, g.h[2], g.bmin[2])};
+        p[a] += t * g.h[a];
+        verts[3 * (size_t)vid + 0] = p[0];
+        verts[3 * (size_t)vid + 1] = p[1];
+        verts[3 * (size_t)vid + 2] = p[2];
+        if (nrms) {
+            const int q0[3] = {ex, ey, ez};
+            float nv[3];
+            edge_normal(A, g, l, q0, a, step, a0, a1, t, nv);
+            nrms[3 * (size_t)vid + 0] = nv[0];
+            nrms[3 * (size_t)vid + 1] = nv[1];
+            nrms[3 * (size_t)vid + 2] = nv[2];
+        }
+        vidx[3 * l + a] = vid;
     }
 }
 }
